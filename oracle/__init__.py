@@ -1,0 +1,301 @@
+"""FP64 CPU oracle for the Fisher Information Field hot path (ctypes binding).
+
+TEST INFRASTRUCTURE ONLY: the test suite, the smoke check and the CPU-baseline
+leg of the benchmark may import this package; the product package never does.
+The C source (``fif_oracle.c``) follows Zhang & Scaramuzza, arXiv 2008.03324,
+step by step in FP64; see the comment of each C function for the passage.
+
+Parity status: every function here is pinned by ``tests/test_oracle_pins.py``
+(finite-difference Jacobians of the bearing model, closed forms, LAPACK
+eigen-solvers, brute force on tiny inputs); none is "parity unpinned".
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "fif_oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+
+TRACE, LMIN, LOGDET, FIM = 1, 2, 4, 8
+
+
+def compile_oracle() -> str:
+    """Compile the oracle with gcc (FP64, no fast-math, no FMA contraction)."""
+    cmd = ["gcc", "-O2", "-fopenmp", "-fPIC", "-shared", "-ffp-contract=off",
+           "-fno-fast-math", "-o", _LIB + ".tmp", _SRC, "-lm"]
+    subprocess.run(cmd, check=True)
+    os.replace(_LIB + ".tmp", _LIB)
+    return _LIB
+
+
+class _Grid(ctypes.Structure):
+    _fields_ = [("origin", ctypes.c_double * 3), ("h", ctypes.c_double),
+                ("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32)]
+
+
+class _Pinhole(ctypes.Structure):
+    _fields_ = [("fx", ctypes.c_double), ("fy", ctypes.c_double),
+                ("cx", ctypes.c_double), ("cy", ctypes.c_double),
+                ("width", ctypes.c_int32), ("height", ctypes.c_int32)]
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+            compile_oracle()
+        _lib = ctypes.CDLL(_LIB)
+    return _lib
+
+
+def _p(a):
+    return a.ctypes.data_as(ctypes.c_void_p) if a is not None else None
+
+
+def _grid(origin, h, shape):
+    g = _Grid()
+    for c in range(3):
+        g.origin[c] = float(origin[c])
+    g.h = float(h)
+    g.nx, g.ny, g.nz = (int(s) for s in shape)
+    return g
+
+
+def _f64(a, shape_last=None):
+    a = np.ascontiguousarray(a, dtype=np.float64)
+    if shape_last is not None:
+        a = a.reshape(-1, shape_last)
+    return a
+
+
+def ncols(metrics: int) -> int:
+    return bool(metrics & 1) + bool(metrics & 2) + bool(metrics & 4) + (21 if metrics & 8 else 0)
+
+
+# ------------------------------------------------------------ visibility
+
+def quad_coeffs(alpha: float, v_alpha: float) -> np.ndarray:
+    """(k2, k1, k0) from eq:quadratic_conditions."""
+    k = np.zeros(3)
+    lib().oracle_quad_coeffs(ctypes.c_double(alpha), ctypes.c_double(v_alpha), _p(k))
+    return k
+
+
+def vr(k, z) -> np.ndarray:
+    out = np.zeros(10)
+    lib().oracle_vr(_p(_f64(k)), _p(_f64(z)), _p(out))
+    return out
+
+
+def vp(u) -> np.ndarray:
+    out = np.zeros(10)
+    lib().oracle_vp(_p(_f64(u)), _p(out))
+    return out
+
+
+def in_range(p, t, r_min, r_max) -> bool:
+    f = lib().oracle_in_range
+    f.restype = ctypes.c_int
+    return bool(f(_p(_f64(p)), _p(_f64(t)), ctypes.c_double(r_min), ctypes.c_double(r_max)))
+
+
+def quat_to_R(q) -> np.ndarray:
+    R = np.zeros(9)
+    lib().oracle_quat_to_R(_p(_f64(q)), _p(R))
+    return R.reshape(3, 3)
+
+
+# ------------------------------------------------------------ FIM pieces
+
+def landmark_fim(p, t, R_wc, sigma) -> np.ndarray:
+    out = np.zeros(36)
+    lib().oracle_landmark_fim(_p(_f64(p)), _p(_f64(t)), _p(_f64(R_wc)),
+                              ctypes.c_double(sigma), _p(out))
+    return out.reshape(6, 6)
+
+
+def info_factor(landmarks, t, sigma, r_min=0.0, r_max=np.inf) -> np.ndarray:
+    """C_I at position t: (10, 6, 6)."""
+    lm = _f64(landmarks, 3)
+    out = np.zeros(360)
+    lib().oracle_info_factor(_p(lm), ctypes.c_int64(lm.shape[0]), _p(_f64(t)),
+                             ctypes.c_double(sigma), ctypes.c_double(r_min),
+                             ctypes.c_double(r_max), _p(out))
+    return out.reshape(10, 6, 6)
+
+
+def trace_factor(landmarks, t, sigma, r_min=0.0, r_max=np.inf) -> np.ndarray:
+    lm = _f64(landmarks, 3)
+    out = np.zeros(10)
+    lib().oracle_trace_factor(_p(lm), ctypes.c_int64(lm.shape[0]), _p(_f64(t)),
+                              ctypes.c_double(sigma), ctypes.c_double(r_min),
+                              ctypes.c_double(r_max), _p(out))
+    return out
+
+
+def build(landmarks, origin, h, shape, sigma, r_min=0.0, r_max=np.inf,
+          voxel_ids=None) -> np.ndarray:
+    """Factors of the listed voxels (all when voxel_ids is None): (n, 10, 6, 6)."""
+    lm = _f64(landmarks, 3)
+    g = _grid(origin, h, shape)
+    if voxel_ids is None:
+        n = int(np.prod(shape))
+        ids = None
+    else:
+        ids = np.ascontiguousarray(voxel_ids, dtype=np.int64)
+        n = ids.shape[0]
+    out = np.zeros((n, 360))
+    lib().oracle_build(_p(lm), ctypes.c_int64(lm.shape[0]), ctypes.byref(g),
+                       ctypes.c_double(sigma), ctypes.c_double(r_min), ctypes.c_double(r_max),
+                       _p(ids), ctypes.c_int64(n), _p(out))
+    return out.reshape(n, 10, 6, 6)
+
+
+def voxel_centre(origin, h, shape, v) -> np.ndarray:
+    t = np.zeros(3)
+    lib().oracle_voxel_centre(ctypes.byref(_grid(origin, h, shape)), ctypes.c_int64(v), _p(t))
+    return t
+
+
+# ------------------------------------------------------------ metrics
+
+def jacobi6(F):
+    w = np.zeros(6)
+    V = np.zeros(36)
+    lib().oracle_jacobi6(_p(_f64(F).reshape(-1)), _p(w), _p(V))
+    return w, V.reshape(6, 6)
+
+
+def logdet6(F, want_inv=False):
+    f = lib().oracle_logdet6
+    f.restype = ctypes.c_double
+    inv = np.zeros(36) if want_inv else None
+    ld = f(_p(_f64(F).reshape(-1)), _p(inv))
+    return (ld, inv.reshape(6, 6)) if want_inv else ld
+
+
+def metrics(F, which: int) -> np.ndarray:
+    out = np.zeros(ncols(which))
+    lib().oracle_metrics(_p(_f64(F).reshape(-1)), ctypes.c_uint32(which), _p(out))
+    return out
+
+
+# ------------------------------------------------------------ queries
+
+class Field:
+    """A factor field held by the oracle: all voxels, or a sparse subset."""
+
+    def __init__(self, C, origin, h, shape, voxel_ids=None):
+        self.C = np.ascontiguousarray(C, dtype=np.float64).reshape(-1, 360)
+        self.origin, self.h, self.shape = tuple(origin), float(h), tuple(int(s) for s in shape)
+        if voxel_ids is not None:
+            order = np.argsort(voxel_ids, kind="stable")
+            self.ids = np.ascontiguousarray(np.asarray(voxel_ids, np.int64)[order])
+            self.C = np.ascontiguousarray(self.C[order])
+        else:
+            self.ids = None
+        self.grid = _grid(self.origin, self.h, self.shape)
+
+    def _args(self):
+        n = self.ids.shape[0] if self.ids is not None else self.C.shape[0]
+        return _p(self.C), _p(self.ids), ctypes.c_int64(n), ctypes.byref(self.grid)
+
+
+def query(field: Field, alpha, v_alpha, t, q, metrics_mask, interp=0):
+    t = _f64(t, 3)
+    q = _f64(q, 4)
+    m = t.shape[0]
+    out = np.zeros((m, ncols(metrics_mask)))
+    flags = np.zeros(m, np.uint8)
+    rc = lib().oracle_query(*field._args(), ctypes.c_double(alpha), ctypes.c_double(v_alpha),
+                            _p(t), _p(q), ctypes.c_int64(m), ctypes.c_uint32(metrics_mask),
+                            ctypes.c_int(interp), _p(out), _p(flags))
+    if rc != 0:
+        raise KeyError("oracle field is missing a voxel the query needs")
+    return out, flags
+
+
+def query_fim(field: Field, alpha, v_alpha, t, q, interp=0):
+    t = _f64(t, 3)
+    q = _f64(q, 4)
+    m = t.shape[0]
+    F = np.zeros((m, 36))
+    rc = lib().oracle_query_fim(*field._args(), ctypes.c_double(alpha), ctypes.c_double(v_alpha),
+                                _p(t), _p(q), ctypes.c_int64(m), ctypes.c_int(interp), _p(F))
+    if rc != 0:
+        raise KeyError("oracle field is missing a voxel the query needs")
+    return F.reshape(m, 6, 6)
+
+
+def query_grad(field: Field, alpha, v_alpha, t, q, metrics_mask, dL_dout):
+    t = _f64(t, 3)
+    q = _f64(q, 4)
+    m = t.shape[0]
+    nc = bool(metrics_mask & 1) + bool(metrics_mask & 2) + bool(metrics_mask & 4)
+    up = _f64(dL_dout).reshape(m, nc)
+    gt = np.zeros((m, 3))
+    gphi = np.zeros((m, 3))
+    rc = lib().oracle_query_grad(*field._args(), ctypes.c_double(alpha),
+                                 ctypes.c_double(v_alpha), _p(t), _p(q), ctypes.c_int64(m),
+                                 ctypes.c_uint32(metrics_mask), _p(up), _p(gt), _p(gphi))
+    if rc != 0:
+        raise KeyError("oracle field is missing a voxel the query needs")
+    return gt, gphi
+
+
+def corner_voxels(origin, h, shape, t) -> np.ndarray:
+    """Voxel ids the trilinear query of each position reads (for sparse builds)."""
+    t = _f64(t, 3)
+    n = np.array(shape)
+    g = (t - np.asarray(origin)) / h
+    i0 = np.clip(np.floor(g), 0, np.maximum(n - 2, 0)).astype(np.int64)
+    ids = []
+    for j in range(8):
+        b = np.array([j & 1, (j >> 1) & 1, (j >> 2) & 1])
+        idx = np.minimum(i0 + b * (n > 1), n - 1)
+        ids.append(idx[:, 0] + n[0] * (idx[:, 1] + n[1] * idx[:, 2]))
+    ni = np.clip(np.floor(g + 0.5), 0, n - 1).astype(np.int64)
+    ids.append(ni[:, 0] + n[0] * (ni[:, 1] + n[1] * ni[:, 2]))
+    return np.unique(np.concatenate(ids))
+
+
+# ------------------------------------------------------------ point cloud
+
+def pc_query(landmarks, alpha, v_alpha, sigma, r_min, r_max, t, q, metrics_mask,
+             pinhole=None, want_fim=False, want_margin=False):
+    lm = _f64(landmarks, 3)
+    t = _f64(t, 3)
+    q = _f64(q, 4)
+    m = t.shape[0]
+    out = np.zeros((m, ncols(metrics_mask)))
+    F = np.zeros((m, 36)) if want_fim else None
+    margin = np.zeros(m) if want_margin else None
+    cam = None
+    if pinhole is not None:
+        cam = _Pinhole(*[float(x) for x in pinhole[:4]], int(pinhole[4]), int(pinhole[5]))
+    lib().oracle_pc_query(_p(lm), ctypes.c_int64(lm.shape[0]), ctypes.c_double(alpha),
+                          ctypes.c_double(v_alpha), ctypes.c_double(sigma),
+                          ctypes.c_double(r_min), ctypes.c_double(r_max),
+                          ctypes.byref(cam) if cam is not None else None, _p(t), _p(q),
+                          ctypes.c_int64(m), ctypes.c_uint32(metrics_mask), _p(out), _p(F),
+                          _p(margin))
+    res = [out]
+    if want_fim:
+        res.append(F.reshape(m, 6, 6))
+    if want_margin:
+        res.append(margin)
+    return res[0] if len(res) == 1 else tuple(res)
+
+
+def num_threads() -> int:
+    f = lib().oracle_num_threads
+    f.restype = ctypes.c_int
+    return int(f())
