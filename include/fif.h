@@ -1,0 +1,178 @@
+/*
+ * fif.h -- C ABI of the MI355X Fisher Information Field library (libfif.so).
+ *
+ * Method: Zhang & Scaramuzza, "Fisher Information Field: an Efficient and
+ * Differentiable Map for Perception-aware Planning", arXiv 2008.03324.
+ *
+ * Memory and ownership
+ *   Every array argument is a DEVICE pointer (HBM of the current HIP device)
+ *   unless its comment says "host".  Struct arguments (fif_grid, fif_vis,
+ *   fif_pinhole, fif_field) are host structs passed by pointer.  The caller
+ *   owns every buffer; the library never allocates or frees device memory.
+ *
+ * Streams and errors
+ *   Work is enqueued on `stream` (a hipStream_t; NULL = the null stream) and is
+ *   asynchronous.  Argument errors are detected on the host before anything is
+ *   enqueued and return FIF_EINVAL; a failed launch returns FIF_EDEVICE and
+ *   fif_last_error() (thread-local) holds the HIP message.  Nothing throws
+ *   across the ABI.  NaN inputs give NaN outputs, not errors.
+ *
+ * Conventions
+ *   Pose T_wc = {R_wc, t}: t is the camera position in the world, R_wc = R(q)
+ *   with q = (w, x, y, z) Hamilton (need not be unit: the library normalises).
+ *   The camera optical axis is e3, so z = R_wc e3 (Sec. V-B).  Perturbations
+ *   are global (left) se(3) about the world origin (Sec. V-A, eq:deriv_se3
+ *   first form, eq:jac_pose_global); so(3) gradients are w.r.t. phi in
+ *   R <- exp([phi]x) R.
+ *   Grid: voxel (i, j, k) has its centre at origin + (i, j, k) h; linear index
+ *   i + nx (j + ny k) (x fastest).
+ *   Landmark membership V_t (Sec. V, first step): a landmark p counts for a
+ *   position t iff max(r_min^2, 1e-12) <= n^2 <= r_max^2, n^2 evaluated in FP32
+ *   as fma(dz, dz, fma(dy, dy, dx*dx)) with d = fl32(p) - fl32(t), bounds
+ *   rounded to FP32 (r_max = INFINITY keeps every landmark, as in Sec. VII-A).
+ *   Visibility: the quadratic model of eq:quad_vis_approx with coefficients
+ *   fixed by eq:quadratic_conditions from (half_fov, v_alpha).
+ *   Noise: sigma_bearing is the bearing noise in radians (1 px at f = 300 px
+ *   is 1/300); I_i = J^T J / sigma^2 (eq:fim_gaussian).
+ */
+#ifndef FIF_H
+#define FIF_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t fif_status;
+#define FIF_OK 0
+#define FIF_EINVAL (-1)       /* bad argument (checked on the host, nothing enqueued) */
+#define FIF_ENOMEM (-2)       /* workspace too small */
+#define FIF_EDEVICE (-3)      /* HIP runtime or launch error, see fif_last_error() */
+#define FIF_EUNSUPPORTED (-4) /* valid but not implemented combination */
+
+/* Precision of a field or of a point-cloud sum. */
+#define FIF_FP32_NAIVE 0 /* FP32 arithmetic, FP32 accumulation */
+#define FIF_FP32_COMP 1  /* FP32 arithmetic, compensated (two-level TwoSum) accumulation */
+#define FIF_FP64 2       /* FP64 throughout */
+
+/* Field kinds. */
+#define FIF_KIND_INFO 0  /* positional information factor C_I (eq:general_info_pif) */
+#define FIF_KIND_TRACE 1 /* positional trace factor C_Tr (eq:general_trace_pif) */
+
+/* Metric mask; output columns follow this bit order.  FIF_FIM21 appends the 21
+ * upper-triangle entries (row-major) of the 6x6 FIM. */
+#define FIF_TRACE 1u
+#define FIF_LMIN 2u
+#define FIF_LOGDET 4u
+#define FIF_FIM21 8u
+
+/* Interpolation of the factors (Sec. VI-A: nearest neighbour or interpolation). */
+#define FIF_TRILINEAR 0 /* over the 8 surrounding voxel centres */
+#define FIF_NEAREST 1   /* round-half-up voxel */
+
+/* Per-query flags (not errors). */
+#define FIF_FLAG_CLAMPED 1u  /* position outside the hull of voxel centres, clamped */
+#define FIF_FLAG_NOT_PD 2u   /* FIM not positive definite: logdet is NaN */
+#define FIF_FLAG_LMIN_TIE 4u /* smallest eigenvalue within 1e-8 lambda_max of the next */
+
+typedef struct {
+  double origin[3]; /* centre of voxel (0, 0, 0), metres */
+  double h;         /* voxel edge, metres */
+  int32_t nx, ny, nz;
+  int32_t reserved; /* must be 0 */
+} fif_grid;
+
+typedef struct {
+  double half_fov;      /* alpha, radians (pi/4 for a 90 deg FoV) */
+  double v_alpha;       /* quadratic visibility at the FoV boundary */
+  double sigma_bearing; /* radians */
+  double r_min, r_max;  /* V_t range predicate, metres; r_max may be INFINITY */
+} fif_vis;
+
+typedef struct {
+  double fx, fy, cx, cy; /* pixels */
+  int32_t width, height; /* image bounds: 0 <= u < width, 0 <= v < height */
+} fif_pinhole;
+
+typedef struct {
+  fif_grid grid;
+  fif_vis vis;
+  int32_t prec; /* FIF_FP32_NAIVE | FIF_FP32_COMP | FIF_FP64 */
+  int32_t kind; /* FIF_KIND_INFO | FIF_KIND_TRACE */
+  void* data;   /* device buffer of fif_field_bytes(&grid, prec, kind) bytes, 256-B aligned */
+} fif_field;
+
+/* Bytes of the device buffer of a field.  The layout is private to the
+ * library; fif_field_export recovers the paper's blocks from it.  Returns 0 for
+ * an invalid grid, precision or kind. */
+size_t fif_field_bytes(const fif_grid* grid, int32_t prec, int32_t kind);
+
+/* Bytes of scratch device memory fif_build needs (may be 0). */
+size_t fif_workspace_bytes(const fif_grid* grid, int64_t n_landmarks, int32_t prec);
+
+/* Build a field (Sec. VI-A): for every voxel centre t_v,
+ *   C_I(t_v) = sum_{i in V_{t_v}} diag6(vp(u_i)) I_i      (eq:general_info_pif)
+ * or, for FIF_KIND_TRACE, C_Tr(t_v) = sum vp(u_i) Tr(I_i)  (eq:general_trace_pif).
+ * landmarks: double[n_landmarks][3], world coordinates.  field->data is
+ * overwritten.  Deterministic: the summation order is fixed. */
+fif_status fif_build(const double* landmarks, int64_t n_landmarks, fif_field* field,
+                     void* workspace, size_t workspace_bytes, void* stream);
+
+/* Incremental update (Sec. VI-A, "Offline Processing vs. Online Update"): add
+ * (sign = +1) or remove (sign = -1) the contribution of the given landmarks to
+ * every voxel whose centre has them in range.  Same landmark layout as
+ * fif_build. */
+fif_status fif_update(const double* landmarks, int64_t n_landmarks, int32_t sign,
+                      fif_field* field, void* stream);
+
+/* Batched pose query (Sec. VI-A, eq:fim_separation): F = V_I(R) C_I(t) with
+ * C_I(t) interpolated from the voxel centres, reduced to the requested metrics
+ * (eq:cost_info: trace, smallest eigenvalue, log-det; the latter two in FP64).
+ * t: [m][3], q: [m][4]; float for FP32 fields, double for FP64 fields.
+ * out: double[m][ncols], ncols = popcount(metrics & 7) + (metrics & FIF_FIM21 ? 21 : 0).
+ * flags: uint8[m] or NULL.  For FIF_KIND_TRACE fields only FIF_TRACE is valid.
+ * m = 0 is allowed (nothing is enqueued). */
+fif_status fif_query(const fif_field* field, const void* t, const void* q, int64_t m,
+                     uint32_t metrics, int32_t interp, double* out, uint8_t* flags,
+                     void* stream);
+
+/* Gradient of L = sum_r sum_c dL_dout[r][c] s_c(pose_r) w.r.t. each pose:
+ *   dL_dt[m][3]   through the trilinear weights,
+ *   dL_dphi[m][3] w.r.t. the left so(3) perturbation of R_wc.
+ * metrics: subset of FIF_TRACE | FIF_LMIN | FIF_LOGDET (dL_dout has that many
+ * columns, in bit order).  dL_dt/dL_dphi have the type of t (float or double).
+ * out (double[m][popcount], or NULL) receives the forward metrics as well.
+ * Trilinear interpolation only; the derivative is one-sided on cell faces. */
+fif_status fif_query_grad(const fif_field* field, const void* t, const void* q, int64_t m,
+                          uint32_t metrics, const double* dL_dout, void* dL_dt, void* dL_dphi,
+                          double* out, void* stream);
+
+/* Point-cloud brute force (eq:cost_info, eq:vis_fim): F = sum_{i in V_t} v_i I_i
+ * for each pose, with v_i the quadratic visibility of z.u_i (cam == NULL,
+ * eq:quad_vis_approx, unclamped) or the exact pinhole test (eq:exact_vis_func:
+ * in front of the camera and inside [0, width) x [0, height)).
+ * t, q: float for FP32 precisions, double for FIF_FP64.  out as fif_query. */
+fif_status pc_query(const double* landmarks, int64_t n_landmarks, const fif_vis* vis,
+                    const fif_pinhole* cam, int32_t prec, const void* t, const void* q,
+                    int64_t m, uint32_t metrics, double* out, void* stream);
+
+/* The paper's positional information factor of the listed voxels, recovered
+ * from the field: blocks[n][10][21] (double), block k = sum_i vp_k(u_i) I_i in
+ * world coordinates (eq:general_info_pif), 21 = upper triangle row-major.
+ * For FIF_KIND_TRACE fields: blocks[n][10] = C_Tr.  voxel_ids: int64[n]. */
+fif_status fif_field_export(const fif_field* field, const int64_t* voxel_ids, int64_t n,
+                            double* blocks, void* stream);
+
+/* Static string for a status code. */
+const char* fif_status_string(fif_status status);
+
+/* Thread-local text of the last FIF_EDEVICE / FIF_EINVAL of this thread. */
+const char* fif_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FIF_H */

@@ -1,0 +1,279 @@
+// C-ABI layer of libfif.so: argument validation on the host, then one kernel
+// launch per call on the caller's stream.  No device memory is allocated here.
+#include <math.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <string>
+
+#include "../../include/fif.h"
+#include "fif_kernels.h"
+
+namespace {
+
+thread_local std::string g_last_error;
+
+fif_status fail(fif_status st, const char* fmt, const char* detail = "") {
+  char buf[512];
+  snprintf(buf, sizeof(buf), fmt, detail);
+  g_last_error = buf;
+  return st;
+}
+
+fif_status device_status(hipError_t e, const char* where) {
+  if (e == hipSuccess) return FIF_OK;
+  std::string msg = std::string(where) + ": " + hipGetErrorString(e);
+  g_last_error = msg;
+  return FIF_EDEVICE;
+}
+
+bool grid_ok(const fif_grid* g) {
+  if (!g) return false;
+  if (g->nx < 1 || g->ny < 1 || g->nz < 1 || g->reserved != 0) return false;
+  if (!(g->h > 0.0) || !isfinite(g->h)) return false;
+  for (int c = 0; c < 3; ++c)
+    if (!isfinite(g->origin[c])) return false;
+  // record offsets are computed in size_t; keep the voxel count sane
+  const double nv = (double)g->nx * g->ny * g->nz;
+  return nv <= 4.0e9;
+}
+
+bool prec_ok(int32_t p) { return p == FIF_FP32_NAIVE || p == FIF_FP32_COMP || p == FIF_FP64; }
+bool kind_ok(int32_t k) { return k == FIF_KIND_INFO || k == FIF_KIND_TRACE; }
+
+bool vis_ok(const fif_vis* v) {
+  if (!v) return false;
+  if (!(v->half_fov > 0.0 && v->half_fov < M_PI)) return false;
+  if (!isfinite(v->v_alpha)) return false;
+  if (!(v->sigma_bearing > 0.0) || !isfinite(v->sigma_bearing)) return false;
+  if (!(v->r_min >= 0.0) || !isfinite(v->r_min)) return false;
+  if (!(v->r_max >= v->r_min)) return false;  // INFINITY allowed
+  return true;
+}
+
+bool aligned(const void* p, size_t a) { return ((uintptr_t)p % a) == 0; }
+
+fif::GridDev grid_dev(const fif_grid* g) {
+  fif::GridDev d;
+  d.ox = g->origin[0]; d.oy = g->origin[1]; d.oz = g->origin[2];
+  d.h = g->h; d.inv_h = 1.0 / g->h;
+  d.nx = g->nx; d.ny = g->ny; d.nz = g->nz;
+  return d;
+}
+
+// Quadratic visibility coefficients from eq:quadratic_conditions:
+//   v(0) = 1, v(pi) = 0  ->  k1 = 1/2, k2 + k0 = 1/2;  v(alpha) = v_alpha.
+fif::VisDev vis_dev(const fif_vis* v) {
+  fif::VisDev d;
+  const double c = cos(v->half_fov), s2 = 1.0 - c * c;
+  d.k1 = 0.5;
+  d.k2 = (0.5 * (1.0 + c) - v->v_alpha) / s2;
+  d.k0 = 0.5 - d.k2;
+  d.inv_s2 = 1.0 / (v->sigma_bearing * v->sigma_bearing);
+  return d;
+}
+
+void range_bounds(const fif_vis* v, float* lo2, float* hi2) {
+  float lo = (float)(v->r_min * v->r_min);
+  *lo2 = lo < 1e-12f ? 1e-12f : lo;
+  *hi2 = isinf(v->r_max) ? INFINITY : (float)(v->r_max * v->r_max);
+}
+
+size_t record_scalars(int32_t kind) { return kind == FIF_KIND_INFO ? fif::kRec : fif::kTRec; }
+size_t scalar_bytes(int32_t prec) { return prec == FIF_FP64 ? 8 : 4; }
+
+fif_status check_field(const fif_field* f) {
+  if (!f) return fail(FIF_EINVAL, "field is NULL%s");
+  if (!grid_ok(&f->grid)) return fail(FIF_EINVAL, "invalid grid%s");
+  if (!prec_ok(f->prec)) return fail(FIF_EINVAL, "invalid precision%s");
+  if (!kind_ok(f->kind)) return fail(FIF_EINVAL, "invalid field kind%s");
+  if (!vis_ok(&f->vis)) return fail(FIF_EINVAL, "invalid visibility parameters%s");
+  if (!f->data) return fail(FIF_EINVAL, "field data is NULL%s");
+  if (!aligned(f->data, 16)) return fail(FIF_EINVAL, "field data must be 16-byte aligned%s");
+  return FIF_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t fif_field_bytes(const fif_grid* grid, int32_t prec, int32_t kind) {
+  if (!grid_ok(grid) || !prec_ok(prec) || !kind_ok(kind)) return 0;
+  return (size_t)grid->nx * grid->ny * grid->nz * record_scalars(kind) * scalar_bytes(prec);
+}
+
+size_t fif_workspace_bytes(const fif_grid* grid, int64_t n_landmarks, int32_t prec) {
+  (void)grid; (void)n_landmarks; (void)prec;
+  return 0;
+}
+
+static fif_status build_common(const double* landmarks, int64_t n_landmarks, fif_field* field,
+                               int accumulate, int sign, void* stream, const char* where) {
+  fif_status st = check_field(field);
+  if (st != FIF_OK) return st;
+  if (n_landmarks < 0) return fail(FIF_EINVAL, "n_landmarks < 0%s");
+  if (n_landmarks > 0 && !landmarks) return fail(FIF_EINVAL, "landmarks is NULL%s");
+  if (landmarks && !aligned(landmarks, 8)) return fail(FIF_EINVAL, "landmarks must be 8-byte aligned%s");
+  if (n_landmarks > ((int64_t)1 << 40)) return fail(FIF_EINVAL, "too many landmarks%s");
+  if ((field->grid.ny + 7) / 8 > 65535 || (field->grid.nz + 3) / 4 > 65535)
+    return fail(FIF_EUNSUPPORTED, "grid too large for one build launch%s");
+  fif::BuildArgs a;
+  a.lm = landmarks;
+  a.L = n_landmarks;
+  a.g = grid_dev(&field->grid);
+  range_bounds(&field->vis, &a.lo2, &a.hi2);
+  a.out = field->data;
+  a.accumulate = accumulate;
+  a.sign = sign;
+  hipError_t e = fif::launch_build(a, field->prec, field->kind, (hipStream_t)stream);
+  return device_status(e, where);
+}
+
+fif_status fif_build(const double* landmarks, int64_t n_landmarks, fif_field* field,
+                     void* workspace, size_t workspace_bytes, void* stream) {
+  (void)workspace; (void)workspace_bytes;
+  return build_common(landmarks, n_landmarks, field, 0, 1, stream, "fif_build");
+}
+
+fif_status fif_update(const double* landmarks, int64_t n_landmarks, int32_t sign,
+                      fif_field* field, void* stream) {
+  if (sign != 1 && sign != -1) return fail(FIF_EINVAL, "sign must be +1 or -1%s");
+  if (n_landmarks == 0) {
+    fif_status st = check_field(field);
+    return st;
+  }
+  return build_common(landmarks, n_landmarks, field, 1, sign, stream, "fif_update");
+}
+
+static int metric_cols(uint32_t metrics) {
+  return (int)((metrics & FIF_TRACE) != 0) + (int)((metrics & FIF_LMIN) != 0) +
+         (int)((metrics & FIF_LOGDET) != 0) + ((metrics & FIF_FIM21) ? 21 : 0);
+}
+
+static fif_status query_common(const fif_field* field, const void* t, const void* q, int64_t m,
+                               uint32_t metrics, int32_t interp, double* out, uint8_t* flags,
+                               bool grad, const double* dL_dout, void* dL_dt, void* dL_dphi,
+                               void* stream, const char* where) {
+  fif_status st = check_field(field);
+  if (st != FIF_OK) return st;
+  if (m < 0) return fail(FIF_EINVAL, "m < 0%s");
+  if (m > ((int64_t)1 << 40)) return fail(FIF_EINVAL, "m too large%s");
+  if (metrics == 0 || (metrics & ~15u)) return fail(FIF_EINVAL, "invalid metric mask%s");
+  if (interp != FIF_TRILINEAR && interp != FIF_NEAREST) return fail(FIF_EINVAL, "invalid interp%s");
+  if (field->kind == FIF_KIND_TRACE && metrics != FIF_TRACE)
+    return fail(FIF_EINVAL, "a trace field only answers FIF_TRACE%s");
+  if (grad) {
+    if ((metrics & 7u) == 0 || (metrics & FIF_FIM21))
+      return fail(FIF_EINVAL, "gradient metrics must be a subset of trace|lmin|logdet%s");
+    if (interp != FIF_TRILINEAR) return fail(FIF_EUNSUPPORTED, "gradient needs trilinear interpolation%s");
+    if (field->kind != FIF_KIND_INFO) return fail(FIF_EUNSUPPORTED, "gradient needs an information field%s");
+  }
+  if (m == 0) return FIF_OK;
+  const size_t sb = scalar_bytes(field->prec);
+  if (!t || !q) return fail(FIF_EINVAL, "t or q is NULL%s");
+  if (!aligned(t, sb) || !aligned(q, sb)) return fail(FIF_EINVAL, "t/q misaligned for the field precision%s");
+  if (!grad && !out) return fail(FIF_EINVAL, "out is NULL%s");
+  if (out && !aligned(out, 8)) return fail(FIF_EINVAL, "out must be 8-byte aligned%s");
+  if (grad && (!dL_dout || !dL_dt || !dL_dphi)) return fail(FIF_EINVAL, "gradient buffers are NULL%s");
+  fif::QueryArgs a;
+  memset(&a, 0, sizeof(a));
+  a.field = field->data;
+  a.g = grid_dev(&field->grid);
+  a.vis = vis_dev(&field->vis);
+  a.t = t;
+  a.q = q;
+  a.m = m;
+  a.metrics = metrics;
+  a.ncols = grad ? metric_cols(metrics & 7u) : metric_cols(metrics);
+  a.interp = interp;
+  a.out = out;
+  a.flags = flags;
+  a.dL_dout = dL_dout;
+  a.dL_dt = dL_dt;
+  a.dL_dphi = dL_dphi;
+  hipError_t e = fif::launch_query(a, field->prec, field->kind, grad, (hipStream_t)stream);
+  return device_status(e, where);
+}
+
+fif_status fif_query(const fif_field* field, const void* t, const void* q, int64_t m,
+                     uint32_t metrics, int32_t interp, double* out, uint8_t* flags,
+                     void* stream) {
+  return query_common(field, t, q, m, metrics, interp, out, flags, false, nullptr, nullptr,
+                      nullptr, stream, "fif_query");
+}
+
+fif_status fif_query_grad(const fif_field* field, const void* t, const void* q, int64_t m,
+                          uint32_t metrics, const double* dL_dout, void* dL_dt, void* dL_dphi,
+                          double* out, void* stream) {
+  return query_common(field, t, q, m, metrics, FIF_TRILINEAR, out, nullptr, true, dL_dout,
+                      dL_dt, dL_dphi, stream, "fif_query_grad");
+}
+
+fif_status pc_query(const double* landmarks, int64_t n_landmarks, const fif_vis* vis,
+                    const fif_pinhole* cam, int32_t prec, const void* t, const void* q,
+                    int64_t m, uint32_t metrics, double* out, void* stream) {
+  if (!vis_ok(vis)) return fail(FIF_EINVAL, "invalid visibility parameters%s");
+  if (!prec_ok(prec)) return fail(FIF_EINVAL, "invalid precision%s");
+  if (n_landmarks < 0 || m < 0) return fail(FIF_EINVAL, "negative size%s");
+  if (metrics == 0 || (metrics & ~15u)) return fail(FIF_EINVAL, "invalid metric mask%s");
+  if (n_landmarks > 0 && !landmarks) return fail(FIF_EINVAL, "landmarks is NULL%s");
+  if (cam && (!(cam->fx > 0) || !(cam->fy > 0) || cam->width < 1 || cam->height < 1))
+    return fail(FIF_EINVAL, "invalid pinhole camera%s");
+  if (m == 0) return FIF_OK;
+  const size_t sb = scalar_bytes(prec);
+  if (!t || !q || !out) return fail(FIF_EINVAL, "t, q or out is NULL%s");
+  if (!aligned(t, sb) || !aligned(q, sb) || !aligned(out, 8))
+    return fail(FIF_EINVAL, "misaligned pointer%s");
+  fif::PcArgs a;
+  memset(&a, 0, sizeof(a));
+  a.lm = landmarks;
+  a.L = n_landmarks;
+  range_bounds(vis, &a.lo2, &a.hi2);
+  a.vis = vis_dev(vis);
+  a.exact = cam ? 1 : 0;
+  if (cam) {
+    a.fx = cam->fx; a.fy = cam->fy; a.cx = cam->cx; a.cy = cam->cy;
+    a.width = cam->width; a.height = cam->height;
+  }
+  a.t = t;
+  a.q = q;
+  a.m = m;
+  a.metrics = metrics;
+  a.ncols = metric_cols(metrics);
+  a.out = out;
+  hipError_t e = fif::launch_pc(a, prec, (hipStream_t)stream);
+  return device_status(e, "pc_query");
+}
+
+fif_status fif_field_export(const fif_field* field, const int64_t* voxel_ids, int64_t n,
+                            double* blocks, void* stream) {
+  fif_status st = check_field(field);
+  if (st != FIF_OK) return st;
+  if (n < 0) return fail(FIF_EINVAL, "n < 0%s");
+  if (n == 0) return FIF_OK;
+  if (!voxel_ids || !blocks) return fail(FIF_EINVAL, "voxel_ids or blocks is NULL%s");
+  fif::ExportArgs a;
+  a.field = field->data;
+  a.g = grid_dev(&field->grid);
+  a.inv_s2 = 1.0 / (field->vis.sigma_bearing * field->vis.sigma_bearing);
+  a.ids = voxel_ids;
+  a.n = n;
+  a.out = blocks;
+  hipError_t e = fif::launch_export(a, field->prec, field->kind, (hipStream_t)stream);
+  return device_status(e, "fif_field_export");
+}
+
+const char* fif_status_string(fif_status s) {
+  switch (s) {
+    case FIF_OK: return "FIF_OK";
+    case FIF_EINVAL: return "FIF_EINVAL: invalid argument";
+    case FIF_ENOMEM: return "FIF_ENOMEM: workspace too small";
+    case FIF_EDEVICE: return "FIF_EDEVICE: HIP runtime error";
+    case FIF_EUNSUPPORTED: return "FIF_EUNSUPPORTED: unsupported combination";
+    default: return "unknown fif_status";
+  }
+}
+
+const char* fif_last_error(void) { return g_last_error.c_str(); }
+
+}  // extern "C"

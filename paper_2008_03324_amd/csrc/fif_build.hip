@@ -1,0 +1,224 @@
+// Field construction kernels (Sec. VI-A: factors computed at the voxel centres
+// from all landmarks in range).
+//
+// One lane owns one voxel; a 256-thread workgroup owns an 8x8x4 voxel tile
+// (each wave a 4x4x4 sub-tile, so the lanes of a wave see nearly the same
+// landmarks in range and the range test stays wave-coherent).  Landmarks are
+// staged through LDS in batches of 256 and read back as broadcasts; each lane
+// folds every landmark in range into its 66 moment sums (see fif_device.h).
+// The summation order is fixed (landmark order), so results are bitwise
+// reproducible.
+#include "fif_device.h"
+#include "fif_kernels.h"
+
+namespace fif {
+
+constexpr int kBuildThreads = 256;
+constexpr int kBatch = 256;
+
+template <typename T>
+struct LmT;
+template <>
+struct LmT<float> { using type = float4; };
+template <>
+struct LmT<double> { using type = double4; };
+
+// Two-sum merge of a partial into (hi, lo): hi + lo gains x exactly.
+__device__ inline void two_sum_into(float& hi, float& lo, float x) {
+  float s = hi + x;
+  float bb = s - hi;
+  float err = (hi - (s - bb)) + (x - bb);
+  hi = s;
+  lo += err;
+}
+
+// Accumulate one landmark's contribution into the 66 moments.
+template <typename T>
+__device__ inline void info_pair(T acc[kMom], T dx, T dy, T dz, T rn) {
+  T ux = dx * rn, uy = dy * rn, uz = dz * rn;
+  T rn2 = rn * rn;
+  T u[3] = {ux, uy, uz};
+  T m2[6], m3[10], m4[15];
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+#pragma unroll
+    for (int b = a; b < 3; ++b) m2[i2(a, b)] = u[a] * u[b];
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+#pragma unroll
+    for (int b = a; b < 3; ++b)
+#pragma unroll
+      for (int c = b; c < 3; ++c) m3[i3(a, b, c)] = m2[i2(a, b)] * u[c];
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+#pragma unroll
+    for (int b = a; b < 3; ++b)
+#pragma unroll
+      for (int c = b; c < 3; ++c)
+#pragma unroll
+        for (int d = c; d < 3; ++d) m4[i4(a, b, c, d)] = m3[i3(a, b, c)] * u[d];
+#pragma unroll
+  for (int i = 0; i < 15; ++i) {
+    acc[O_G0_4 + i] += m4[i];
+    acc[O_G2_4 + i] = fma(m4[i], rn2, acc[O_G2_4 + i]);
+  }
+#pragma unroll
+  for (int i = 0; i < 10; ++i) {
+    acc[O_G0_3 + i] += m3[i];
+    acc[O_G2_3 + i] = fma(m3[i], rn2, acc[O_G2_3 + i]);
+    acc[O_G1_3 + i] = fma(m3[i], rn, acc[O_G1_3 + i]);
+  }
+#pragma unroll
+  for (int i = 0; i < 6; ++i) acc[O_G1_2 + i] = fma(m2[i], rn, acc[O_G1_2 + i]);
+}
+
+// Trace factor of one landmark without 1/sigma^2: vp(u) Tr(I_i) sigma^2 with
+// Tr(I_i) sigma^2 = (2 + |p|^2 + (u.p)^2) / n^2.
+template <typename T>
+__device__ inline void trace_pair(T acc[10], T dx, T dy, T dz, T rn, T px, T py, T pz, T p2) {
+  T rn2 = rn * rn;
+  T ux = dx * rn, uy = dy * rn, uz = dz * rn;
+  T up = ux * px + uy * py + uz * pz;
+  T tr = (T(2) + p2 + up * up) * rn2;
+  acc[0] = fma(ux * ux, tr, acc[0]);
+  acc[1] = fma(uy * uy, tr, acc[1]);
+  acc[2] = fma(uz * uz, tr, acc[2]);
+  acc[3] = fma(ux * uy, tr, acc[3]);
+  acc[4] = fma(ux * uz, tr, acc[4]);
+  acc[5] = fma(uy * uz, tr, acc[5]);
+  acc[6] = fma(ux, tr, acc[6]);
+  acc[7] = fma(uy, tr, acc[7]);
+  acc[8] = fma(uz, tr, acc[8]);
+  acc[9] += tr;
+}
+
+template <typename T>
+__device__ inline T inv_sqrt(T x);
+template <>
+__device__ inline float inv_sqrt<float>(float x) { return rsqrtf(x); }
+template <>
+__device__ inline double inv_sqrt<double>(double x) { return 1.0 / sqrt(x); }
+
+// PREC: FIF_FP32_NAIVE / FIF_FP32_COMP / FIF_FP64; KIND: info or trace.
+template <int PREC, int KIND>
+__global__ __launch_bounds__(kBuildThreads) void build_kernel(BuildArgs a) {
+  using T = typename std::conditional<PREC == 2, double, float>::type;
+  using L4 = typename LmT<T>::type;
+  constexpr int NACC = (KIND == 0) ? kMom : 10;
+  constexpr int STRIDE = (KIND == 0) ? kRec : kTRec;
+  constexpr bool COMP = (PREC == 1);
+
+  __shared__ L4 s_lm[kBatch];
+
+  const int tid = threadIdx.x;
+  const int wave = tid >> 6, lane = tid & 63;
+  const int ix = blockIdx.x * 8 + (wave & 1) * 4 + (lane & 3);
+  const int iy = blockIdx.y * 8 + (wave >> 1) * 4 + ((lane >> 2) & 3);
+  const int iz = blockIdx.z * 4 + (lane >> 4);
+  const bool valid = ix < a.g.nx && iy < a.g.ny && iz < a.g.nz;
+
+  const double tx = a.g.ox + (double)ix * a.g.h;
+  const double ty = a.g.oy + (double)iy * a.g.h;
+  const double tz = a.g.oz + (double)iz * a.g.h;
+  const float fx = (float)tx, fy = (float)ty, fz = (float)tz;
+  const T vx = (T)tx, vy = (T)ty, vz = (T)tz;
+
+  T acc[NACC];
+  float hi[COMP ? NACC : 1], lo[COMP ? NACC : 1];
+#pragma unroll
+  for (int i = 0; i < NACC; ++i) acc[i] = T(0);
+  if (COMP) {
+#pragma unroll
+    for (int i = 0; i < NACC; ++i) { hi[i] = 0.f; lo[i] = 0.f; }
+  }
+
+  for (int64_t base = 0; base < a.L; base += kBatch) {
+    const int nb = (int)((a.L - base) < kBatch ? (a.L - base) : kBatch);
+    __syncthreads();
+    if (tid < nb) {
+      const double* p = a.lm + 3 * (base + tid);
+      double px = p[0], py = p[1], pz = p[2];
+      L4 v;
+      v.x = (T)px; v.y = (T)py; v.z = (T)pz;
+      v.w = (T)(px * px + py * py + pz * pz);
+      s_lm[tid] = v;
+    }
+    __syncthreads();
+    for (int i = 0; i < nb; ++i) {
+      const L4 p = s_lm[i];
+      // V_t range test in FP32 (same decision in every precision)
+      float ddx = (float)p.x - fx, ddy = (float)p.y - fy, ddz = (float)p.z - fz;
+      float n2 = __fmaf_rn(ddz, ddz, __fmaf_rn(ddy, ddy, ddx * ddx));
+      bool in = valid && (n2 >= a.lo2) && (n2 <= a.hi2);
+      if (in) {
+        T dx = p.x - vx, dy = p.y - vy, dz = p.z - vz;
+        T nn = (PREC == 2) ? (T)fma((double)dz, (double)dz, fma((double)dy, (double)dy, (double)dx * dx))
+                           : (T)n2;
+        T rn = inv_sqrt<T>(nn);
+        if (KIND == 0)
+          info_pair<T>(acc, dx, dy, dz, rn);
+        else
+          trace_pair<T>(acc, dx, dy, dz, rn, p.x, p.y, p.z, p.w);
+      }
+    }
+    if (COMP) {
+#pragma unroll
+      for (int k = 0; k < NACC; ++k) {
+        two_sum_into(hi[k], lo[k], (float)acc[k]);
+        acc[k] = T(0);
+      }
+    }
+  }
+  if (!valid) return;
+  const size_t vox = (size_t)ix + (size_t)a.g.nx * ((size_t)iy + (size_t)a.g.ny * (size_t)iz);
+  T* out = reinterpret_cast<T*>(a.out) + vox * STRIDE;
+  T res[STRIDE];
+#pragma unroll
+  for (int k = 0; k < STRIDE; ++k) {
+    T v = T(0);
+    if (k < NACC) v = COMP ? (T)(hi[k] + lo[k]) : acc[k];
+    res[k] = v;
+  }
+  if (a.accumulate) {
+#pragma unroll
+    for (int k = 0; k < NACC; ++k) res[k] = out[k] + (T)a.sign * res[k];
+  }
+  if (PREC == 2) {
+#pragma unroll
+    for (int k = 0; k < STRIDE; k += 2) {
+      double2 v;
+      v.x = (double)res[k];
+      v.y = (double)res[k + 1];
+      reinterpret_cast<double2*>(out)[k / 2] = v;
+    }
+  } else {
+#pragma unroll
+    for (int k = 0; k < STRIDE; k += 4) {
+      float4 v;
+      v.x = (float)res[k];
+      v.y = (float)res[k + 1];
+      v.z = (float)res[k + 2];
+      v.w = (float)res[k + 3];
+      reinterpret_cast<float4*>(out)[k / 4] = v;
+    }
+  }
+}
+
+hipError_t launch_build(const BuildArgs& a, int prec, int kind, hipStream_t stream) {
+  dim3 grid((a.g.nx + 7) / 8, (a.g.ny + 7) / 8, (a.g.nz + 3) / 4);
+  dim3 block(kBuildThreads);
+#define FIF_LAUNCH(P, K) hipLaunchKernelGGL((build_kernel<P, K>), grid, block, 0, stream, a)
+  if (kind == 0) {
+    if (prec == 0) FIF_LAUNCH(0, 0);
+    else if (prec == 1) FIF_LAUNCH(1, 0);
+    else FIF_LAUNCH(2, 0);
+  } else {
+    if (prec == 0) FIF_LAUNCH(0, 1);
+    else if (prec == 1) FIF_LAUNCH(1, 1);
+    else FIF_LAUNCH(2, 1);
+  }
+#undef FIF_LAUNCH
+  return hipGetLastError();
+}
+
+}  // namespace fif

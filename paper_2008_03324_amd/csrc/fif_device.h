@@ -1,0 +1,576 @@
+// Device-side building blocks of the FIF kernels (gfx950).
+//
+// Field layout ("moment form").  Under the quadratic visibility of
+// eq:quad_vis_approx the positional information factor of a voxel
+// (eq:general_info_pif) is a fixed linear function of 66 sums over the
+// landmarks in range, u = (p - t_v)/n, n = |p - t_v|:
+//   G0: sum u^a             for all monomials of degree 4 (15) and 3 (10)
+//   G2: sum u^a / n^2       degree 4 (15) and 3 (10)
+//   G1: sum u^a / n         degree 3 (10) and 2 (6)
+// Lower degrees follow from |u| = 1 (e.g. sum u_a u_b = sum_c sum u_a u_b u_c u_c).
+// Writing the per-landmark FIM about the voxel centre,
+//   I_i = M(t_v)^T (1/sigma^2) [[P/n^2, -[u]x/n], [[u]x/n, P]] M(t_v),
+//   P = I - u u^T,  M(t) = [[I, -[t]x], [0, I]],
+// follows from eq:jac_pose_global with [p]x = [t_v]x + [d]x and P[d]x = [d]x.
+// A voxel record is 68 scalars (66 used, 2 zero) of the field's precision.
+//
+// 21-vectors hold symmetric 6x6 matrices as their upper triangle, row-major.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace fif {
+
+constexpr int kRec = 68;   // scalars per voxel record (information field)
+constexpr int kMom = 66;   // used scalars
+constexpr int kTRec = 12;  // scalars per voxel record (trace field, 10 used)
+constexpr int O_G0_4 = 0, O_G0_3 = 15, O_G2_4 = 25, O_G2_3 = 40, O_G1_3 = 50, O_G1_2 = 60;
+
+// ------------------------------------------------------------ symmetric indices
+
+__host__ __device__ constexpr int i2(int a, int b) {  // a <= b
+  return a == 0 ? b : (a == 1 ? 2 + b : 5);
+}
+__host__ __device__ constexpr int s2(int a, int b) { return a <= b ? i2(a, b) : i2(b, a); }
+
+__host__ __device__ constexpr int i3(int a, int b, int c) {  // a <= b <= c
+  int idx = 0;
+  for (int x = 0; x < 3; ++x)
+    for (int y = x; y < 3; ++y)
+      for (int z = y; z < 3; ++z) {
+        if (x == a && y == b && z == c) return idx;
+        ++idx;
+      }
+  return -1;
+}
+__host__ __device__ constexpr int s3(int a, int b, int c) {
+  // sort three indices
+  return (a <= b) ? ((b <= c) ? i3(a, b, c) : (a <= c ? i3(a, c, b) : i3(c, a, b)))
+                  : ((a <= c) ? i3(b, a, c) : (b <= c ? i3(b, c, a) : i3(c, b, a)));
+}
+
+__host__ __device__ constexpr int i4(int a, int b, int c, int d) {  // sorted
+  int idx = 0;
+  for (int x = 0; x < 3; ++x)
+    for (int y = x; y < 3; ++y)
+      for (int z = y; z < 3; ++z)
+        for (int w = z; w < 3; ++w) {
+          if (x == a && y == b && z == c && w == d) return idx;
+          ++idx;
+        }
+  return -1;
+}
+__host__ __device__ constexpr int s4(int a, int b, int c, int d) {
+  int v[4] = {a, b, c, d};
+  for (int i = 0; i < 4; ++i)
+    for (int j = 0; j + 1 < 4 - i; ++j)
+      if (v[j] > v[j + 1]) {
+        int t = v[j]; v[j] = v[j + 1]; v[j + 1] = t;
+      }
+  return i4(v[0], v[1], v[2], v[3]);
+}
+
+__host__ __device__ constexpr int u21(int i, int j) {  // i <= j < 6
+  return i * 6 - (i * (i - 1)) / 2 + (j - i);
+}
+__host__ __device__ constexpr int su21(int i, int j) { return i <= j ? u21(i, j) : u21(j, i); }
+
+// ------------------------------------------------------------ pose helpers
+
+// Optical axis z = R(q) e3 for a quaternion (w, x, y, z) of any norm.
+__device__ inline void quat_axis(double w, double x, double y, double z, double out[3]) {
+  double n = w * w + x * x + y * y + z * z;
+  double inv = 1.0 / n;
+  out[0] = 2.0 * (x * z + w * y) * inv;
+  out[1] = 2.0 * (y * z - w * x) * inv;
+  out[2] = (w * w - x * x - y * y + z * z) * inv;
+}
+
+// Full R_wc (row-major) for a quaternion of any norm.
+__device__ inline void quat_R(double w, double x, double y, double z, double R[9]) {
+  double n = w * w + x * x + y * y + z * z;
+  double inv = 1.0 / n;
+  R[0] = (w * w + x * x - y * y - z * z) * inv;
+  R[1] = 2.0 * (x * y - w * z) * inv;
+  R[2] = 2.0 * (x * z + w * y) * inv;
+  R[3] = 2.0 * (x * y + w * z) * inv;
+  R[4] = (w * w - x * x + y * y - z * z) * inv;
+  R[5] = 2.0 * (y * z - w * x) * inv;
+  R[6] = 2.0 * (x * z - w * y) * inv;
+  R[7] = 2.0 * (y * z + w * x) * inv;
+  R[8] = (w * w - x * x - y * y + z * z) * inv;
+}
+
+struct GridDev {
+  double ox, oy, oz, h, inv_h;
+  int32_t nx, ny, nz;
+};
+
+// Per-axis cell of a position: lower index, fraction, d fraction / d t, clamp.
+struct AxisCell {
+  int32_t i0;
+  int32_t step;  // 1, or 0 on a single-voxel axis
+  double f;
+  double df;
+  bool clamped;
+};
+
+__device__ inline AxisCell axis_cell(double t, double o, double h, int32_t n) {
+  AxisCell c;
+  double g = (t - o) / h;
+  c.clamped = !(g >= 0.0 && g <= (double)(n - 1));
+  if (n == 1) {
+    c.i0 = 0; c.step = 0; c.f = 0.0; c.df = 0.0;
+    return c;
+  }
+  double fl = floor(g);
+  fl = fmax(fl, 0.0);                 // NaN g gives fl = 0 here
+  fl = fmin(fl, (double)(n - 2));
+  c.i0 = (int32_t)fl;
+  c.step = 1;
+  c.f = g - fl;
+  c.df = 1.0 / h;
+  if (c.f < 0.0) { c.f = 0.0; c.df = 0.0; }
+  if (c.f > 1.0) { c.f = 1.0; c.df = 0.0; }
+  return c;
+}
+
+__device__ inline int32_t axis_nearest(double t, double o, double h, int32_t n, bool* clamped) {
+  double g = (t - o) / h;
+  *clamped = !(g >= 0.0 && g <= (double)(n - 1));
+  double r = floor(g + 0.5);
+  r = fmax(r, 0.0);
+  r = fmin(r, (double)(n - 1));
+  return (int32_t)r;
+}
+
+// ------------------------------------------------------------ moment contraction
+
+// For one moment group with degree-4 part S4[15] and degree-3 part S3[10]
+// (weights 1 or 1/n^2), Q = sum v u u^T with v = k2 c^2 + k1 c + k0, c = z.u.
+template <typename T>
+__device__ inline void group_Q(const T* S4, const T* S3, const double z[3], double k2, double k1,
+                               double k0, double Q[6]) {
+  double zw[6];
+#pragma unroll
+  for (int c = 0; c < 3; ++c)
+#pragma unroll
+    for (int d = c; d < 3; ++d) zw[i2(c, d)] = (c == d ? 1.0 : 2.0) * z[c] * z[d];
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+#pragma unroll
+    for (int b = a; b < 3; ++b) {
+      double q4 = 0.0, q3 = 0.0, s2v = 0.0;
+#pragma unroll
+      for (int c = 0; c < 3; ++c)
+#pragma unroll
+        for (int d = c; d < 3; ++d) q4 = fma(zw[i2(c, d)], (double)S4[s4(a, b, c, d)], q4);
+#pragma unroll
+      for (int c = 0; c < 3; ++c) q3 = fma(z[c], (double)S3[s3(a, b, c)], q3);
+#pragma unroll
+      for (int c = 0; c < 3; ++c) s2v += (double)S4[s4(a, b, c, c)];
+      Q[i2(a, b)] = k2 * q4 + k1 * q3 + k0 * s2v;
+    }
+}
+
+// b = sum v u / n from the G1 group (degree 3 R3[10], degree 2 R2[6]).
+template <typename T>
+__device__ inline void group_b(const T* R3, const T* R2, const double z[3], double k2, double k1,
+                               double k0, double bvec[3]) {
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    double q3 = 0.0, q2 = 0.0, r1 = 0.0;
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+#pragma unroll
+      for (int d = c; d < 3; ++d)
+        q3 = fma((c == d ? 1.0 : 2.0) * z[c] * z[d], (double)R3[s3(a, c, d)], q3);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) q2 = fma(z[c], (double)R2[s2(a, c)], q2);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) r1 += (double)R3[s3(a, c, c)];
+    bvec[a] = k2 * q3 + k1 * q2 + k0 * r1;
+  }
+}
+
+// 3x3 helpers: symmetric matrices as 6-vectors (i2 order), general as row-major 9.
+__device__ inline double sym3(const double* A, int i, int j) { return A[s2(i, j)]; }
+
+// X = M(delta)^T [[A, B], [B^T, D]] M(delta), M(delta) = [[I, -[delta]x], [0, I]]:
+//   TL = A, TR = B + (S A)^T, BR = D + S (S A)^T + S B + (S B)^T,  S = [delta]x.
+__device__ inline void shift_frame(const double A[6], const double B[9], const double D[6],
+                                   const double dl[3], double out[21]) {
+  // rows of S
+  const double S[9] = {0.0, -dl[2], dl[1], dl[2], 0.0, -dl[0], -dl[1], dl[0], 0.0};
+  double SA[9], SB[9];
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+      double sa = 0.0, sb = 0.0;
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        sa = fma(S[i * 3 + k], sym3(A, k, j), sa);
+        sb = fma(S[i * 3 + k], B[k * 3 + j], sb);
+      }
+      SA[i * 3 + j] = sa;
+      SB[i * 3 + j] = sb;
+    }
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = i; j < 3; ++j) out[u21(i, j)] = sym3(A, i, j);
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) out[u21(i, 3 + j)] = B[i * 3 + j] + SA[j * 3 + i];
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = i; j < 3; ++j) {
+      double s = 0.0;  // (S (SA)^T)_ij = sum_k S_ik SA_jk
+#pragma unroll
+      for (int k = 0; k < 3; ++k) s = fma(S[i * 3 + k], SA[j * 3 + k], s);
+      out[u21(3 + i, 3 + j)] = sym3(D, i, j) + s + SB[i * 3 + j] + SB[j * 3 + i];
+    }
+}
+
+// Camera-frame block of one voxel at optical axis z, shifted by delta = t_v - t:
+// returns the 21-vector of M(delta)^T X M(delta) (without the 1/sigma^2 factor).
+template <typename T>
+__device__ inline void corner_fim(const T* rec, const double z[3], double k2, double k1, double k0,
+                                  const double dl[3], double out[21]) {
+  double Q2[6], Q0[6], bv[3];
+  group_Q(rec + O_G2_4, rec + O_G2_3, z, k2, k1, k0, Q2);
+  group_Q(rec + O_G0_4, rec + O_G0_3, z, k2, k1, k0, Q0);
+  group_b(rec + O_G1_3, rec + O_G1_2, z, k2, k1, k0, bv);
+  double A[6], D[6], B[9];
+  double tr2 = Q2[0] + Q2[3] + Q2[5], tr0 = Q0[0] + Q0[3] + Q0[5];
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+#pragma unroll
+    for (int b = a; b < 3; ++b) {
+      A[i2(a, b)] = (a == b ? tr2 : 0.0) - Q2[i2(a, b)];
+      D[i2(a, b)] = (a == b ? tr0 : 0.0) - Q0[i2(a, b)];
+    }
+  // B = -[b]x
+  B[0] = 0.0;    B[1] = bv[2];  B[2] = -bv[1];
+  B[3] = -bv[2]; B[4] = 0.0;    B[5] = bv[0];
+  B[6] = bv[1];  B[7] = -bv[0]; B[8] = 0.0;
+  shift_frame(A, B, D, dl, out);
+}
+
+// General symmetric 6x6 (21) -> world frame: M(t)^T Z M(t).
+__device__ inline void shift21(const double Z[21], const double t[3], double out[21]) {
+  double A[6], D[6], B[9];
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = i; j < 3; ++j) {
+      A[i2(i, j)] = Z[u21(i, j)];
+      D[i2(i, j)] = Z[u21(3 + i, 3 + j)];
+    }
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) B[i * 3 + j] = Z[u21(i, 3 + j)];
+  shift_frame(A, B, D, t, out);
+}
+
+// Adjoint shift for gradients: G' = M(delta) G M(delta)^T with
+//   G = [[P, Q], [Q^T, R]], S = [delta]x:
+//   TL' = P + QS + (QS)^T + S (S R)^T,  TR' = Q - S R,  BR' = R.
+__device__ inline void shift21_adj(const double G[21], const double dl[3], double out[21]) {
+  const double S[9] = {0.0, -dl[2], dl[1], dl[2], 0.0, -dl[0], -dl[1], dl[0], 0.0};
+  double Q[9], QS[9], SR[9];
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) Q[i * 3 + j] = G[u21(i, 3 + j)];
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+      double qs = 0.0, sr = 0.0;
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        qs = fma(Q[i * 3 + k], S[k * 3 + j], qs);
+        sr = fma(S[i * 3 + k], G[su21(3 + k, 3 + j)], sr);
+      }
+      QS[i * 3 + j] = qs;
+      SR[i * 3 + j] = sr;
+    }
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = i; j < 3; ++j) {
+      double s = 0.0;  // (S (SR)^T)_ij = sum_k S_ik SR_jk
+#pragma unroll
+      for (int k = 0; k < 3; ++k) s = fma(S[i * 3 + k], SR[j * 3 + k], s);
+      out[u21(i, j)] = G[u21(i, j)] + QS[i * 3 + j] + QS[j * 3 + i] + s;
+    }
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) out[u21(i, 3 + j)] = Q[i * 3 + j] - SR[i * 3 + j];
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = i; j < 3; ++j) out[u21(3 + i, 3 + j)] = G[u21(3 + i, 3 + j)];
+}
+
+// ------------------------------------------------------------ backward pieces
+
+// For a symmetric 3x3 H (6, i2 order) and one moment group (S4, S3):
+//   val   = sum v (tr H - u^T H u)  (times the group weight)
+//   gz[c] = d val / d z_c
+template <typename T>
+__device__ inline void group_vjp(const T* S4, const T* S3, const double H[6], const double z[3],
+                                 double k2, double k1, double k0, double* val, double gz[3]) {
+  double trH = H[0] + H[3] + H[5];
+  double HS4[6], HS3[3], S2[6], S1[3];
+#pragma unroll
+  for (int c = 0; c < 3; ++c)
+#pragma unroll
+    for (int d = c; d < 3; ++d) {
+      double acc = 0.0, s2v = 0.0;
+#pragma unroll
+      for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int b = a; b < 3; ++b)
+          acc = fma((a == b ? 1.0 : 2.0) * H[i2(a, b)], (double)S4[s4(a, b, c, d)], acc);
+#pragma unroll
+      for (int e = 0; e < 3; ++e) s2v += (double)S4[s4(c, d, e, e)];
+      HS4[i2(c, d)] = acc;
+      S2[i2(c, d)] = s2v;
+    }
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    double acc = 0.0, s1v = 0.0;
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+      for (int b = a; b < 3; ++b)
+        acc = fma((a == b ? 1.0 : 2.0) * H[i2(a, b)], (double)S3[s3(a, b, c)], acc);
+#pragma unroll
+    for (int e = 0; e < 3; ++e) s1v += (double)S3[s3(c, e, e)];
+    HS3[c] = acc;
+    S1[c] = s1v;
+  }
+  double S0 = S2[0] + S2[3] + S2[5];
+  // sv = sum v,  hq = sum v u^T H u
+  double zSz = 0.0, zHSz = 0.0, hS2 = 0.0;
+#pragma unroll
+  for (int c = 0; c < 3; ++c)
+#pragma unroll
+    for (int d = c; d < 3; ++d) {
+      double m = (c == d ? 1.0 : 2.0) * z[c] * z[d];
+      zSz = fma(m, S2[i2(c, d)], zSz);
+      zHSz = fma(m, HS4[i2(c, d)], zHSz);
+      hS2 = fma((c == d ? 1.0 : 2.0) * H[i2(c, d)], S2[i2(c, d)], hS2);
+    }
+  double zS1 = z[0] * S1[0] + z[1] * S1[1] + z[2] * S1[2];
+  double zHS3 = z[0] * HS3[0] + z[1] * HS3[1] + z[2] * HS3[2];
+  double sv = k2 * zSz + k1 * zS1 + k0 * S0;
+  double hq = k2 * zHSz + k1 * zHS3 + k0 * hS2;
+  *val = trH * sv - hq;
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    double zS2c = 0.0, zHS4c = 0.0;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      zS2c = fma(z[d], S2[s2(c, d)], zS2c);
+      zHS4c = fma(z[d], HS4[s2(c, d)], zHS4c);
+    }
+    gz[c] = 2.0 * k2 * (trH * zS2c - zHS4c) + k1 * (trH * S1[c] - HS3[c]);
+  }
+}
+
+// For the G1 group and a 3-vector om: val = om . b, gz = d val / dz.
+template <typename T>
+__device__ inline void group_b_vjp(const T* R3, const T* R2, const double om[3], const double z[3],
+                                   double k2, double k1, double k0, double* val, double gz[3]) {
+  double oR3[6], oR2[3], r1 = 0.0;
+#pragma unroll
+  for (int c = 0; c < 3; ++c)
+#pragma unroll
+    for (int d = c; d < 3; ++d) {
+      double acc = 0.0;
+#pragma unroll
+      for (int a = 0; a < 3; ++a) acc = fma(om[a], (double)R3[s3(a, c, d)], acc);
+      oR3[i2(c, d)] = acc;
+    }
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    double acc = 0.0;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) acc = fma(om[a], (double)R2[s2(a, c)], acc);
+    oR2[c] = acc;
+  }
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    double s = 0.0;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) s += (double)R3[s3(a, c, c)];
+    r1 = fma(om[a], s, r1);
+  }
+  double zz = 0.0;
+#pragma unroll
+  for (int c = 0; c < 3; ++c)
+#pragma unroll
+    for (int d = c; d < 3; ++d) zz = fma((c == d ? 1.0 : 2.0) * z[c] * z[d], oR3[i2(c, d)], zz);
+  double zo2 = z[0] * oR2[0] + z[1] * oR2[1] + z[2] * oR2[2];
+  *val = k2 * zz + k1 * zo2 + k0 * r1;
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    double s = 0.0;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) s = fma(z[d], oR3[s2(c, d)], s);
+    gz[c] = 2.0 * k2 * s + k1 * oR2[c];
+  }
+}
+
+// <G', X(z)> and its z-gradient for one voxel record, with G' the (already
+// adjoint-shifted) 21-vector; X = camera-frame block without 1/sigma^2.
+template <typename T>
+__device__ inline void corner_vjp(const T* rec, const double Gp[21], const double z[3], double k2,
+                                  double k1, double k0, double* val, double gz[3]) {
+  double HTL[6], HBR[6], om[3];
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = i; j < 3; ++j) {
+      HTL[i2(i, j)] = Gp[u21(i, j)];
+      HBR[i2(i, j)] = Gp[u21(3 + i, 3 + j)];
+    }
+  // omega(TR) = (TR_21 - TR_12, TR_02 - TR_20, TR_10 - TR_01)
+  om[0] = Gp[u21(2, 4)] - Gp[u21(1, 5)];
+  om[1] = Gp[u21(0, 5)] - Gp[u21(2, 3)];
+  om[2] = Gp[u21(1, 3)] - Gp[u21(0, 4)];
+  double v2, v0, vb, g2[3], g0[3], gb[3];
+  group_vjp(rec + O_G2_4, rec + O_G2_3, HTL, z, k2, k1, k0, &v2, g2);
+  group_vjp(rec + O_G0_4, rec + O_G0_3, HBR, z, k2, k1, k0, &v0, g0);
+  group_b_vjp(rec + O_G1_3, rec + O_G1_2, om, z, k2, k1, k0, &vb, gb);
+  *val = v2 + v0 - 2.0 * vb;
+#pragma unroll
+  for (int c = 0; c < 3; ++c) gz[c] = g2[c] + g0[c] - 2.0 * gb[c];
+}
+
+// ------------------------------------------------------------ 6x6 metrics (FP64)
+
+#define FIF_A(i, j) a[su21((i), (j))]
+
+// Cyclic Jacobi on a symmetric 6x6 held as 21 values.  Sweeps until the
+// off-diagonal mass is below 1e-30 of the Frobenius mass (or 16 sweeps).
+// On return the diagonal of `a` holds the eigenvalues; when WANT_V the
+// columns of V (row-major 36) are the eigenvectors.
+template <bool WANT_V>
+__device__ inline void jacobi6(double a[21], double V[36]) {
+  if (WANT_V) {
+#pragma unroll
+    for (int i = 0; i < 36; ++i) V[i] = (i % 7 == 0) ? 1.0 : 0.0;
+  }
+  double fro = 0.0;
+#pragma unroll
+  for (int i = 0; i < 6; ++i)
+#pragma unroll
+    for (int j = i; j < 6; ++j) fro += (i == j ? 1.0 : 2.0) * FIF_A(i, j) * FIF_A(i, j);
+  for (int sweep = 0; sweep < 16; ++sweep) {
+    double off = 0.0;
+#pragma unroll
+    for (int i = 0; i < 6; ++i)
+#pragma unroll
+      for (int j = i + 1; j < 6; ++j) off += 2.0 * FIF_A(i, j) * FIF_A(i, j);
+    if (!(off > 1e-30 * fro)) break;
+#pragma unroll
+    for (int p = 0; p < 6; ++p)
+#pragma unroll
+      for (int q = p + 1; q < 6; ++q) {
+        double apq = FIF_A(p, q);
+        double app = FIF_A(p, p), aqq = FIF_A(q, q);
+        double theta = (aqq - app) / (2.0 * apq);
+        double at = fabs(theta);
+        double tt = (at > 1e150) ? 0.5 / at : 1.0 / (at + sqrt(fma(at, at, 1.0)));
+        tt = (theta < 0.0) ? -tt : tt;
+        bool skip = (apq == 0.0);
+        tt = skip ? 0.0 : tt;
+        double c = 1.0 / sqrt(fma(tt, tt, 1.0));
+        double s = tt * c;
+#pragma unroll
+        for (int k = 0; k < 6; ++k) {
+          if (k == p || k == q) continue;
+          double akp = FIF_A(k, p), akq = FIF_A(k, q);
+          FIF_A(k, p) = c * akp - s * akq;
+          FIF_A(k, q) = s * akp + c * akq;
+        }
+        FIF_A(p, p) = app - tt * apq;
+        FIF_A(q, q) = aqq + tt * apq;
+        FIF_A(p, q) = skip ? apq : 0.0;
+        if (WANT_V) {
+#pragma unroll
+          for (int k = 0; k < 6; ++k) {
+            double vkp = V[k * 6 + p], vkq = V[k * 6 + q];
+            V[k * 6 + p] = c * vkp - s * vkq;
+            V[k * 6 + q] = s * vkp + c * vkq;
+          }
+        }
+      }
+  }
+}
+
+// LDL^T of a symmetric 6x6 (21 values) in place.  Returns false when a pivot
+// is not positive (not PD).  logdet = sum log d_i.
+__device__ inline bool ldlt6(const double F[21], double L[36], double dinv[6], double* logdet) {
+  double d[6];
+  bool pd = true;
+#pragma unroll
+  for (int j = 0; j < 6; ++j) {
+    double s = F[u21(j, j)];
+#pragma unroll
+    for (int k = 0; k < j; ++k) s -= L[j * 6 + k] * L[j * 6 + k] * d[k];
+    d[j] = s;
+    pd = pd && (s > 0.0);
+    double inv = 1.0 / s;
+    dinv[j] = inv;
+#pragma unroll
+    for (int i = j + 1; i < 6; ++i) {
+      double r = F[u21(j, i)];
+#pragma unroll
+      for (int k = 0; k < j; ++k) r -= L[i * 6 + k] * L[j * 6 + k] * d[k];
+      L[i * 6 + j] = r * inv;
+    }
+  }
+  double prod = d[0] * d[1] * d[2];
+  double prod2 = d[3] * d[4] * d[5];
+  *logdet = pd ? (log(prod) + log(prod2)) : __builtin_nan("");
+  return pd;
+}
+
+// F^-1 (21) from the LDL^T factors.
+__device__ inline void ldlt6_inverse(const double L[36], const double dinv[6], double out[21]) {
+  // X = L^-T D^-1 L^-1; compute W = L^-1 (unit lower), then X = W^T D^-1 W
+  double W[36];
+#pragma unroll
+  for (int c = 0; c < 6; ++c)
+#pragma unroll
+    for (int i = 0; i < 6; ++i) {
+      double s = (i == c) ? 1.0 : 0.0;
+#pragma unroll
+      for (int k = 0; k < i; ++k)
+        if (k >= c) s -= L[i * 6 + k] * W[k * 6 + c];
+      W[i * 6 + c] = (i < c) ? 0.0 : s;
+    }
+#pragma unroll
+  for (int i = 0; i < 6; ++i)
+#pragma unroll
+    for (int j = i; j < 6; ++j) {
+      double s = 0.0;
+#pragma unroll
+      for (int k = 0; k < 6; ++k)
+        if (k >= i && k >= j) s = fma(W[k * 6 + i] * dinv[k], W[k * 6 + j], s);
+      out[u21(i, j)] = s;
+    }
+}
+
+}  // namespace fif

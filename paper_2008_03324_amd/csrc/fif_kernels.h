@@ -1,0 +1,75 @@
+// Kernel argument blocks and launchers shared by the kernel files and the
+// C-ABI layer.  Host code only sees these declarations.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "fif_device.h"
+
+namespace fif {
+
+struct BuildArgs {
+  const double* lm;  // [L][3]
+  int64_t L;
+  GridDev g;
+  float lo2, hi2;  // FP32 range bounds on n^2
+  void* out;       // field records
+  int32_t accumulate;  // 0: overwrite, 1: out += sign * contribution
+  int32_t sign;
+};
+
+struct VisDev {
+  double k2, k1, k0;  // quadratic visibility coefficients
+  double inv_s2;      // 1 / sigma^2
+};
+
+struct QueryArgs {
+  const void* field;
+  GridDev g;
+  VisDev vis;
+  const void* t;  // [m][3] float or double
+  const void* q;  // [m][4]
+  int64_t m;
+  uint32_t metrics;
+  int32_t ncols;
+  int32_t interp;
+  double* out;
+  uint8_t* flags;
+  // gradient
+  const double* dL_dout;
+  void* dL_dt;
+  void* dL_dphi;
+};
+
+struct PcArgs {
+  const double* lm;
+  int64_t L;
+  float lo2, hi2;
+  VisDev vis;
+  int32_t exact;
+  double fx, fy, cx, cy;
+  double width, height;
+  const void* t;
+  const void* q;
+  int64_t m;
+  uint32_t metrics;
+  int32_t ncols;
+  double* out;
+};
+
+struct ExportArgs {
+  const void* field;
+  GridDev g;
+  double inv_s2;
+  const int64_t* ids;
+  int64_t n;
+  double* out;
+};
+
+hipError_t launch_build(const BuildArgs& a, int prec, int kind, hipStream_t stream);
+hipError_t launch_query(const QueryArgs& a, int prec, int kind, bool grad, hipStream_t stream);
+hipError_t launch_pc(const PcArgs& a, int prec, hipStream_t stream);
+hipError_t launch_export(const ExportArgs& a, int prec, int kind, hipStream_t stream);
+
+}  // namespace fif

@@ -1,0 +1,96 @@
+// Information metrics s(F) of eq:cost_info (trace, smallest eigenvalue,
+// log-determinant) on a symmetric 6x6 FIM held as 21 FP64 values, and their
+// gradients dS/dF for the backward pass.
+#pragma once
+
+#include "fif_device.h"
+
+namespace fif {
+
+constexpr uint32_t M_TRACE = 1u, M_LMIN = 2u, M_LOGDET = 4u, M_FIM = 8u;
+constexpr uint8_t FL_CLAMPED = 1u, FL_NOT_PD = 2u, FL_TIE = 4u;
+
+// Writes the requested columns to `row` (when non-null), sets flag bits, and
+// when GRAD accumulates G = sum_c up[c] d s_c / dF (21, symmetric).
+template <bool GRAD>
+__device__ inline void eval_metrics(const double F[21], uint32_t metrics, double* row,
+                                    uint8_t* flag, const double* up, double G[21]) {
+  int col = 0, upc = 0;
+  if (GRAD) {
+#pragma unroll
+    for (int e = 0; e < 21; ++e) G[e] = 0.0;
+  }
+  if (metrics & M_TRACE) {
+    double tr = F[u21(0, 0)] + F[u21(1, 1)] + F[u21(2, 2)] + F[u21(3, 3)] + F[u21(4, 4)] +
+                F[u21(5, 5)];
+    if (row) row[col] = tr;
+    ++col;
+    if (GRAD) {
+      double g = up[upc++];
+#pragma unroll
+      for (int i = 0; i < 6; ++i) G[u21(i, i)] += g;
+    }
+  }
+  if (metrics & M_LMIN) {
+    double a[21];
+#pragma unroll
+    for (int e = 0; e < 21; ++e) a[e] = F[e];
+    double V[GRAD ? 36 : 1];
+    jacobi6<GRAD>(a, V);
+    double ev[6];
+#pragma unroll
+    for (int i = 0; i < 6; ++i) ev[i] = a[u21(i, i)];
+    double lmin = ev[0], amax = fabs(ev[0]);
+    int imin = 0;
+#pragma unroll
+    for (int i = 1; i < 6; ++i) {
+      bool lt = ev[i] < lmin;
+      lmin = lt ? ev[i] : lmin;
+      imin = lt ? i : imin;
+      amax = fmax(amax, fabs(ev[i]));
+    }
+    double second = __builtin_inf();
+#pragma unroll
+    for (int i = 0; i < 6; ++i) second = (i != imin) ? fmin(second, ev[i]) : second;
+    if (second - lmin <= 1e-8 * amax) *flag |= FL_TIE;
+    if (row) row[col] = lmin;
+    ++col;
+    if (GRAD) {
+      double g = up[upc++];
+      double v[6];
+#pragma unroll
+      for (int r = 0; r < 6; ++r) {
+        double s = V[r * 6 + 0];
+#pragma unroll
+        for (int c = 1; c < 6; ++c) s = (imin == c) ? V[r * 6 + c] : s;
+        v[r] = s;
+      }
+#pragma unroll
+      for (int i = 0; i < 6; ++i)
+#pragma unroll
+        for (int j = i; j < 6; ++j) G[u21(i, j)] = fma(g * v[i], v[j], G[u21(i, j)]);
+    }
+  }
+  {
+    double L[36], dinv[6], ld;
+    bool pd = ldlt6(F, L, dinv, &ld);
+    if (!pd) *flag |= FL_NOT_PD;
+    if (metrics & M_LOGDET) {
+      if (row) row[col] = ld;
+      ++col;
+      if (GRAD) {
+        double g = up[upc++];
+        double inv[21];
+        ldlt6_inverse(L, dinv, inv);
+#pragma unroll
+        for (int e = 0; e < 21; ++e) G[e] = pd ? fma(g, inv[e], G[e]) : __builtin_nan("");
+      }
+    }
+  }
+  if ((metrics & M_FIM) && row) {
+#pragma unroll
+    for (int e = 0; e < 21; ++e) row[col + e] = F[e];
+  }
+}
+
+}  // namespace fif

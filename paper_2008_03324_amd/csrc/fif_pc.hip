@@ -1,0 +1,160 @@
+// Point-cloud brute force (eq:cost_info, eq:vis_fim): for each pose, the sum
+// of v_i I_i over every landmark in range.  One lane per pose; landmarks are
+// staged through LDS in batches of 256 and read back as broadcasts.
+//
+// The sum is accumulated about the camera position t, where a landmark's FIM
+// has the form (1/sigma^2) [[P/n^2, -[u]x/n], [[u]x/n, P]] (P = I - u u^T), so
+// 15 running sums suffice: sum v u u^T, sum v u u^T / n^2, sum v u / n.  One
+// shift to the world origin at the end gives eq:jac_pose_global's frame.
+#include "fif_kernels.h"
+#include "fif_metrics.h"
+
+namespace fif {
+
+constexpr int kPcThreads = 256;
+constexpr int kPcBatch = 256;
+
+__device__ inline void pc_two_sum(float& hi, float& lo, float x) {
+  float s = hi + x;
+  float bb = s - hi;
+  float err = (hi - (s - bb)) + (x - bb);
+  hi = s;
+  lo += err;
+}
+
+template <int PREC, bool EXACT>
+__global__ __launch_bounds__(kPcThreads) void pc_kernel(PcArgs a) {
+  using T = typename std::conditional<PREC == 2, double, float>::type;
+  using L4 = typename std::conditional<PREC == 2, double4, float4>::type;
+  constexpr bool COMP = (PREC == 1);
+  __shared__ L4 s_lm[kPcBatch];
+
+  const int tid = threadIdx.x;
+  const int64_t qi = (int64_t)blockIdx.x * kPcThreads + tid;
+  const bool valid = qi < a.m;
+  const int64_t ql = valid ? qi : a.m - 1;
+
+  const T* TT = reinterpret_cast<const T*>(a.t);
+  const T* QQ = reinterpret_cast<const T*>(a.q);
+  const double t[3] = {(double)TT[3 * ql], (double)TT[3 * ql + 1], (double)TT[3 * ql + 2]};
+  const double qw = QQ[4 * ql], qx = QQ[4 * ql + 1], qy = QQ[4 * ql + 2], qz = QQ[4 * ql + 3];
+  double Rd[9];
+  quat_R(qw, qx, qy, qz, Rd);
+  T R[9];
+#pragma unroll
+  for (int e = 0; e < 9; ++e) R[e] = (T)Rd[e];
+  const T zx = R[2], zy = R[5], zz = R[8];
+  const float ftx = (float)t[0], fty = (float)t[1], ftz = (float)t[2];
+  const T tx = (T)t[0], ty = (T)t[1], tz = (T)t[2];
+  const T k2 = (T)a.vis.k2, k1 = (T)a.vis.k1, k0 = (T)a.vis.k0;
+  const T fx = (T)a.fx, fy = (T)a.fy, cx = (T)a.cx, cy = (T)a.cy;
+  const T W = (T)a.width, H = (T)a.height;
+
+  T acc[15];  // Q0 (6), Q2 (6), B1 (3)
+  float hi[COMP ? 15 : 1], lo[COMP ? 15 : 1];
+#pragma unroll
+  for (int e = 0; e < 15; ++e) acc[e] = T(0);
+  if (COMP) {
+#pragma unroll
+    for (int e = 0; e < 15; ++e) { hi[e] = 0.f; lo[e] = 0.f; }
+  }
+
+  for (int64_t base = 0; base < a.L; base += kPcBatch) {
+    const int nb = (int)((a.L - base) < kPcBatch ? (a.L - base) : kPcBatch);
+    __syncthreads();
+    if (tid < nb) {
+      const double* p = a.lm + 3 * (base + tid);
+      L4 v;
+      v.x = (T)p[0]; v.y = (T)p[1]; v.z = (T)p[2]; v.w = T(0);
+      s_lm[tid] = v;
+    }
+    __syncthreads();
+    for (int i = 0; i < nb; ++i) {
+      const L4 p = s_lm[i];
+      float ddx = (float)p.x - ftx, ddy = (float)p.y - fty, ddz = (float)p.z - ftz;
+      float n2 = __fmaf_rn(ddz, ddz, __fmaf_rn(ddy, ddy, ddx * ddx));
+      bool in = valid && (n2 >= a.lo2) && (n2 <= a.hi2);
+      T dx = p.x - tx, dy = p.y - ty, dz = p.z - tz;
+      T w = T(0);
+      if (EXACT) {
+        T pcx = R[0] * dx + R[3] * dy + R[6] * dz;
+        T pcy = R[1] * dx + R[4] * dy + R[7] * dz;
+        T pcz = R[2] * dx + R[5] * dy + R[8] * dz;
+        T u = fx * pcx / pcz + cx;
+        T v = fy * pcy / pcz + cy;
+        bool vis = (pcz > T(0)) && (u >= T(0)) && (u < W) && (v >= T(0)) && (v < H);
+        in = in && vis;
+        w = T(1);
+      }
+      if (in) {
+        T nn = (PREC == 2) ? (T)fma((double)dz, (double)dz, fma((double)dy, (double)dy, (double)dx * dx))
+                           : (T)n2;
+        T rn = (PREC == 2) ? (T)(1.0 / sqrt((double)nn)) : (T)rsqrtf((float)nn);
+        T ux = dx * rn, uy = dy * rn, uz = dz * rn;
+        if (!EXACT) {
+          T c = zx * ux + zy * uy + zz * uz;
+          w = fma(fma(k2, c, k1), c, k0);
+        }
+        T rn2 = rn * rn;
+        T wn = w * rn, wn2 = w * rn2;
+        T m2[6] = {ux * ux, ux * uy, ux * uz, uy * uy, uy * uz, uz * uz};
+#pragma unroll
+        for (int e = 0; e < 6; ++e) {
+          acc[e] = fma(w, m2[e], acc[e]);
+          acc[6 + e] = fma(wn2, m2[e], acc[6 + e]);
+        }
+        acc[12] = fma(wn, ux, acc[12]);
+        acc[13] = fma(wn, uy, acc[13]);
+        acc[14] = fma(wn, uz, acc[14]);
+      }
+    }
+    if (COMP) {
+#pragma unroll
+      for (int e = 0; e < 15; ++e) {
+        pc_two_sum(hi[e], lo[e], (float)acc[e]);
+        acc[e] = T(0);
+      }
+    }
+  }
+  if (!valid) return;
+  double s[15];
+#pragma unroll
+  for (int e = 0; e < 15; ++e) s[e] = COMP ? (double)hi[e] + (double)lo[e] : (double)acc[e];
+  double A[6], D[6], B[9];
+  const double tr0 = s[0] + s[3] + s[5], tr2 = s[6] + s[9] + s[11];
+#pragma unroll
+  for (int e = 0; e < 6; ++e) {
+    const bool diag = (e == 0 || e == 3 || e == 5);
+    D[e] = (diag ? tr0 : 0.0) - s[e];
+    A[e] = (diag ? tr2 : 0.0) - s[6 + e];
+  }
+  const double b0 = s[12], b1 = s[13], b2 = s[14];
+  B[0] = 0.0; B[1] = b2;  B[2] = -b1;
+  B[3] = -b2; B[4] = 0.0; B[5] = b0;
+  B[6] = b1;  B[7] = -b0; B[8] = 0.0;
+  double F[21];
+  shift_frame(A, B, D, t, F);
+#pragma unroll
+  for (int e = 0; e < 21; ++e) F[e] *= a.vis.inv_s2;
+  uint8_t flag = 0;
+  eval_metrics<false>(F, a.metrics, a.out + qi * a.ncols, &flag, nullptr, nullptr);
+}
+
+hipError_t launch_pc(const PcArgs& a, int prec, hipStream_t stream) {
+  if (a.m <= 0) return hipSuccess;
+  dim3 grid((unsigned)((a.m + kPcThreads - 1) / kPcThreads)), block(kPcThreads);
+#define FIF_PC(P, E) hipLaunchKernelGGL((pc_kernel<P, E>), grid, block, 0, stream, a)
+  if (a.exact) {
+    if (prec == 0) FIF_PC(0, true);
+    else if (prec == 1) FIF_PC(1, true);
+    else FIF_PC(2, true);
+  } else {
+    if (prec == 0) FIF_PC(0, false);
+    else if (prec == 1) FIF_PC(1, false);
+    else FIF_PC(2, false);
+  }
+#undef FIF_PC
+  return hipGetLastError();
+}
+
+}  // namespace fif

@@ -1,0 +1,401 @@
+// Batched pose queries, their fused backward, and the export of the paper's
+// factor blocks (Sec. VI-A, eq:fim_separation).
+//
+// Information field, trilinear: a wave serves 64 queries.  Lanes are grouped
+// by 8; in pass `it` group g serves query 8g + it and lane j of the group
+// gathers trilinear corner j (a 272-B record for FP32 fields), contracts its
+// moments with the optical axis into the voxel's 6x6 block, moves it to the
+// query position (the blocks are taken about different voxel centres, so
+// each corner is shifted before the weighted sum), and the 8 partial sums
+// are reduced with cross-lane shuffles.  After 8 passes every lane holds the
+// FIM of its own query and evaluates the FP64 metrics, so no lane idles in the
+// eigen-solve.  The fused backward repeats the corner gathers with the metric
+// gradient broadcast to the group.
+#include "fif_kernels.h"
+#include "fif_metrics.h"
+
+namespace fif {
+
+constexpr int kQThreads = 256;
+
+template <typename FT>
+__device__ inline void load_record(const FT* field, size_t vox, FT rec[kRec]);
+
+template <>
+__device__ inline void load_record<float>(const float* field, size_t vox, float rec[kRec]) {
+  const float4* p = reinterpret_cast<const float4*>(field + vox * kRec);
+#pragma unroll
+  for (int i = 0; i < kRec / 4; ++i) {
+    float4 v = p[i];
+    rec[4 * i] = v.x; rec[4 * i + 1] = v.y; rec[4 * i + 2] = v.z; rec[4 * i + 3] = v.w;
+  }
+}
+
+template <>
+__device__ inline void load_record<double>(const double* field, size_t vox, double rec[kRec]) {
+  const double2* p = reinterpret_cast<const double2*>(field + vox * kRec);
+#pragma unroll
+  for (int i = 0; i < kRec / 2; ++i) {
+    double2 v = p[i];
+    rec[2 * i] = v.x; rec[2 * i + 1] = v.y;
+  }
+}
+
+struct Corner {
+  size_t vox;
+  double w;
+  double dw[3];
+  double dl[3];  // voxel centre - query position
+  bool clamped;
+  bool active;
+};
+
+// Corner j (bits x, y, z) of the cell holding t, or the nearest voxel for j = 0.
+__device__ inline Corner make_corner(const GridDev& g, const double t[3], int j, int interp) {
+  Corner c;
+  const double o[3] = {g.ox, g.oy, g.oz};
+  const int32_t n[3] = {g.nx, g.ny, g.nz};
+  int32_t idx[3];
+  if (interp == 1) {
+    bool cl[3];
+#pragma unroll
+    for (int ax = 0; ax < 3; ++ax) idx[ax] = axis_nearest(t[ax], o[ax], g.h, n[ax], &cl[ax]);
+    c.clamped = cl[0] || cl[1] || cl[2];
+    c.active = (j == 0);
+    // NaN positions must give NaN results
+    double nanp = (t[0] - t[0]) + (t[1] - t[1]) + (t[2] - t[2]);
+    c.w = c.active ? 1.0 + nanp : 0.0;
+    c.dw[0] = c.dw[1] = c.dw[2] = 0.0;
+  } else {
+    double wc[3], dwc[3];
+    c.clamped = false;
+#pragma unroll
+    for (int ax = 0; ax < 3; ++ax) {
+      AxisCell ac = axis_cell(t[ax], o[ax], g.h, n[ax]);
+      int b = (j >> ax) & 1;
+      idx[ax] = ac.i0 + b * ac.step;
+      wc[ax] = b ? ac.f : 1.0 - ac.f;
+      dwc[ax] = b ? ac.df : -ac.df;
+      c.clamped = c.clamped || ac.clamped;
+    }
+    c.active = true;
+    c.w = wc[0] * wc[1] * wc[2];
+    c.dw[0] = dwc[0] * wc[1] * wc[2];
+    c.dw[1] = wc[0] * dwc[1] * wc[2];
+    c.dw[2] = wc[0] * wc[1] * dwc[2];
+  }
+  c.vox = (size_t)idx[0] + (size_t)g.nx * ((size_t)idx[1] + (size_t)g.ny * (size_t)idx[2]);
+#pragma unroll
+  for (int ax = 0; ax < 3; ++ax) c.dl[ax] = (o[ax] + (double)idx[ax] * g.h) - t[ax];
+  return c;
+}
+
+template <typename PT>
+__device__ inline void load_pose(const QueryArgs& a, int64_t i, double t[3], double z[3]) {
+  const PT* T = reinterpret_cast<const PT*>(a.t);
+  const PT* Q = reinterpret_cast<const PT*>(a.q);
+  t[0] = (double)T[3 * i]; t[1] = (double)T[3 * i + 1]; t[2] = (double)T[3 * i + 2];
+  quat_axis((double)Q[4 * i], (double)Q[4 * i + 1], (double)Q[4 * i + 2], (double)Q[4 * i + 3], z);
+}
+
+template <typename FT, bool GRAD>
+__global__ __launch_bounds__(kQThreads) void query_info_kernel(QueryArgs a) {
+  const int lane = threadIdx.x & 63;
+  const int grp = lane >> 3, j = lane & 7;
+  const int64_t wbase = ((int64_t)blockIdx.x * (kQThreads / 64) + (threadIdx.x >> 6)) * 64;
+  const FT* field = reinterpret_cast<const FT*>(a.field);
+  const double k2 = a.vis.k2, k1 = a.vis.k1, k0 = a.vis.k0;
+
+  double Z[21];
+  bool clamped = false;
+#pragma unroll
+  for (int e = 0; e < 21; ++e) Z[e] = 0.0;
+
+  for (int it = 0; it < 8; ++it) {
+    int64_t qi = wbase + grp * 8 + it;
+    qi = qi < a.m ? qi : a.m - 1;
+    double t[3], z[3];
+    load_pose<FT>(a, qi, t, z);
+    Corner c = make_corner(a.g, t, j, a.interp);
+    double Y[21];
+    if (c.active) {
+      FT rec[kRec];
+      load_record<FT>(field, c.vox, rec);
+      corner_fim<FT>(rec, z, k2, k1, k0, c.dl, Y);
+#pragma unroll
+      for (int e = 0; e < 21; ++e) Y[e] *= c.w;
+    } else {
+#pragma unroll
+      for (int e = 0; e < 21; ++e) Y[e] = 0.0;
+    }
+#pragma unroll
+    for (int e = 0; e < 21; ++e) {
+      Y[e] += __shfl_xor(Y[e], 1, 8);
+      Y[e] += __shfl_xor(Y[e], 2, 8);
+      Y[e] += __shfl_xor(Y[e], 4, 8);
+    }
+    if (j == it) {
+#pragma unroll
+      for (int e = 0; e < 21; ++e) Z[e] = Y[e];
+      clamped = c.clamped;
+    }
+  }
+
+  const int64_t qown = wbase + lane;
+  const bool valid = qown < a.m;
+  const int64_t ql = valid ? qown : a.m - 1;
+  double t[3], z[3];
+  load_pose<FT>(a, ql, t, z);
+  double F[21];
+  shift21(Z, t, F);
+#pragma unroll
+  for (int e = 0; e < 21; ++e) F[e] *= a.vis.inv_s2;
+
+  uint8_t flag = clamped ? FL_CLAMPED : 0;
+  double G[GRAD ? 21 : 1];
+  int nmet = (int)((a.metrics & 1u) != 0) + (int)((a.metrics & 2u) != 0) +
+             (int)((a.metrics & 4u) != 0);
+  double up[3] = {0.0, 0.0, 0.0};
+  if (GRAD) {
+    for (int c = 0; c < nmet; ++c) up[c] = valid ? a.dL_dout[ql * nmet + c] : 0.0;
+  }
+  double* row = (valid && a.out) ? a.out + ql * a.ncols : nullptr;
+  eval_metrics<GRAD>(F, a.metrics, row, &flag, up, G);
+  if (valid && a.flags) a.flags[ql] = flag;
+  if (!GRAD) return;
+
+  // ------------------------------------------------------------ backward
+  double Gt[21];
+  if (GRAD) {
+    shift21_adj(G, t, Gt);
+#pragma unroll
+    for (int e = 0; e < 21; ++e) Gt[e] = valid ? Gt[e] * a.vis.inv_s2 : 0.0;
+  }
+  double keep[6] = {0, 0, 0, 0, 0, 0};
+  for (int it = 0; it < 8; ++it) {
+    const int src = (lane & ~7) | it;
+    double Gb[21];
+#pragma unroll
+    for (int e = 0; e < 21; ++e) Gb[e] = __shfl(Gt[e], src, 64);
+    int64_t qi = wbase + grp * 8 + it;
+    qi = qi < a.m ? qi : a.m - 1;
+    double tq[3], zq[3];
+    load_pose<FT>(a, qi, tq, zq);
+    Corner c = make_corner(a.g, tq, j, 0);
+    FT rec[kRec];
+    load_record<FT>(field, c.vox, rec);
+    double Gp[21];
+    shift21_adj(Gb, c.dl, Gp);
+    double val, gz[3];
+    corner_vjp<FT>(rec, Gp, zq, k2, k1, k0, &val, gz);
+    double r[6] = {c.dw[0] * val, c.dw[1] * val, c.dw[2] * val,
+                   c.w * gz[0], c.w * gz[1], c.w * gz[2]};
+#pragma unroll
+    for (int e = 0; e < 6; ++e) {
+      r[e] += __shfl_xor(r[e], 1, 8);
+      r[e] += __shfl_xor(r[e], 2, 8);
+      r[e] += __shfl_xor(r[e], 4, 8);
+    }
+    if (j == it) {
+#pragma unroll
+      for (int e = 0; e < 6; ++e) keep[e] = r[e];
+    }
+  }
+  if (!valid) return;
+  double gphi[3] = {z[1] * keep[5] - z[2] * keep[4], z[2] * keep[3] - z[0] * keep[5],
+                    z[0] * keep[4] - z[1] * keep[3]};
+  FT* gt_out = reinterpret_cast<FT*>(a.dL_dt);
+  FT* gp_out = reinterpret_cast<FT*>(a.dL_dphi);
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    gt_out[3 * ql + c] = (FT)keep[c];
+    gp_out[3 * ql + c] = (FT)gphi[c];
+  }
+}
+
+// Trace field (eq:general_trace_pif): one lane per query, 8 gathers of 48 B.
+template <typename FT>
+__global__ __launch_bounds__(kQThreads) void query_trace_kernel(QueryArgs a) {
+  const int64_t qi = (int64_t)blockIdx.x * kQThreads + threadIdx.x;
+  if (qi >= a.m) return;
+  const FT* field = reinterpret_cast<const FT*>(a.field);
+  double t[3], z[3];
+  load_pose<FT>(a, qi, t, z);
+  const double k2 = a.vis.k2, k1 = a.vis.k1, k0 = a.vis.k0;
+  const double vr[10] = {k2 * z[0] * z[0],       k2 * z[1] * z[1],       k2 * z[2] * z[2],
+                         2.0 * k2 * z[0] * z[1], 2.0 * k2 * z[0] * z[2], 2.0 * k2 * z[1] * z[2],
+                         k1 * z[0],              k1 * z[1],              k1 * z[2],
+                         k0};
+  double cbar[10];
+#pragma unroll
+  for (int k = 0; k < 10; ++k) cbar[k] = 0.0;
+  bool clamped = false;
+  const int ncorner = (a.interp == 1) ? 1 : 8;
+  for (int j = 0; j < ncorner; ++j) {
+    Corner c = make_corner(a.g, t, j, a.interp);
+    clamped = clamped || c.clamped;
+    const FT* r = field + c.vox * kTRec;
+#pragma unroll
+    for (int k = 0; k < 10; ++k) cbar[k] = fma(c.w, (double)r[k], cbar[k]);
+  }
+  double tr = 0.0;
+#pragma unroll
+  for (int k = 0; k < 10; ++k) tr = fma(vr[k], cbar[k], tr);
+  a.out[qi * a.ncols] = tr * a.vis.inv_s2;
+  if (a.flags) a.flags[qi] = clamped ? FL_CLAMPED : 0;
+}
+
+// ------------------------------------------------------------ export
+
+// Expand a moment group to all degrees: S2 (6), S1 (3), S0 from S4, S3.
+template <typename FT>
+__device__ inline void expand_group(const FT* S4, const FT* S3, double E4[15], double E3[10],
+                                    double E2[6], double E1[3], double* E0) {
+#pragma unroll
+  for (int i = 0; i < 15; ++i) E4[i] = (double)S4[i];
+#pragma unroll
+  for (int i = 0; i < 10; ++i) E3[i] = (double)S3[i];
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+#pragma unroll
+    for (int b = a; b < 3; ++b) E2[i2(a, b)] = E4[s4(a, b, 0, 0)] + E4[s4(a, b, 1, 1)] + E4[s4(a, b, 2, 2)];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) E1[a] = E3[s3(a, 0, 0)] + E3[s3(a, 1, 1)] + E3[s3(a, 2, 2)];
+  *E0 = E2[0] + E2[3] + E2[5];
+}
+
+// Paper's vp order: u1^2, u2^2, u3^2, u1u2, u1u3, u2u3, u1, u2, u3, 1.
+__device__ constexpr int vp_a(int k) {
+  return k < 3 ? k : (k == 3 ? 0 : (k == 4 ? 0 : (k == 5 ? 1 : k - 6)));
+}
+__device__ constexpr int vp_b(int k) { return k < 3 ? k : (k == 3 ? 1 : (k == 4 ? 2 : 2)); }
+
+template <typename FT>
+__global__ void export_info_kernel(ExportArgs a) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= a.n) return;
+  const int64_t v = a.ids[i];
+  const int64_t nvox = (int64_t)a.g.nx * a.g.ny * a.g.nz;
+  if (v < 0 || v >= nvox) {  // ids live on the device: reject out-of-grid ones here
+    for (int e = 0; e < 210; ++e) a.out[i * 210 + e] = __builtin_nan("");
+    return;
+  }
+  const int64_t ix = v % a.g.nx, iy = (v / a.g.nx) % a.g.ny, iz = v / ((int64_t)a.g.nx * a.g.ny);
+  const double tv[3] = {a.g.ox + (double)ix * a.g.h, a.g.oy + (double)iy * a.g.h,
+                        a.g.oz + (double)iz * a.g.h};
+  const FT* rec = reinterpret_cast<const FT*>(a.field) + (size_t)v * kRec;
+  double S4[15], S3[10], S2[6], S1[3], S0;   // G0
+  double T4[15], T3[10], T2[6], T1[3], T0;   // G2
+  expand_group<FT>(rec + O_G0_4, rec + O_G0_3, S4, S3, S2, S1, &S0);
+  expand_group<FT>(rec + O_G2_4, rec + O_G2_3, T4, T3, T2, T1, &T0);
+  double R3[10], R2[6], R1[3];
+#pragma unroll
+  for (int e = 0; e < 10; ++e) R3[e] = (double)rec[O_G1_3 + e];
+#pragma unroll
+  for (int e = 0; e < 6; ++e) R2[e] = (double)rec[O_G1_2 + e];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) R1[c] = R3[s3(c, 0, 0)] + R3[s3(c, 1, 1)] + R3[s3(c, 2, 2)];
+  double* out = a.out + i * 210;
+#pragma unroll
+  for (int k = 0; k < 10; ++k) {
+    double sv0, sv2, Q0[6], Q2[6], bv[3];
+    const int pa = vp_a(k), pb = vp_b(k);
+    if (k < 6) {
+      sv0 = S2[s2(pa, pb)];
+      sv2 = T2[s2(pa, pb)];
+#pragma unroll
+      for (int c = 0; c < 3; ++c)
+#pragma unroll
+        for (int d = c; d < 3; ++d) {
+          Q0[i2(c, d)] = S4[s4(pa, pb, c, d)];
+          Q2[i2(c, d)] = T4[s4(pa, pb, c, d)];
+        }
+#pragma unroll
+      for (int c = 0; c < 3; ++c) bv[c] = R3[s3(pa, pb, c)];
+    } else if (k < 9) {
+      sv0 = S1[pa];
+      sv2 = T1[pa];
+#pragma unroll
+      for (int c = 0; c < 3; ++c)
+#pragma unroll
+        for (int d = c; d < 3; ++d) {
+          Q0[i2(c, d)] = S3[s3(pa, c, d)];
+          Q2[i2(c, d)] = T3[s3(pa, c, d)];
+        }
+#pragma unroll
+      for (int c = 0; c < 3; ++c) bv[c] = R2[s2(pa, c)];
+    } else {
+      sv0 = S0;
+      sv2 = T0;
+#pragma unroll
+      for (int e = 0; e < 6; ++e) { Q0[e] = S2[e]; Q2[e] = T2[e]; }
+#pragma unroll
+      for (int c = 0; c < 3; ++c) bv[c] = R1[c];
+    }
+    double A[6], D[6], B[9];
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+#pragma unroll
+      for (int d = c; d < 3; ++d) {
+        A[i2(c, d)] = (c == d ? sv2 : 0.0) - Q2[i2(c, d)];
+        D[i2(c, d)] = (c == d ? sv0 : 0.0) - Q0[i2(c, d)];
+      }
+    B[0] = 0.0;    B[1] = bv[2];  B[2] = -bv[1];
+    B[3] = -bv[2]; B[4] = 0.0;    B[5] = bv[0];
+    B[6] = bv[1];  B[7] = -bv[0]; B[8] = 0.0;
+    double W[21];
+    shift_frame(A, B, D, tv, W);
+#pragma unroll
+    for (int e = 0; e < 21; ++e) out[k * 21 + e] = W[e] * a.inv_s2;
+  }
+}
+
+template <typename FT>
+__global__ void export_trace_kernel(ExportArgs a) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= a.n) return;
+  const int64_t v = a.ids[i];
+  if (v < 0 || v >= (int64_t)a.g.nx * a.g.ny * a.g.nz) {
+    for (int k = 0; k < 10; ++k) a.out[i * 10 + k] = __builtin_nan("");
+    return;
+  }
+  const FT* rec = reinterpret_cast<const FT*>(a.field) + (size_t)v * kTRec;
+#pragma unroll
+  for (int k = 0; k < 10; ++k) a.out[i * 10 + k] = (double)rec[k] * a.inv_s2;
+}
+
+hipError_t launch_query(const QueryArgs& a, int prec, int kind, bool grad, hipStream_t stream) {
+  if (a.m <= 0) return hipSuccess;
+  const bool dbl = (prec == 2);
+  if (kind == 0) {
+    dim3 grid((unsigned)((a.m + kQThreads - 1) / kQThreads));
+    if (grad) {
+      if (dbl) hipLaunchKernelGGL((query_info_kernel<double, true>), grid, dim3(kQThreads), 0, stream, a);
+      else hipLaunchKernelGGL((query_info_kernel<float, true>), grid, dim3(kQThreads), 0, stream, a);
+    } else {
+      if (dbl) hipLaunchKernelGGL((query_info_kernel<double, false>), grid, dim3(kQThreads), 0, stream, a);
+      else hipLaunchKernelGGL((query_info_kernel<float, false>), grid, dim3(kQThreads), 0, stream, a);
+    }
+  } else {
+    dim3 grid((unsigned)((a.m + kQThreads - 1) / kQThreads));
+    if (dbl) hipLaunchKernelGGL((query_trace_kernel<double>), grid, dim3(kQThreads), 0, stream, a);
+    else hipLaunchKernelGGL((query_trace_kernel<float>), grid, dim3(kQThreads), 0, stream, a);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_export(const ExportArgs& a, int prec, int kind, hipStream_t stream) {
+  if (a.n <= 0) return hipSuccess;
+  dim3 grid((unsigned)((a.n + 127) / 128)), block(128);
+  const bool dbl = (prec == 2);
+  if (kind == 0) {
+    if (dbl) hipLaunchKernelGGL((export_info_kernel<double>), grid, block, 0, stream, a);
+    else hipLaunchKernelGGL((export_info_kernel<float>), grid, block, 0, stream, a);
+  } else {
+    if (dbl) hipLaunchKernelGGL((export_trace_kernel<double>), grid, block, 0, stream, a);
+    else hipLaunchKernelGGL((export_trace_kernel<float>), grid, block, 0, stream, a);
+  }
+  return hipGetLastError();
+}
+
+}  // namespace fif

@@ -1,0 +1,113 @@
+"""The C-ABI library loads and exports every symbol of include/fif.h (CPU only).
+
+Only calls that return before touching the GPU are made: sizes, status strings
+and host-side argument validation.
+"""
+import ctypes
+import math
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "fif.h")
+
+
+def _lib():
+    import paper_2008_03324_amd as fif
+    if not os.path.exists(fif.LIB_PATH):
+        from paper_2008_03324_amd import buildlib
+        buildlib.build()
+    return fif, fif.lib()
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    names = re.findall(r"^\s*(?:const\s+)?[A-Za-z_][A-Za-z0-9_]*\s*\*?\s*([a-z_][a-z0-9_]*)\s*\(",
+                       text, flags=re.M)
+    return sorted(set(n for n in names if n.startswith(("fif_", "pc_"))))
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for want in ("fif_build", "fif_query", "fif_query_grad", "pc_query", "fif_field_bytes",
+                 "fif_workspace_bytes", "fif_update", "fif_field_export", "fif_status_string",
+                 "fif_last_error"):
+        assert want in names
+
+
+def test_library_exports_every_declared_symbol():
+    fif, L = _lib()
+    for name in declared_functions():
+        assert hasattr(L, name), f"libfif.so does not export {name}"
+        assert name in fif.EXPORTS, f"binding does not bind {name}"
+
+
+def test_field_bytes_and_status_strings():
+    fif, L = _lib()
+    g = fif.Grid((0.0, 0.0, 0.0), 0.5, (20, 20, 6))
+    assert fif.field_bytes(g, fif.FP32_COMP) == 2400 * 68 * 4
+    assert fif.field_bytes(g, fif.FP64) == 2400 * 68 * 8
+    assert fif.field_bytes(g, fif.FP32_NAIVE, fif.KIND_TRACE) == 2400 * 12 * 4
+    bad = fif.Grid((0.0, 0.0, 0.0), -1.0, (20, 20, 6))
+    assert fif.field_bytes(bad, fif.FP64) == 0
+    assert fif.field_bytes(fif.Grid((0, 0, 0), 0.5, (0, 1, 1)), fif.FP64) == 0
+    assert fif.field_bytes(g, 7) == 0
+    for s in (0, -1, -2, -3, -4):
+        assert L.fif_status_string(s).decode().startswith(fif.STATUS[s])
+    assert L.fif_workspace_bytes(ctypes.byref(g.c()), 1000, fif.FP32_COMP) == 0
+
+
+def test_host_side_validation_returns_einval():
+    """Every check below fails before anything is enqueued (no GPU needed)."""
+    fif, L = _lib()
+    g = fif.Grid((0.0, 0.0, 0.0), 0.5, (4, 4, 4))
+    vis = fif.Vis()
+    f = fif.CField(g.c(), vis.c(), fif.FP64, fif.KIND_INFO, None)  # NULL data
+    assert L.fif_build(None, 10, ctypes.byref(f), None, 0, None) == -1
+    assert b"NULL" in L.fif_last_error()
+    f.data = 4096
+    assert L.fif_build(None, 10, ctypes.byref(f), None, 0, None) == -1  # NULL landmarks
+    assert L.fif_build(None, -1, ctypes.byref(f), None, 0, None) == -1
+    assert L.fif_update(None, 1, 2, ctypes.byref(f), None) == -1  # bad sign
+    assert L.fif_query(ctypes.byref(f), None, None, 5, 0, 0, None, None, None) == -1  # no metric
+    assert L.fif_query(ctypes.byref(f), None, None, 5, 1, 3, None, None, None) == -1  # interp
+    assert L.fif_query(ctypes.byref(f), None, None, 5, 1, 0, None, None, None) == -1  # NULL t
+    assert L.fif_query(ctypes.byref(f), None, None, 0, 1, 0, None, None, None) == 0   # m = 0
+    assert L.fif_query_grad(ctypes.byref(f), None, None, 5, 8, None, None, None, None,
+                            None) == -1  # FIM21 has no gradient
+    ftr = fif.CField(g.c(), vis.c(), fif.FP64, fif.KIND_TRACE, 4096)
+    assert L.fif_query(ctypes.byref(ftr), None, None, 5, 2, 0, None, None, None) == -1
+    assert L.fif_query_grad(ctypes.byref(ftr), None, None, 5, 1, None, None, None, None,
+                            None) == -4
+    badvis = fif.Vis(sigma=0.0)
+    assert L.pc_query(None, 0, ctypes.byref(badvis.c()), None, 2, None, None, 1, 1, None,
+                      None) == -1
+    cam = fif.CPinhole(-1.0, 300.0, 300.0, 300.0, 600, 600)
+    assert L.pc_query(None, 0, ctypes.byref(vis.c()), ctypes.byref(cam), 2, None, None, 1, 1,
+                      None, None) == -1
+    assert L.fif_field_export(ctypes.byref(f), None, 3, None, None) == -1
+    gb = g.c()
+    gb.reserved = 1
+    fb = fif.CField(gb, vis.c(), fif.FP64, fif.KIND_INFO, 4096)
+    assert L.fif_query(ctypes.byref(fb), None, None, 1, 1, 0, None, None, None) == -1
+
+
+def test_binding_fails_loudly_without_library(tmp_path, monkeypatch):
+    import paper_2008_03324_amd as fif
+    monkeypatch.setattr(fif, "_lib", None)
+    monkeypatch.setattr(fif, "LIB_PATH", str(tmp_path / "missing.so"))
+    with pytest.raises(ImportError):
+        fif.lib()
+
+
+def test_product_package_does_not_import_the_oracle():
+    pkg = os.path.join(ROOT, "paper_2008_03324_amd")
+    for dirpath, _, files in os.walk(pkg):
+        for fn in files:
+            if fn.endswith((".py", ".hip", ".h", ".cpp")):
+                text = open(os.path.join(dirpath, fn)).read()
+                assert "import oracle" not in text and "oracle/" not in text, fn
+                assert "fif_oracle" not in text, fn
