@@ -1,0 +1,296 @@
+"""Benchmark of the Fisher Information Field hot path on one MI355X.
+
+One step = the whole path over one batch of the building-scale workload:
+  build  the FP32-compensated field of 200x200x50 voxels (h = 0.2 m) from
+         100k landmarks (70 % on walls) with a 15 m range cutoff
+  query  10M Haar-random poses -> trace, lambda_min, log-det
+  grad   4,096 trajectories x 64 poses -> d/dt and d/dphi of the three metrics
+  pc     the point-cloud brute force on the same 10M poses (FP32 compensated)
+`value` is field pose-FIM queries per second (the query phase); the other
+phases are reported beside it.  Inputs are resident in HBM before timing.
+
+Usage: python bench.py [--gpus 1] [--steps 3] [--warmup 1]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import platform
+import subprocess
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+FP32_PEAK_TFLOPS = 157.3
+RECORD_BYTES_USED = 66 * 4          # moment scalars read per corner (FP32 field)
+POSE_BYTES = 7 * 4                  # t (3) + q (4), float32
+OUT_BYTES_3 = 3 * 8                 # three FP64 metrics
+# FP32 flops of one build pair: 35 monomial products, 25 adds,
+# 41 FMAs (2 flops), 3 (u) + 1 (rn^2) products, d and n^2 (8), 1 rsqrt
+BUILD_FLOPS_CONTRIB = 151
+BUILD_FLOPS_TESTED = 10             # d (3), n^2 (5), two compares
+PC_FLOPS_CONTRIB = 45
+PC_FLOPS_TESTED = 10
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--landmarks", type=int, default=100_000)
+    ap.add_argument("--poses", type=int, default=10_000_000)
+    ap.add_argument("--no-pc", action="store_true", help="skip the point-cloud phase")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="run one 1 GiB device copy first (reference for HBM counters)")
+    ap.add_argument("--phases", default="build,query,grad,pc",
+                    help="comma list of phases to run in each step")
+    ap.add_argument("--cpu-sample", type=int, default=2048, help="poses in the oracle sample")
+    return ap.parse_args()
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return platform.processor() or "unknown"
+
+
+def contributing_fraction(torch, lm_d, grid, r_max, n_sample=32768, seed=7):
+    """Fraction of (voxel, landmark) pairs inside the range (sampled voxels)."""
+    g = torch.Generator(device="cpu").manual_seed(seed)
+    shape = torch.tensor(grid.shape)
+    idx = torch.stack([torch.randint(0, int(s), (n_sample,), generator=g) for s in grid.shape], 1)
+    tv = (torch.tensor(grid.origin) + idx.double() * grid.h).float().cuda()
+    lm = lm_d.float()
+    r2 = float(np.float32(r_max * r_max))
+    inside = 0
+    for c in range(0, n_sample, 1024):
+        d = ((tv[c:c + 1024, None, :] - lm[None, :, :]) ** 2).sum(-1)
+        inside += int((d <= r2).sum().item())
+    return inside / (n_sample * lm.shape[0])
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU; --gpus above 1 is not "
+                                   "supported (see DESIGN.md for how the path would shard)"}))
+        sys.exit(2)
+    import torch
+
+    import paper_2008_03324_amd as fif
+    import scenes
+
+    dev = torch.device("cuda:0")
+    fif.lib()
+    log(f"device {torch.cuda.get_device_name(0)}")
+
+    # ------------------------------------------------------------- inputs
+    lm, g, v = scenes.building_scene(n_landmarks=args.landmarks)
+    grid = fif.Grid(g.origin, g.h, g.shape)
+    vis = fif.Vis(v.half_fov, v.v_alpha, v.sigma, v.r_min, v.r_max)
+    t, q = scenes.building_poses(g, args.poses)
+    tt, tq = scenes.trajectories(g, 4096, 64)
+    tt, tq = tt.reshape(-1, 3), tq.reshape(-1, 4)
+    lm_d = torch.tensor(lm, dtype=torch.float64, device=dev)
+    t_d = torch.from_numpy(t).to(dev)
+    q_d = torch.from_numpy(q).to(dev)
+    tt_d = torch.from_numpy(np.ascontiguousarray(tt)).to(dev)
+    tq_d = torch.from_numpy(np.ascontiguousarray(tq)).to(dev)
+    m, mg = t.shape[0], tt.shape[0]
+    metrics = fif.TRACE | fif.LMIN | fif.LOGDET
+    out = torch.empty((m, 3), dtype=torch.float64, device=dev)
+    pc_out = torch.empty((m, 3), dtype=torch.float64, device=dev)
+    up = torch.ones((mg, 3), dtype=torch.float64, device=dev)
+    field = fif.Field(grid, vis, fif.FP32_COMP, device=dev)
+    log(f"inputs resident: {args.landmarks} landmarks, {grid.n_voxels} voxels, {m} poses, "
+        f"{mg} trajectory poses, field {field.nbytes / 1e6:.1f} MB")
+    frac = contributing_fraction(torch, lm_d, grid, v.r_max)
+    tested = float(grid.n_voxels) * args.landmarks
+    contrib = frac * tested
+    pc_tested = float(m) * args.landmarks
+    log(f"contributing fraction {frac:.4f} (sampled)")
+
+    phases = [p for p in args.phases.split(",") if p]
+    if args.no_pc and "pc" in phases:
+        phases.remove("pc")
+    if "build" not in phases:  # later phases read the field
+        fif.build(lm_d, grid, vis, field=field)
+    if args.calib_copy:
+        src = torch.empty(1 << 30, dtype=torch.uint8, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+
+    def step(rec):
+        ev = {}
+        for ph in phases:
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record()
+            if ph == "build":
+                fif.build(lm_d, grid, vis, field=field)
+            elif ph == "query":
+                fif.query(field, t_d, q_d, metrics, out=out)
+            elif ph == "grad":
+                fif.query_grad(field, tt_d, tq_d, metrics, up)
+            else:
+                fif.pc_query(lm_d, vis, t_d, q_d, metrics, prec=fif.FP32_COMP, out=pc_out)
+            e1.record()
+            ev[ph] = (e0, e1)
+        rec.append(ev)
+
+    for i in range(args.warmup):
+        warm = []
+        step(warm)
+        torch.cuda.synchronize()
+        log(f"warmup {i + 1}/{args.warmup} done")
+    recs = []
+    torch.cuda.synchronize()
+    w0 = time.perf_counter()
+    for i in range(args.steps):
+        step(recs)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - w0
+    ms = {ph: [r[ph][0].elapsed_time(r[ph][1]) for r in recs] for ph in phases}
+    med = {ph: float(np.median(ms[ph])) for ph in phases}
+    log("phase medians (ms): " + ", ".join(f"{k} {v:.3f}" for k, v in med.items()))
+
+    for ph in ("build", "query", "grad"):
+        med.setdefault(ph, float("nan"))
+    q_rate = m / (med["query"] / 1e3)
+    q_bytes = m * (8 * RECORD_BYTES_USED + POSE_BYTES + OUT_BYTES_3)
+    q_gbs = q_bytes / (med["query"] / 1e3) / 1e9
+    b_flops = contrib * BUILD_FLOPS_CONTRIB + (tested - contrib) * BUILD_FLOPS_TESTED
+    b_tfs = b_flops / (med["build"] / 1e3) / 1e12
+    res = {
+        "metric": "pose-FIM queries/s field vs point cloud at stated rel. err; build pairs/s; p99",
+        "value": q_rate,
+        "unit": "queries/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": wall * 1e3 / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32 field and gathers, f64 metric step",
+        "data": "synthetic (seeded walls + clutter scene, Haar poses, B-spline trajectories)",
+        "config": {
+            "workload": "building scene: 100k landmarks (70% on 12 walls), 200x200x50 voxels "
+                        "at 0.2 m, 15 m range cutoff, 10M Haar poses; FP32-compensated "
+                        "field; trace + lambda_min + log-det; grad on 4096x64 trajectory "
+                        "poses; point cloud on the same 10M poses",
+            "landmarks": args.landmarks, "voxels": grid.n_voxels, "poses": m,
+            "grad_poses": mg, "field_precision": "FP32_COMP",
+        },
+        "phases_ms": med,
+        "build_pairs_per_s": contrib / (med["build"] / 1e3),
+        "build_tested_pairs_per_s": tested / (med["build"] / 1e3),
+        "contributing_fraction": frac,
+        "grad_poses_per_s": mg / (med["grad"] / 1e3),
+        "roofline": {"kernel": "query_info_kernel<float>", "bound": "hbm",
+                     "achieved": q_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": q_gbs / HBM_PEAK_GBS, "traffic": None,
+                     "bytes_per_query": q_bytes / m},
+        "roofline_build": {"kernel": "build_kernel<FP32_COMP>", "bound": "fp32 valu",
+                           "achieved": b_tfs, "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
+                           "frac": b_tfs / FP32_PEAK_TFLOPS},
+    }
+    if "pc" in phases:
+        pc_rate = m / (med["pc"] / 1e3)
+        pc_flops = frac * pc_tested * PC_FLOPS_CONTRIB + (1 - frac) * pc_tested * PC_FLOPS_TESTED
+        res["pc_queries_per_s"] = pc_rate
+        res["speedup_vs_pc"] = q_rate / pc_rate
+        res["roofline_pc"] = {"kernel": "pc_kernel<FP32_COMP>", "bound": "fp32 valu",
+                              "achieved": pc_flops / (med["pc"] / 1e3) / 1e12,
+                              "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s"}
+        res["roofline_pc"]["frac"] = res["roofline_pc"]["achieved"] / FP32_PEAK_TFLOPS
+
+    # ------------------------------------------------ accuracy + CPU baseline
+    if not args.no_cpu:
+        res.update(cpu_leg(args, fif, torch, lm, g, v, t, q, out, pc_out, metrics))
+    print(json.dumps(res), flush=True)
+
+
+def cpu_leg(args, fif, torch, lm, g, v, t, q, out, pc_out, metrics):
+    """Oracle on a bounded sample: its own throughput, and the GPU's error."""
+    import oracle
+    rng = np.random.default_rng(11)
+    ns = args.cpu_sample
+    pick = rng.choice(t.shape[0], ns, replace=False)
+    ts = t[pick].astype(np.float64)
+    qs = q[pick].astype(np.float64)
+    ids = oracle.corner_voxels(g.origin, g.h, g.shape, ts)
+    nthreads = oracle.num_threads()
+    log(f"oracle sample: {ns} poses, {ids.size} corner voxels, {nthreads} threads")
+    c0 = time.perf_counter()
+    C = oracle.build(lm, g.origin, g.h, g.shape, v.sigma, v.r_min, v.r_max, voxel_ids=ids)
+    build_s = time.perf_counter() - c0
+    ofield = oracle.Field(C, g.origin, g.h, g.shape, voxel_ids=ids)
+    reps = 20
+    c0 = time.perf_counter()
+    for _ in range(reps):
+        ref, _ = oracle.query(ofield, v.half_fov, v.v_alpha, ts, qs, metrics)
+    q_s = (time.perf_counter() - c0) / reps
+    n_pc = max(8, ns // 4)
+    c0 = time.perf_counter()
+    ref_pc = oracle.pc_query(lm, v.half_fov, v.v_alpha, v.sigma, v.r_min, v.r_max, ts[:n_pc],
+                             qs[:n_pc], metrics)
+    pc_s = time.perf_counter() - c0
+    _, F_ref = oracle.pc_query(lm, v.half_fov, v.v_alpha, v.sigma, v.r_min, v.r_max, ts[:1],
+                               qs[:1], 8, want_fim=True)
+    gpu = out[torch.from_numpy(pick).to(out.device)].cpu().numpy()
+    gpu_pc = pc_out[torch.from_numpy(pick[:n_pc]).to(out.device)].cpu().numpy()
+    ref_fim, _ = oracle.query(ofield, v.half_fov, v.v_alpha, ts, qs, 8)
+    iu = np.triu_indices(6)
+    lmax = []
+    for r in ref_fim:
+        F = np.zeros((6, 6))
+        F[iu] = r
+        F[(iu[1], iu[0])] = r
+        lmax.append(np.linalg.eigvalsh(F)[-1])
+    lmax = np.array(lmax)
+
+    def errs(a, b, lm_):
+        return {"trace_rel_max": float(np.max(np.abs(a[:, 0] - b[:, 0]) / np.abs(b[:, 0]))),
+                "lmin_weyl_max": float(np.max(np.abs(a[:, 1] - b[:, 1]) / lm_)),
+                "lmin_rel_max": float(np.max(np.abs(a[:, 1] - b[:, 1]) / np.abs(b[:, 1]))),
+                "logdet_abs_max": float(np.nanmax(np.abs(a[:, 2] - b[:, 2])))}
+
+    pairs = ids.size * lm.shape[0]
+    return {
+        "rel_err_field_vs_oracle": errs(gpu, ref, lmax),
+        "rel_err_pc_vs_oracle": errs(gpu_pc, ref_pc, lmax[:n_pc]),
+        "cpu_baseline": {
+            "value": ns / q_s, "unit": "queries/s", "cores": nthreads, "kind": "oracle",
+            "cpu": cpu_model(),
+            "sample": f"{ns} of the 10M poses: FP64 factors of their {ids.size} corner "
+                      f"voxels built from all {lm.shape[0]} landmarks ({build_s:.1f} s), then "
+                      f"queried (trace+lmin+logdet); point cloud on {n_pc} poses "
+                      f"({pc_s:.1f} s)",
+            "build_pairs_per_s": pairs / build_s,
+            "pc_queries_per_s": n_pc / pc_s,
+        },
+    }
+
+
+if __name__ == "__main__":
+    main()
