@@ -79,7 +79,9 @@ void range_bounds(const fif_vis* v, float* lo2, float* hi2) {
   *hi2 = isinf(v->r_max) ? INFINITY : (float)(v->r_max * v->r_max);
 }
 
-size_t record_scalars(int32_t kind) { return kind == FIF_KIND_INFO ? fif::kRec : fif::kTRec; }
+size_t record_scalars(int32_t kind) {
+  return kind == FIF_KIND_INFO ? (size_t)(fif::kMain + fif::kSideRec) : (size_t)fif::kTRec;
+}
 size_t scalar_bytes(int32_t prec) { return prec == FIF_FP64 ? 8 : 4; }
 
 fif_status check_field(const fif_field* f) {

@@ -99,13 +99,33 @@ __device__ inline float inv_sqrt<float>(float x) { return rsqrtf(x); }
 template <>
 __device__ inline double inv_sqrt<double>(double x) { return 1.0 / sqrt(x); }
 
+// Vector stores of N scalars (16-B aligned destination, N even).
+template <typename T, int N>
+__device__ inline void store_vec(T* dst, const T* v) {
+  if (sizeof(T) == 8 || (N % 4) != 0) {
+#pragma unroll
+    for (int k = 0; k < N; k += 2) {
+      typename std::conditional<sizeof(T) == 8, double2, float2>::type w;
+      w.x = v[k];
+      w.y = v[k + 1];
+      reinterpret_cast<decltype(w)*>(dst)[k / 2] = w;
+    }
+  } else {
+#pragma unroll
+    for (int k = 0; k < N; k += 4) {
+      float4 w;
+      w.x = (float)v[k]; w.y = (float)v[k + 1]; w.z = (float)v[k + 2]; w.w = (float)v[k + 3];
+      reinterpret_cast<float4*>(dst)[k / 4] = w;
+    }
+  }
+}
+
 // PREC: FIF_FP32_NAIVE / FIF_FP32_COMP / FIF_FP64; KIND: info or trace.
 template <int PREC, int KIND>
 __global__ __launch_bounds__(kBuildThreads) void build_kernel(BuildArgs a) {
   using T = typename std::conditional<PREC == 2, double, float>::type;
   using L4 = typename LmT<T>::type;
   constexpr int NACC = (KIND == 0) ? kMom : 10;
-  constexpr int STRIDE = (KIND == 0) ? kRec : kTRec;
   constexpr bool COMP = (PREC == 1);
 
   __shared__ L4 s_lm[kBatch];
@@ -155,7 +175,7 @@ __global__ __launch_bounds__(kBuildThreads) void build_kernel(BuildArgs a) {
         T nn = (PREC == 2) ? (T)fma((double)dz, (double)dz, fma((double)dy, (double)dy, (double)dx * dx))
                            : (T)n2;
         T rn = inv_sqrt<T>(nn);
-        if (KIND == 0)
+        if constexpr (KIND == 0)
           info_pair<T>(acc, dx, dy, dz, rn);
         else
           trace_pair<T>(acc, dx, dy, dz, rn, p.x, p.y, p.z, p.w);
@@ -171,37 +191,56 @@ __global__ __launch_bounds__(kBuildThreads) void build_kernel(BuildArgs a) {
   }
   if (!valid) return;
   const size_t vox = (size_t)ix + (size_t)a.g.nx * ((size_t)iy + (size_t)a.g.ny * (size_t)iz);
-  T* out = reinterpret_cast<T*>(a.out) + vox * STRIDE;
-  T res[STRIDE];
+  const size_t nvox = (size_t)a.g.nx * a.g.ny * a.g.nz;
+  T res[NACC];
 #pragma unroll
-  for (int k = 0; k < STRIDE; ++k) {
-    T v = T(0);
-    if (k < NACC) v = COMP ? (T)(hi[k] + lo[k]) : acc[k];
-    res[k] = v;
-  }
-  if (a.accumulate) {
+  for (int k = 0; k < NACC; ++k) res[k] = COMP ? (T)(hi[k] + lo[k]) : acc[k];
+  if constexpr (KIND == 0) {
+    T* main = reinterpret_cast<T*>(a.out) + vox * kMain;
+    T* side = reinterpret_cast<T*>(a.out) + nvox * kMain + vox * kSideRec;  // slot 0
+    if (a.accumulate) {
 #pragma unroll
-    for (int k = 0; k < NACC; ++k) res[k] = out[k] + (T)a.sign * res[k];
-  }
-  if (PREC == 2) {
+      for (int k = 0; k < kMain; ++k) res[k] = main[k] + (T)a.sign * res[k];
 #pragma unroll
-    for (int k = 0; k < STRIDE; k += 2) {
-      double2 v;
-      v.x = (double)res[k];
-      v.y = (double)res[k + 1];
-      reinterpret_cast<double2*>(out)[k / 2] = v;
+      for (int k = 0; k < kSide; ++k) res[kMain + k] = side[k] + (T)a.sign * res[kMain + k];
     }
+    store_vec<T, kMain>(main, res);
+    store_vec<T, kSide>(side, res + kMain);
   } else {
+    T* out = reinterpret_cast<T*>(a.out) + vox * kTRec;
+    T r12[kTRec];
 #pragma unroll
-    for (int k = 0; k < STRIDE; k += 4) {
-      float4 v;
-      v.x = (float)res[k];
-      v.y = (float)res[k + 1];
-      v.z = (float)res[k + 2];
-      v.w = (float)res[k + 3];
-      reinterpret_cast<float4*>(out)[k / 4] = v;
+    for (int k = 0; k < kTRec; ++k) r12[k] = (k < NACC) ? res[k] : T(0);
+    if (a.accumulate) {
+#pragma unroll
+      for (int k = 0; k < NACC; ++k) r12[k] = out[k] + (T)a.sign * r12[k];
     }
+    store_vec<T, kTRec>(out, r12);
   }
+}
+
+// Slots 1..7 of every cell side record from slot 0 of the corner voxels' records.
+template <typename T>
+__global__ __launch_bounds__(256) void fill_side_kernel(GridDev g, void* field) {
+  const size_t nvox = (size_t)g.nx * g.ny * g.nz;
+  const size_t v = (size_t)blockIdx.x * 256 + threadIdx.x;
+  if (v >= nvox) return;
+  T* side = reinterpret_cast<T*>(field) + nvox * kMain;
+  const int32_t ix = (int32_t)(v % g.nx), iy = (int32_t)((v / g.nx) % g.ny),
+                iz = (int32_t)(v / ((size_t)g.nx * g.ny));
+  T vals[kSideRec];
+#pragma unroll
+  for (int s = 0; s < 8; ++s) {
+    const int32_t cx = min(ix + (s & 1), g.nx - 1);
+    const int32_t cy = min(iy + ((s >> 1) & 1), g.ny - 1);
+    const int32_t cz = min(iz + (s >> 2), g.nz - 1);
+    const size_t c = (size_t)cx + (size_t)g.nx * ((size_t)cy + (size_t)g.ny * (size_t)cz);
+    vals[2 * s] = side[c * kSideRec];
+    vals[2 * s + 1] = side[c * kSideRec + 1];
+  }
+  // slot 0 is unchanged; rewrite slots 1..7 only
+#pragma unroll
+  for (int k = 2; k < kSideRec; ++k) side[v * kSideRec + k] = vals[k];
 }
 
 hipError_t launch_build(const BuildArgs& a, int prec, int kind, hipStream_t stream) {
@@ -218,6 +257,14 @@ hipError_t launch_build(const BuildArgs& a, int prec, int kind, hipStream_t stre
     else FIF_LAUNCH(2, 1);
   }
 #undef FIF_LAUNCH
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess || kind != 0) return e;
+  const size_t nvox = (size_t)a.g.nx * a.g.ny * a.g.nz;
+  dim3 sgrid((unsigned)((nvox + 255) / 256));
+  if (prec == 2)
+    hipLaunchKernelGGL((fill_side_kernel<double>), sgrid, dim3(256), 0, stream, a.g, a.out);
+  else
+    hipLaunchKernelGGL((fill_side_kernel<float>), sgrid, dim3(256), 0, stream, a.g, a.out);
   return hipGetLastError();
 }
 

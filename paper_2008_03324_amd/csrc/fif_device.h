@@ -12,7 +12,14 @@
 //   I_i = M(t_v)^T (1/sigma^2) [[P/n^2, -[u]x/n], [[u]x/n, P]] M(t_v),
 //   P = I - u u^T,  M(t) = [[I, -[t]x], [0, I]],
 // follows from eq:jac_pose_global with [p]x = [t_v]x + [d]x and P[d]x = [d]x.
-// A voxel record is 68 scalars (66 used, 2 zero) of the field's precision.
+// Storage: the first 64 moments of every voxel form a 256-B (FP32) main record,
+// exactly two 128-B cache lines.  The last 2 moments go to a "cell side
+// record" of 16 scalars per voxel v: slot s = bx + 2 by + 4 bz holds the 2 side
+// moments of voxel min(v + (bx, by, bz), n - 1), i.e. of every corner of the
+// cell whose lowest corner is v.  A trilinear query then reads its 8 side pairs
+// as one aligned 64-B block instead of touching four more cache lines.  Slot 0
+// is written by the build; slots 1..7 are copied from the slot 0 of the
+// neighbouring records by a second pass.
 //
 // 21-vectors hold symmetric 6x6 matrices as their upper triangle, row-major.
 #pragma once
@@ -22,8 +29,10 @@
 
 namespace fif {
 
-constexpr int kRec = 68;   // scalars per voxel record (information field)
-constexpr int kMom = 66;   // used scalars
+constexpr int kMain = 64;  // scalars per voxel in the main record
+constexpr int kSide = 2;   // side moments per voxel
+constexpr int kSideRec = 16;  // scalars per cell side record (8 corners x 2)
+constexpr int kMom = 66;   // moments per voxel
 constexpr int kTRec = 12;  // scalars per voxel record (trace field, 10 used)
 constexpr int O_G0_4 = 0, O_G0_3 = 15, O_G2_4 = 25, O_G2_3 = 40, O_G1_3 = 50, O_G1_2 = 60;
 
@@ -147,68 +156,81 @@ __device__ inline int32_t axis_nearest(double t, double o, double h, int32_t n, 
 
 // ------------------------------------------------------------ moment contraction
 
-// For one moment group with degree-4 part S4[15] and degree-3 part S3[10]
-// (weights 1 or 1/n^2), Q = sum v u u^T with v = k2 c^2 + k1 c + k0, c = z.u.
-template <typename T>
-__device__ inline void group_Q(const T* S4, const T* S3, const double z[3], double k2, double k1,
-                               double k0, double Q[6]) {
-  double zw[6];
+// Per-query weights of the moment contraction with the quadratic visibility
+// v(c) = k2 c^2 + k1 c + k0, c = z.u.  On the unit sphere the constant k0 folds
+// into the squared terms (|u| = 1): v = sum_{c<=d} w2[cd] u_c u_d + sum_c w1[c] u_c
+// with w2[cc] = k2 z_c^2 + k0, w2[cd] = 2 k2 z_c z_d (c < d), w1 = k1 z.
+template <typename CT>
+struct VisW {
+  CT w2[6];
+  CT w1[3];
+};
+
+template <typename CT>
+__device__ inline VisW<CT> vis_weights(const CT z[3], CT k2, CT k1, CT k0) {
+  VisW<CT> w;
 #pragma unroll
   for (int c = 0; c < 3; ++c)
 #pragma unroll
-    for (int d = c; d < 3; ++d) zw[i2(c, d)] = (c == d ? 1.0 : 2.0) * z[c] * z[d];
+    for (int d = c; d < 3; ++d)
+      w.w2[i2(c, d)] = (c == d) ? fma(k2 * z[c], z[c], k0) : CT(2) * k2 * z[c] * z[d];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) w.w1[c] = k1 * z[c];
+  return w;
+}
+
+// For one moment group with degree-4 part S4[15] and degree-3 part S3[10]
+// (weights 1 or 1/n^2), Q = sum v u u^T.
+template <typename CT, typename T>
+__device__ inline void group_Q(const T* S4, const T* S3, const VisW<CT>& w, CT Q[6]) {
 #pragma unroll
   for (int a = 0; a < 3; ++a)
 #pragma unroll
     for (int b = a; b < 3; ++b) {
-      double q4 = 0.0, q3 = 0.0, s2v = 0.0;
+      CT q = 0;
 #pragma unroll
       for (int c = 0; c < 3; ++c)
 #pragma unroll
-        for (int d = c; d < 3; ++d) q4 = fma(zw[i2(c, d)], (double)S4[s4(a, b, c, d)], q4);
+        for (int d = c; d < 3; ++d) q = fma(w.w2[i2(c, d)], (CT)S4[s4(a, b, c, d)], q);
 #pragma unroll
-      for (int c = 0; c < 3; ++c) q3 = fma(z[c], (double)S3[s3(a, b, c)], q3);
-#pragma unroll
-      for (int c = 0; c < 3; ++c) s2v += (double)S4[s4(a, b, c, c)];
-      Q[i2(a, b)] = k2 * q4 + k1 * q3 + k0 * s2v;
+      for (int c = 0; c < 3; ++c) q = fma(w.w1[c], (CT)S3[s3(a, b, c)], q);
+      Q[i2(a, b)] = q;
     }
 }
 
 // b = sum v u / n from the G1 group (degree 3 R3[10], degree 2 R2[6]).
-template <typename T>
-__device__ inline void group_b(const T* R3, const T* R2, const double z[3], double k2, double k1,
-                               double k0, double bvec[3]) {
+template <typename CT, typename T>
+__device__ inline void group_b(const T* R3, const T* R2, const VisW<CT>& w, CT bvec[3]) {
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
-    double q3 = 0.0, q2 = 0.0, r1 = 0.0;
+    CT q = 0;
 #pragma unroll
     for (int c = 0; c < 3; ++c)
 #pragma unroll
-      for (int d = c; d < 3; ++d)
-        q3 = fma((c == d ? 1.0 : 2.0) * z[c] * z[d], (double)R3[s3(a, c, d)], q3);
+      for (int d = c; d < 3; ++d) q = fma(w.w2[i2(c, d)], (CT)R3[s3(a, c, d)], q);
 #pragma unroll
-    for (int c = 0; c < 3; ++c) q2 = fma(z[c], (double)R2[s2(a, c)], q2);
-#pragma unroll
-    for (int c = 0; c < 3; ++c) r1 += (double)R3[s3(a, c, c)];
-    bvec[a] = k2 * q3 + k1 * q2 + k0 * r1;
+    for (int c = 0; c < 3; ++c) q = fma(w.w1[c], (CT)R2[s2(a, c)], q);
+    bvec[a] = q;
   }
 }
 
 // 3x3 helpers: symmetric matrices as 6-vectors (i2 order), general as row-major 9.
-__device__ inline double sym3(const double* A, int i, int j) { return A[s2(i, j)]; }
+template <typename CT>
+__device__ inline CT sym3(const CT* A, int i, int j) { return A[s2(i, j)]; }
 
 // X = M(delta)^T [[A, B], [B^T, D]] M(delta), M(delta) = [[I, -[delta]x], [0, I]]:
 //   TL = A, TR = B + (S A)^T, BR = D + S (S A)^T + S B + (S B)^T,  S = [delta]x.
-__device__ inline void shift_frame(const double A[6], const double B[9], const double D[6],
-                                   const double dl[3], double out[21]) {
+template <typename CT>
+__device__ inline void shift_frame(const CT A[6], const CT B[9], const CT D[6], const CT dl[3],
+                                   CT out[21]) {
   // rows of S
-  const double S[9] = {0.0, -dl[2], dl[1], dl[2], 0.0, -dl[0], -dl[1], dl[0], 0.0};
-  double SA[9], SB[9];
+  const CT S[9] = {0, -dl[2], dl[1], dl[2], 0, -dl[0], -dl[1], dl[0], 0};
+  CT SA[9], SB[9];
 #pragma unroll
   for (int i = 0; i < 3; ++i)
 #pragma unroll
     for (int j = 0; j < 3; ++j) {
-      double sa = 0.0, sb = 0.0;
+      CT sa = 0, sb = 0;
 #pragma unroll
       for (int k = 0; k < 3; ++k) {
         sa = fma(S[i * 3 + k], sym3(A, k, j), sa);
@@ -229,7 +251,7 @@ __device__ inline void shift_frame(const double A[6], const double B[9], const d
   for (int i = 0; i < 3; ++i)
 #pragma unroll
     for (int j = i; j < 3; ++j) {
-      double s = 0.0;  // (S (SA)^T)_ij = sum_k S_ik SA_jk
+      CT s = 0;  // (S (SA)^T)_ij = sum_k S_ik SA_jk
 #pragma unroll
       for (int k = 0; k < 3; ++k) s = fma(S[i * 3 + k], SA[j * 3 + k], s);
       out[u21(3 + i, 3 + j)] = sym3(D, i, j) + s + SB[i * 3 + j] + SB[j * 3 + i];
@@ -238,32 +260,32 @@ __device__ inline void shift_frame(const double A[6], const double B[9], const d
 
 // Camera-frame block of one voxel at optical axis z, shifted by delta = t_v - t:
 // returns the 21-vector of M(delta)^T X M(delta) (without the 1/sigma^2 factor).
-template <typename T>
-__device__ inline void corner_fim(const T* rec, const double z[3], double k2, double k1, double k0,
-                                  const double dl[3], double out[21]) {
-  double Q2[6], Q0[6], bv[3];
-  group_Q(rec + O_G2_4, rec + O_G2_3, z, k2, k1, k0, Q2);
-  group_Q(rec + O_G0_4, rec + O_G0_3, z, k2, k1, k0, Q0);
-  group_b(rec + O_G1_3, rec + O_G1_2, z, k2, k1, k0, bv);
-  double A[6], D[6], B[9];
-  double tr2 = Q2[0] + Q2[3] + Q2[5], tr0 = Q0[0] + Q0[3] + Q0[5];
+template <typename CT, typename T>
+__device__ inline void corner_fim(const T* rec, const VisW<CT>& w, const CT dl[3], CT out[21]) {
+  CT Q2[6], Q0[6], bv[3];
+  group_Q<CT>(rec + O_G2_4, rec + O_G2_3, w, Q2);
+  group_Q<CT>(rec + O_G0_4, rec + O_G0_3, w, Q0);
+  group_b<CT>(rec + O_G1_3, rec + O_G1_2, w, bv);
+  CT A[6], D[6], B[9];
+  CT tr2 = Q2[0] + Q2[3] + Q2[5], tr0 = Q0[0] + Q0[3] + Q0[5];
 #pragma unroll
   for (int a = 0; a < 3; ++a)
 #pragma unroll
     for (int b = a; b < 3; ++b) {
-      A[i2(a, b)] = (a == b ? tr2 : 0.0) - Q2[i2(a, b)];
-      D[i2(a, b)] = (a == b ? tr0 : 0.0) - Q0[i2(a, b)];
+      A[i2(a, b)] = (a == b ? tr2 : CT(0)) - Q2[i2(a, b)];
+      D[i2(a, b)] = (a == b ? tr0 : CT(0)) - Q0[i2(a, b)];
     }
   // B = -[b]x
-  B[0] = 0.0;    B[1] = bv[2];  B[2] = -bv[1];
-  B[3] = -bv[2]; B[4] = 0.0;    B[5] = bv[0];
-  B[6] = bv[1];  B[7] = -bv[0]; B[8] = 0.0;
-  shift_frame(A, B, D, dl, out);
+  B[0] = 0;      B[1] = bv[2];  B[2] = -bv[1];
+  B[3] = -bv[2]; B[4] = 0;      B[5] = bv[0];
+  B[6] = bv[1];  B[7] = -bv[0]; B[8] = 0;
+  shift_frame<CT>(A, B, D, dl, out);
 }
 
 // General symmetric 6x6 (21) -> world frame: M(t)^T Z M(t).
-__device__ inline void shift21(const double Z[21], const double t[3], double out[21]) {
-  double A[6], D[6], B[9];
+template <typename CT>
+__device__ inline void shift21(const CT Z[21], const CT t[3], CT out[21]) {
+  CT A[6], D[6], B[9];
 #pragma unroll
   for (int i = 0; i < 3; ++i)
 #pragma unroll
@@ -275,15 +297,16 @@ __device__ inline void shift21(const double Z[21], const double t[3], double out
   for (int i = 0; i < 3; ++i)
 #pragma unroll
     for (int j = 0; j < 3; ++j) B[i * 3 + j] = Z[u21(i, 3 + j)];
-  shift_frame(A, B, D, t, out);
+  shift_frame<CT>(A, B, D, t, out);
 }
 
 // Adjoint shift for gradients: G' = M(delta) G M(delta)^T with
 //   G = [[P, Q], [Q^T, R]], S = [delta]x:
 //   TL' = P + QS + (QS)^T + S (S R)^T,  TR' = Q - S R,  BR' = R.
-__device__ inline void shift21_adj(const double G[21], const double dl[3], double out[21]) {
-  const double S[9] = {0.0, -dl[2], dl[1], dl[2], 0.0, -dl[0], -dl[1], dl[0], 0.0};
-  double Q[9], QS[9], SR[9];
+template <typename CT>
+__device__ inline void shift21_adj(const CT G[21], const CT dl[3], CT out[21]) {
+  const CT S[9] = {0, -dl[2], dl[1], dl[2], 0, -dl[0], -dl[1], dl[0], 0};
+  CT Q[9], QS[9], SR[9];
 #pragma unroll
   for (int i = 0; i < 3; ++i)
 #pragma unroll
@@ -292,7 +315,7 @@ __device__ inline void shift21_adj(const double G[21], const double dl[3], doubl
   for (int i = 0; i < 3; ++i)
 #pragma unroll
     for (int j = 0; j < 3; ++j) {
-      double qs = 0.0, sr = 0.0;
+      CT qs = 0, sr = 0;
 #pragma unroll
       for (int k = 0; k < 3; ++k) {
         qs = fma(Q[i * 3 + k], S[k * 3 + j], qs);
@@ -305,7 +328,7 @@ __device__ inline void shift21_adj(const double G[21], const double dl[3], doubl
   for (int i = 0; i < 3; ++i)
 #pragma unroll
     for (int j = i; j < 3; ++j) {
-      double s = 0.0;  // (S (SR)^T)_ij = sum_k S_ik SR_jk
+      CT s = 0;  // (S (SR)^T)_ij = sum_k S_ik SR_jk
 #pragma unroll
       for (int k = 0; k < 3; ++k) s = fma(S[i * 3 + k], SR[j * 3 + k], s);
       out[u21(i, j)] = G[u21(i, j)] + QS[i * 3 + j] + QS[j * 3 + i] + s;
@@ -325,118 +348,118 @@ __device__ inline void shift21_adj(const double G[21], const double dl[3], doubl
 // For a symmetric 3x3 H (6, i2 order) and one moment group (S4, S3):
 //   val   = sum v (tr H - u^T H u)  (times the group weight)
 //   gz[c] = d val / d z_c
-template <typename T>
-__device__ inline void group_vjp(const T* S4, const T* S3, const double H[6], const double z[3],
-                                 double k2, double k1, double k0, double* val, double gz[3]) {
-  double trH = H[0] + H[3] + H[5];
-  double HS4[6], HS3[3], S2[6], S1[3];
+template <typename CT, typename T>
+__device__ inline void group_vjp(const T* S4, const T* S3, const CT H[6], const CT z[3], CT k2,
+                                 CT k1, CT k0, CT* val, CT gz[3]) {
+  CT trH = H[0] + H[3] + H[5];
+  CT HS4[6], HS3[3], S2[6], S1[3];
 #pragma unroll
   for (int c = 0; c < 3; ++c)
 #pragma unroll
     for (int d = c; d < 3; ++d) {
-      double acc = 0.0, s2v = 0.0;
+      CT acc = 0, s2v = 0;
 #pragma unroll
       for (int a = 0; a < 3; ++a)
 #pragma unroll
         for (int b = a; b < 3; ++b)
-          acc = fma((a == b ? 1.0 : 2.0) * H[i2(a, b)], (double)S4[s4(a, b, c, d)], acc);
+          acc = fma((a == b ? CT(1) : CT(2)) * H[i2(a, b)], (CT)S4[s4(a, b, c, d)], acc);
 #pragma unroll
-      for (int e = 0; e < 3; ++e) s2v += (double)S4[s4(c, d, e, e)];
+      for (int e = 0; e < 3; ++e) s2v += (CT)S4[s4(c, d, e, e)];
       HS4[i2(c, d)] = acc;
       S2[i2(c, d)] = s2v;
     }
 #pragma unroll
   for (int c = 0; c < 3; ++c) {
-    double acc = 0.0, s1v = 0.0;
+    CT acc = 0, s1v = 0;
 #pragma unroll
     for (int a = 0; a < 3; ++a)
 #pragma unroll
       for (int b = a; b < 3; ++b)
-        acc = fma((a == b ? 1.0 : 2.0) * H[i2(a, b)], (double)S3[s3(a, b, c)], acc);
+        acc = fma((a == b ? CT(1) : CT(2)) * H[i2(a, b)], (CT)S3[s3(a, b, c)], acc);
 #pragma unroll
-    for (int e = 0; e < 3; ++e) s1v += (double)S3[s3(c, e, e)];
+    for (int e = 0; e < 3; ++e) s1v += (CT)S3[s3(c, e, e)];
     HS3[c] = acc;
     S1[c] = s1v;
   }
-  double S0 = S2[0] + S2[3] + S2[5];
+  CT S0 = S2[0] + S2[3] + S2[5];
   // sv = sum v,  hq = sum v u^T H u
-  double zSz = 0.0, zHSz = 0.0, hS2 = 0.0;
+  CT zSz = 0, zHSz = 0, hS2 = 0;
 #pragma unroll
   for (int c = 0; c < 3; ++c)
 #pragma unroll
     for (int d = c; d < 3; ++d) {
-      double m = (c == d ? 1.0 : 2.0) * z[c] * z[d];
+      CT m = (c == d ? CT(1) : CT(2)) * z[c] * z[d];
       zSz = fma(m, S2[i2(c, d)], zSz);
       zHSz = fma(m, HS4[i2(c, d)], zHSz);
-      hS2 = fma((c == d ? 1.0 : 2.0) * H[i2(c, d)], S2[i2(c, d)], hS2);
+      hS2 = fma((c == d ? CT(1) : CT(2)) * H[i2(c, d)], S2[i2(c, d)], hS2);
     }
-  double zS1 = z[0] * S1[0] + z[1] * S1[1] + z[2] * S1[2];
-  double zHS3 = z[0] * HS3[0] + z[1] * HS3[1] + z[2] * HS3[2];
-  double sv = k2 * zSz + k1 * zS1 + k0 * S0;
-  double hq = k2 * zHSz + k1 * zHS3 + k0 * hS2;
+  CT zS1 = z[0] * S1[0] + z[1] * S1[1] + z[2] * S1[2];
+  CT zHS3 = z[0] * HS3[0] + z[1] * HS3[1] + z[2] * HS3[2];
+  CT sv = k2 * zSz + k1 * zS1 + k0 * S0;
+  CT hq = k2 * zHSz + k1 * zHS3 + k0 * hS2;
   *val = trH * sv - hq;
 #pragma unroll
   for (int c = 0; c < 3; ++c) {
-    double zS2c = 0.0, zHS4c = 0.0;
+    CT zS2c = 0, zHS4c = 0;
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
       zS2c = fma(z[d], S2[s2(c, d)], zS2c);
       zHS4c = fma(z[d], HS4[s2(c, d)], zHS4c);
     }
-    gz[c] = 2.0 * k2 * (trH * zS2c - zHS4c) + k1 * (trH * S1[c] - HS3[c]);
+    gz[c] = CT(2) * k2 * (trH * zS2c - zHS4c) + k1 * (trH * S1[c] - HS3[c]);
   }
 }
 
 // For the G1 group and a 3-vector om: val = om . b, gz = d val / dz.
-template <typename T>
-__device__ inline void group_b_vjp(const T* R3, const T* R2, const double om[3], const double z[3],
-                                   double k2, double k1, double k0, double* val, double gz[3]) {
-  double oR3[6], oR2[3], r1 = 0.0;
+template <typename CT, typename T>
+__device__ inline void group_b_vjp(const T* R3, const T* R2, const CT om[3], const CT z[3], CT k2,
+                                   CT k1, CT k0, CT* val, CT gz[3]) {
+  CT oR3[6], oR2[3], r1 = 0;
 #pragma unroll
   for (int c = 0; c < 3; ++c)
 #pragma unroll
     for (int d = c; d < 3; ++d) {
-      double acc = 0.0;
+      CT acc = 0;
 #pragma unroll
-      for (int a = 0; a < 3; ++a) acc = fma(om[a], (double)R3[s3(a, c, d)], acc);
+      for (int a = 0; a < 3; ++a) acc = fma(om[a], (CT)R3[s3(a, c, d)], acc);
       oR3[i2(c, d)] = acc;
     }
 #pragma unroll
   for (int c = 0; c < 3; ++c) {
-    double acc = 0.0;
+    CT acc = 0;
 #pragma unroll
-    for (int a = 0; a < 3; ++a) acc = fma(om[a], (double)R2[s2(a, c)], acc);
+    for (int a = 0; a < 3; ++a) acc = fma(om[a], (CT)R2[s2(a, c)], acc);
     oR2[c] = acc;
   }
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
-    double s = 0.0;
+    CT s = 0;
 #pragma unroll
-    for (int c = 0; c < 3; ++c) s += (double)R3[s3(a, c, c)];
+    for (int c = 0; c < 3; ++c) s += (CT)R3[s3(a, c, c)];
     r1 = fma(om[a], s, r1);
   }
-  double zz = 0.0;
+  CT zz = 0;
 #pragma unroll
   for (int c = 0; c < 3; ++c)
 #pragma unroll
-    for (int d = c; d < 3; ++d) zz = fma((c == d ? 1.0 : 2.0) * z[c] * z[d], oR3[i2(c, d)], zz);
-  double zo2 = z[0] * oR2[0] + z[1] * oR2[1] + z[2] * oR2[2];
+    for (int d = c; d < 3; ++d) zz = fma((c == d ? CT(1) : CT(2)) * z[c] * z[d], oR3[i2(c, d)], zz);
+  CT zo2 = z[0] * oR2[0] + z[1] * oR2[1] + z[2] * oR2[2];
   *val = k2 * zz + k1 * zo2 + k0 * r1;
 #pragma unroll
   for (int c = 0; c < 3; ++c) {
-    double s = 0.0;
+    CT s = 0;
 #pragma unroll
     for (int d = 0; d < 3; ++d) s = fma(z[d], oR3[s2(c, d)], s);
-    gz[c] = 2.0 * k2 * s + k1 * oR2[c];
+    gz[c] = CT(2) * k2 * s + k1 * oR2[c];
   }
 }
 
 // <G', X(z)> and its z-gradient for one voxel record, with G' the (already
 // adjoint-shifted) 21-vector; X = camera-frame block without 1/sigma^2.
-template <typename T>
-__device__ inline void corner_vjp(const T* rec, const double Gp[21], const double z[3], double k2,
-                                  double k1, double k0, double* val, double gz[3]) {
-  double HTL[6], HBR[6], om[3];
+template <typename CT, typename T>
+__device__ inline void corner_vjp(const T* rec, const CT Gp[21], const CT z[3], CT k2, CT k1, CT k0,
+                                  CT* val, CT gz[3]) {
+  CT HTL[6], HBR[6], om[3];
 #pragma unroll
   for (int i = 0; i < 3; ++i)
 #pragma unroll
@@ -448,21 +471,43 @@ __device__ inline void corner_vjp(const T* rec, const double Gp[21], const doubl
   om[0] = Gp[u21(2, 4)] - Gp[u21(1, 5)];
   om[1] = Gp[u21(0, 5)] - Gp[u21(2, 3)];
   om[2] = Gp[u21(1, 3)] - Gp[u21(0, 4)];
-  double v2, v0, vb, g2[3], g0[3], gb[3];
-  group_vjp(rec + O_G2_4, rec + O_G2_3, HTL, z, k2, k1, k0, &v2, g2);
-  group_vjp(rec + O_G0_4, rec + O_G0_3, HBR, z, k2, k1, k0, &v0, g0);
-  group_b_vjp(rec + O_G1_3, rec + O_G1_2, om, z, k2, k1, k0, &vb, gb);
-  *val = v2 + v0 - 2.0 * vb;
+  CT v2, v0, vb, g2[3], g0[3], gb[3];
+  group_vjp<CT>(rec + O_G2_4, rec + O_G2_3, HTL, z, k2, k1, k0, &v2, g2);
+  group_vjp<CT>(rec + O_G0_4, rec + O_G0_3, HBR, z, k2, k1, k0, &v0, g0);
+  group_b_vjp<CT>(rec + O_G1_3, rec + O_G1_2, om, z, k2, k1, k0, &vb, gb);
+  *val = v2 + v0 - CT(2) * vb;
 #pragma unroll
-  for (int c = 0; c < 3; ++c) gz[c] = g2[c] + g0[c] - 2.0 * gb[c];
+  for (int c = 0; c < 3; ++c) gz[c] = g2[c] + g0[c] - CT(2) * gb[c];
 }
 
 // ------------------------------------------------------------ 6x6 metrics (FP64)
 
+// 1/sqrt(x) and 1/x for positive normal FP64 x: hardware estimate refined by
+// two Newton steps (quadratic convergence from the estimate's ~2^-26 error).
+__device__ inline double rsq_nr(double x) {
+  double y = __builtin_amdgcn_rsq(x);
+  double r = fma(-x * y, y, 1.0);
+  y = fma(0.5 * y, r, y);
+  r = fma(-x * y, y, 1.0);
+  return fma(0.5 * y, r, y);
+}
+__device__ inline double rcp_nr(double x) {
+  double y = __builtin_amdgcn_rcp(x);
+  double e = fma(-x, y, 1.0);
+  y = fma(y, e, y);
+  e = fma(-x, y, 1.0);
+  return fma(y, e, y);
+}
+
 #define FIF_A(i, j) a[su21((i), (j))]
 
 // Cyclic Jacobi on a symmetric 6x6 held as 21 values.  Sweeps until the
-// off-diagonal mass is below 1e-30 of the Frobenius mass (or 16 sweeps).
+// off-diagonal Frobenius norm is below 1e-11 of the full norm (or 16 sweeps);
+// by Weyl's inequality every diagonal entry is then within that distance of an
+// eigenvalue, far inside the FP64 metric tolerance.
+// Rotation (p, q): t = sgn(d) 2 a_pq / (|d| + sqrt(d^2 + 4 a_pq^2)), d = a_qq - a_pp
+// (the smaller root of t^2 + 2 t theta - 1 = 0, theta = d / (2 a_pq)),
+// c = 1 / sqrt(1 + t^2), s = t c.
 // On return the diagonal of `a` holds the eigenvalues; when WANT_V the
 // columns of V (row-major 36) are the eigenvectors.
 template <bool WANT_V>
@@ -482,21 +527,23 @@ __device__ inline void jacobi6(double a[21], double V[36]) {
     for (int i = 0; i < 6; ++i)
 #pragma unroll
       for (int j = i + 1; j < 6; ++j) off += 2.0 * FIF_A(i, j) * FIF_A(i, j);
-    if (!(off > 1e-30 * fro)) break;
+    if (!(off > 1e-22 * fro)) break;
 #pragma unroll
     for (int p = 0; p < 6; ++p)
 #pragma unroll
       for (int q = p + 1; q < 6; ++q) {
-        double apq = FIF_A(p, q);
-        double app = FIF_A(p, p), aqq = FIF_A(q, q);
-        double theta = (aqq - app) / (2.0 * apq);
-        double at = fabs(theta);
-        double tt = (at > 1e150) ? 0.5 / at : 1.0 / (at + sqrt(fma(at, at, 1.0)));
-        tt = (theta < 0.0) ? -tt : tt;
-        bool skip = (apq == 0.0);
+        const double apq = FIF_A(p, q);
+        const double app = FIF_A(p, p), aqq = FIF_A(q, q);
+        const double d = aqq - app;
+        const double r2 = fma(d, d, 4.0 * apq * apq);
+        const bool skip = !(r2 > 0.0) || (apq == 0.0);
+        const double r2s = skip ? 1.0 : r2;
+        const double r = r2s * rsq_nr(r2s);
+        double tt = 2.0 * apq * rcp_nr(fabs(d) + r);
+        tt = (d < 0.0) ? -tt : tt;
         tt = skip ? 0.0 : tt;
-        double c = 1.0 / sqrt(fma(tt, tt, 1.0));
-        double s = tt * c;
+        const double c = rsq_nr(fma(tt, tt, 1.0));
+        const double s = tt * c;
 #pragma unroll
         for (int k = 0; k < 6; ++k) {
           if (k == p || k == q) continue;
@@ -531,7 +578,7 @@ __device__ inline bool ldlt6(const double F[21], double L[36], double dinv[6], d
     for (int k = 0; k < j; ++k) s -= L[j * 6 + k] * L[j * 6 + k] * d[k];
     d[j] = s;
     pd = pd && (s > 0.0);
-    double inv = 1.0 / s;
+    double inv = (s > 0.0) ? rcp_nr(s) : 1.0 / s;
     dinv[j] = inv;
 #pragma unroll
     for (int i = j + 1; i < 6; ++i) {
@@ -571,6 +618,45 @@ __device__ inline void ldlt6_inverse(const double L[36], const double dinv[6], d
         if (k >= i && k >= j) s = fma(W[k * 6 + i] * dinv[k], W[k * 6 + j], s);
       out[u21(i, j)] = s;
     }
+}
+
+// ------------------------------------------------------------ cross-lane sums
+
+// Sum over aligned groups of 8 lanes with DPP moves (no LDS traffic):
+// quad_perm [1,0,3,2], quad_perm [2,3,0,1], then row_half_mirror (lane i <-> 7-i).
+template <int CTRL>
+__device__ inline float dpp_f32(float x) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), CTRL, 0xF, 0xF, true));
+}
+template <int CTRL>
+__device__ inline double dpp_f64(double x) {
+  int lo = __double2loint(x), hi = __double2hiint(x);
+  lo = __builtin_amdgcn_update_dpp(0, lo, CTRL, 0xF, 0xF, true);
+  hi = __builtin_amdgcn_update_dpp(0, hi, CTRL, 0xF, 0xF, true);
+  return __hiloint2double(hi, lo);
+}
+__device__ inline float sum8(float x) {
+  x += dpp_f32<0xB1>(x);
+  x += dpp_f32<0x4E>(x);
+  x += dpp_f32<0x141>(x);
+  return x;
+}
+__device__ inline double sum8(double x) {
+  x += dpp_f64<0xB1>(x);
+  x += dpp_f64<0x4E>(x);
+  x += dpp_f64<0x141>(x);
+  return x;
+}
+// The same over an array, one butterfly stage at a time across all entries,
+// so consecutive DPP reads never wait on the add just issued.
+template <int N, typename CT>
+__device__ inline void sum8_arr(CT* x) {
+#pragma unroll
+  for (int e = 0; e < N; ++e) x[e] += (sizeof(CT) == 4) ? (CT)dpp_f32<0xB1>((float)x[e]) : (CT)dpp_f64<0xB1>((double)x[e]);
+#pragma unroll
+  for (int e = 0; e < N; ++e) x[e] += (sizeof(CT) == 4) ? (CT)dpp_f32<0x4E>((float)x[e]) : (CT)dpp_f64<0x4E>((double)x[e]);
+#pragma unroll
+  for (int e = 0; e < N; ++e) x[e] += (sizeof(CT) == 4) ? (CT)dpp_f32<0x141>((float)x[e]) : (CT)dpp_f64<0x141>((double)x[e]);
 }
 
 }  // namespace fif

@@ -14,7 +14,8 @@ constexpr uint8_t FL_CLAMPED = 1u, FL_NOT_PD = 2u, FL_TIE = 4u;
 // when GRAD accumulates G = sum_c up[c] d s_c / dF (21, symmetric).
 template <bool GRAD>
 __device__ inline void eval_metrics(const double F[21], uint32_t metrics, double* row,
-                                    uint8_t* flag, const double* up, double G[21]) {
+                                    uint8_t* flag, const double* up, double G[21],
+                                    bool want_pd = true) {
   int col = 0, upc = 0;
   if (GRAD) {
 #pragma unroll
@@ -71,7 +72,7 @@ __device__ inline void eval_metrics(const double F[21], uint32_t metrics, double
         for (int j = i; j < 6; ++j) G[u21(i, j)] = fma(g * v[i], v[j], G[u21(i, j)]);
     }
   }
-  {
+  if (want_pd || (metrics & M_LOGDET)) {
     double L[36], dinv[6], ld;
     bool pd = ldlt6(F, L, dinv, &ld);
     if (!pd) *flag |= FL_NOT_PD;

@@ -18,27 +18,36 @@ namespace fif {
 
 constexpr int kQThreads = 256;
 
+// The 66 moments of a corner voxel: 64 from its main record, 2 from slot
+// `slot` of the cell side record `cell`.
 template <typename FT>
-__device__ inline void load_record(const FT* field, size_t vox, FT rec[kRec]);
+__device__ inline void load_record(const FT* field, size_t nvox, size_t vox, size_t cell,
+                                   int slot, FT rec[kMom]);
 
 template <>
-__device__ inline void load_record<float>(const float* field, size_t vox, float rec[kRec]) {
-  const float4* p = reinterpret_cast<const float4*>(field + vox * kRec);
+__device__ inline void load_record<float>(const float* field, size_t nvox, size_t vox,
+                                          size_t cell, int slot, float rec[kMom]) {
+  const float4* p = reinterpret_cast<const float4*>(field + vox * kMain);
 #pragma unroll
-  for (int i = 0; i < kRec / 4; ++i) {
+  for (int i = 0; i < kMain / 4; ++i) {
     float4 v = p[i];
     rec[4 * i] = v.x; rec[4 * i + 1] = v.y; rec[4 * i + 2] = v.z; rec[4 * i + 3] = v.w;
   }
+  float2 w = *reinterpret_cast<const float2*>(field + nvox * kMain + cell * kSideRec + 2 * slot);
+  rec[kMain] = w.x; rec[kMain + 1] = w.y;
 }
 
 template <>
-__device__ inline void load_record<double>(const double* field, size_t vox, double rec[kRec]) {
-  const double2* p = reinterpret_cast<const double2*>(field + vox * kRec);
+__device__ inline void load_record<double>(const double* field, size_t nvox, size_t vox,
+                                           size_t cell, int slot, double rec[kMom]) {
+  const double2* p = reinterpret_cast<const double2*>(field + vox * kMain);
 #pragma unroll
-  for (int i = 0; i < kRec / 2; ++i) {
+  for (int i = 0; i < kMain / 2; ++i) {
     double2 v = p[i];
     rec[2 * i] = v.x; rec[2 * i + 1] = v.y;
   }
+  double2 w = *reinterpret_cast<const double2*>(field + nvox * kMain + cell * kSideRec + 2 * slot);
+  rec[kMain] = w.x; rec[kMain + 1] = w.y;
 }
 
 struct Corner {
@@ -98,112 +107,181 @@ __device__ inline void load_pose(const QueryArgs& a, int64_t i, double t[3], dou
   quat_axis((double)Q[4 * i], (double)Q[4 * i + 1], (double)Q[4 * i + 2], (double)Q[4 * i + 3], z);
 }
 
+// Per-query data computed once by the lane that owns the query and read by
+// the 8 corner lanes of its group through LDS.
+template <typename CT>
+struct QSlot {
+  CT t[3];   // position (exact copy of the input)
+  CT z[3];   // optical axis
+  CT f[3];   // trilinear fractions
+  CT df[3];  // d f / d t (1/h, or 0 where clamped)
+  int32_t i0[3];
+  int32_t bits;  // bit ax: axis has two voxels; bit 3: clamped; bit 4: nearest mode
+};
+
+template <typename FT>
+__device__ inline QSlot<FT> make_slot(const QueryArgs& a, int64_t i) {
+  QSlot<FT> s;
+  double t[3], z[3];
+  load_pose<FT>(a, i, t, z);
+  const double o[3] = {a.g.ox, a.g.oy, a.g.oz};
+  const int32_t n[3] = {a.g.nx, a.g.ny, a.g.nz};
+  int32_t bits = 0;
+  bool cl = false;
+#pragma unroll
+  for (int ax = 0; ax < 3; ++ax) {
+    s.t[ax] = (FT)t[ax];
+    s.z[ax] = (FT)z[ax];
+    if (a.interp == 1) {
+      bool c;
+      s.i0[ax] = axis_nearest(t[ax], o[ax], a.g.h, n[ax], &c);
+      cl = cl || c;
+      // NaN positions must give NaN results: carry NaN in the fraction
+      s.f[ax] = (FT)(t[ax] - t[ax]);
+      s.df[ax] = 0;
+    } else {
+      AxisCell c = axis_cell(t[ax], o[ax], a.g.h, n[ax]);
+      s.i0[ax] = c.i0;
+      s.f[ax] = (FT)c.f;
+      s.df[ax] = (FT)c.df;
+      bits |= c.step << ax;
+      cl = cl || c.clamped;
+    }
+  }
+  s.bits = bits | (cl ? 8 : 0) | (a.interp == 1 ? 16 : 0);
+  return s;
+}
+
+template <typename CT>
+struct CornerC {
+  size_t vox, cell;
+  CT w, dw[3], dl[3];
+  bool active;
+};
+
+template <typename CT>
+__device__ inline CornerC<CT> slot_corner(const QSlot<CT>& s, const GridDev& g, int j) {
+  CornerC<CT> c;
+  const double o[3] = {g.ox, g.oy, g.oz};
+  int32_t idx[3];
+  CT wc[3], dwc[3];
+  const bool nearest = (s.bits & 16) != 0;
+#pragma unroll
+  for (int ax = 0; ax < 3; ++ax) {
+    const int b = (j >> ax) & 1;
+    const int step = (s.bits >> ax) & 1;
+    idx[ax] = s.i0[ax] + b * step;
+    wc[ax] = nearest ? CT(1) + s.f[ax] : (b ? s.f[ax] : CT(1) - s.f[ax]);
+    dwc[ax] = b ? s.df[ax] : -s.df[ax];
+  }
+  c.active = !nearest || j == 0;
+  c.w = wc[0] * wc[1] * wc[2];
+  c.dw[0] = dwc[0] * wc[1] * wc[2];
+  c.dw[1] = wc[0] * dwc[1] * wc[2];
+  c.dw[2] = wc[0] * wc[1] * dwc[2];
+  c.vox = (size_t)idx[0] + (size_t)g.nx * ((size_t)idx[1] + (size_t)g.ny * (size_t)idx[2]);
+  c.cell = (size_t)s.i0[0] + (size_t)g.nx * ((size_t)s.i0[1] + (size_t)g.ny * (size_t)s.i0[2]);
+#pragma unroll
+  for (int ax = 0; ax < 3; ++ax)
+    c.dl[ax] = (CT)((o[ax] + (double)idx[ax] * g.h) - (double)s.t[ax]);
+  return c;
+}
+
 template <typename FT, bool GRAD>
 __global__ __launch_bounds__(kQThreads) void query_info_kernel(QueryArgs a) {
-  const int lane = threadIdx.x & 63;
+  using CT = FT;  // corner arithmetic in the field's precision; metrics in FP64
+  __shared__ QSlot<CT> s_q[kQThreads];
+  __shared__ CT s_g[GRAD ? kQThreads : 1][21];
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
   const int grp = lane >> 3, j = lane & 7;
-  const int64_t wbase = ((int64_t)blockIdx.x * (kQThreads / 64) + (threadIdx.x >> 6)) * 64;
+  const int wbase = tid & ~63;
+  const int64_t qown = (int64_t)blockIdx.x * kQThreads + tid;
+  const bool valid = qown < a.m;
+  const int64_t ql = valid ? qown : a.m - 1;
   const FT* field = reinterpret_cast<const FT*>(a.field);
-  const double k2 = a.vis.k2, k1 = a.vis.k1, k0 = a.vis.k0;
+  const size_t nvox = (size_t)a.g.nx * a.g.ny * a.g.nz;
+  const CT k2 = (CT)a.vis.k2, k1 = (CT)a.vis.k1, k0 = (CT)a.vis.k0;
 
-  double Z[21];
-  bool clamped = false;
+  s_q[tid] = make_slot<FT>(a, ql);
+  __syncthreads();
+
+  CT Z[21];
 #pragma unroll
-  for (int e = 0; e < 21; ++e) Z[e] = 0.0;
-
+  for (int e = 0; e < 21; ++e) Z[e] = 0;
   for (int it = 0; it < 8; ++it) {
-    int64_t qi = wbase + grp * 8 + it;
-    qi = qi < a.m ? qi : a.m - 1;
-    double t[3], z[3];
-    load_pose<FT>(a, qi, t, z);
-    Corner c = make_corner(a.g, t, j, a.interp);
-    double Y[21];
+    const QSlot<CT> sl = s_q[wbase + grp * 8 + it];
+    const CornerC<CT> c = slot_corner(sl, a.g, j);
+    CT Y[21];
     if (c.active) {
-      FT rec[kRec];
-      load_record<FT>(field, c.vox, rec);
-      corner_fim<FT>(rec, z, k2, k1, k0, c.dl, Y);
+      FT rec[kMom];
+      load_record<FT>(field, nvox, c.vox, c.cell, j, rec);
+      corner_fim<CT>(rec, vis_weights<CT>(sl.z, k2, k1, k0), c.dl, Y);
 #pragma unroll
       for (int e = 0; e < 21; ++e) Y[e] *= c.w;
     } else {
 #pragma unroll
-      for (int e = 0; e < 21; ++e) Y[e] = 0.0;
+      for (int e = 0; e < 21; ++e) Y[e] = 0;
     }
+    sum8_arr<21>(Y);
 #pragma unroll
-    for (int e = 0; e < 21; ++e) {
-      Y[e] += __shfl_xor(Y[e], 1, 8);
-      Y[e] += __shfl_xor(Y[e], 2, 8);
-      Y[e] += __shfl_xor(Y[e], 4, 8);
-    }
-    if (j == it) {
-#pragma unroll
-      for (int e = 0; e < 21; ++e) Z[e] = Y[e];
-      clamped = c.clamped;
-    }
+    for (int e = 0; e < 21; ++e) Z[e] = (j == it) ? Y[e] : Z[e];
   }
 
-  const int64_t qown = wbase + lane;
-  const bool valid = qown < a.m;
-  const int64_t ql = valid ? qown : a.m - 1;
-  double t[3], z[3];
-  load_pose<FT>(a, ql, t, z);
-  double F[21];
-  shift21(Z, t, F);
+  const QSlot<CT> own = s_q[tid];
+  double td[3] = {(double)own.t[0], (double)own.t[1], (double)own.t[2]};
+  double Zd[21], F[21];
+#pragma unroll
+  for (int e = 0; e < 21; ++e) Zd[e] = (double)Z[e];
+  shift21<double>(Zd, td, F);
 #pragma unroll
   for (int e = 0; e < 21; ++e) F[e] *= a.vis.inv_s2;
 
-  uint8_t flag = clamped ? FL_CLAMPED : 0;
+  uint8_t flag = (own.bits & 8) ? FL_CLAMPED : 0;
   double G[GRAD ? 21 : 1];
-  int nmet = (int)((a.metrics & 1u) != 0) + (int)((a.metrics & 2u) != 0) +
-             (int)((a.metrics & 4u) != 0);
+  const int nmet = (int)((a.metrics & 1u) != 0) + (int)((a.metrics & 2u) != 0) +
+                   (int)((a.metrics & 4u) != 0);
   double up[3] = {0.0, 0.0, 0.0};
   if (GRAD) {
-    for (int c = 0; c < nmet; ++c) up[c] = valid ? a.dL_dout[ql * nmet + c] : 0.0;
+    for (int m = 0; m < nmet; ++m) up[m] = valid ? a.dL_dout[ql * nmet + m] : 0.0;
   }
   double* row = (valid && a.out) ? a.out + ql * a.ncols : nullptr;
-  eval_metrics<GRAD>(F, a.metrics, row, &flag, up, G);
+  eval_metrics<GRAD>(F, a.metrics, row, &flag, up, G, a.flags != nullptr);
   if (valid && a.flags) a.flags[ql] = flag;
   if (!GRAD) return;
 
   // ------------------------------------------------------------ backward
-  double Gt[21];
-  if (GRAD) {
-    shift21_adj(G, t, Gt);
+  {
+    double Gt[21];
+    shift21_adj<double>(G, td, Gt);
 #pragma unroll
-    for (int e = 0; e < 21; ++e) Gt[e] = valid ? Gt[e] * a.vis.inv_s2 : 0.0;
+    for (int e = 0; e < 21; ++e) s_g[GRAD ? tid : 0][e] = (CT)(valid ? Gt[e] * a.vis.inv_s2 : 0.0);
   }
-  double keep[6] = {0, 0, 0, 0, 0, 0};
+  __syncthreads();
+  CT keep[6] = {0, 0, 0, 0, 0, 0};
   for (int it = 0; it < 8; ++it) {
-    const int src = (lane & ~7) | it;
-    double Gb[21];
+    const int src = wbase + grp * 8 + it;
+    const QSlot<CT> sl = s_q[src];
+    CT Gb[21];
 #pragma unroll
-    for (int e = 0; e < 21; ++e) Gb[e] = __shfl(Gt[e], src, 64);
-    int64_t qi = wbase + grp * 8 + it;
-    qi = qi < a.m ? qi : a.m - 1;
-    double tq[3], zq[3];
-    load_pose<FT>(a, qi, tq, zq);
-    Corner c = make_corner(a.g, tq, j, 0);
-    FT rec[kRec];
-    load_record<FT>(field, c.vox, rec);
-    double Gp[21];
-    shift21_adj(Gb, c.dl, Gp);
-    double val, gz[3];
-    corner_vjp<FT>(rec, Gp, zq, k2, k1, k0, &val, gz);
-    double r[6] = {c.dw[0] * val, c.dw[1] * val, c.dw[2] * val,
-                   c.w * gz[0], c.w * gz[1], c.w * gz[2]};
+    for (int e = 0; e < 21; ++e) Gb[e] = s_g[GRAD ? src : 0][e];
+    const CornerC<CT> c = slot_corner(sl, a.g, j);
+    FT rec[kMom];
+    load_record<FT>(field, nvox, c.vox, c.cell, j, rec);
+    CT Gp[21];
+    shift21_adj<CT>(Gb, c.dl, Gp);
+    CT val, gz[3];
+    corner_vjp<CT>(rec, Gp, sl.z, k2, k1, k0, &val, gz);
+    CT r[6] = {c.dw[0] * val, c.dw[1] * val, c.dw[2] * val, c.w * gz[0], c.w * gz[1], c.w * gz[2]};
+    sum8_arr<6>(r);
 #pragma unroll
-    for (int e = 0; e < 6; ++e) {
-      r[e] += __shfl_xor(r[e], 1, 8);
-      r[e] += __shfl_xor(r[e], 2, 8);
-      r[e] += __shfl_xor(r[e], 4, 8);
-    }
-    if (j == it) {
-#pragma unroll
-      for (int e = 0; e < 6; ++e) keep[e] = r[e];
-    }
+    for (int e = 0; e < 6; ++e) keep[e] = (j == it) ? r[e] : keep[e];
   }
   if (!valid) return;
-  double gphi[3] = {z[1] * keep[5] - z[2] * keep[4], z[2] * keep[3] - z[0] * keep[5],
-                    z[0] * keep[4] - z[1] * keep[3]};
+  const CT* z = own.z;
+  CT gphi[3] = {z[1] * keep[5] - z[2] * keep[4], z[2] * keep[3] - z[0] * keep[5],
+                z[0] * keep[4] - z[1] * keep[3]};
   FT* gt_out = reinterpret_cast<FT*>(a.dL_dt);
   FT* gp_out = reinterpret_cast<FT*>(a.dL_dphi);
 #pragma unroll
@@ -283,7 +361,8 @@ __global__ void export_info_kernel(ExportArgs a) {
   const int64_t ix = v % a.g.nx, iy = (v / a.g.nx) % a.g.ny, iz = v / ((int64_t)a.g.nx * a.g.ny);
   const double tv[3] = {a.g.ox + (double)ix * a.g.h, a.g.oy + (double)iy * a.g.h,
                         a.g.oz + (double)iz * a.g.h};
-  const FT* rec = reinterpret_cast<const FT*>(a.field) + (size_t)v * kRec;
+  FT rec[kMom];
+  load_record<FT>(reinterpret_cast<const FT*>(a.field), (size_t)nvox, (size_t)v, (size_t)v, 0, rec);
   double S4[15], S3[10], S2[6], S1[3], S0;   // G0
   double T4[15], T3[10], T2[6], T1[3], T0;   // G2
   expand_group<FT>(rec + O_G0_4, rec + O_G0_3, S4, S3, S2, S1, &S0);

@@ -48,8 +48,8 @@ def test_library_exports_every_declared_symbol():
 def test_field_bytes_and_status_strings():
     fif, L = _lib()
     g = fif.Grid((0.0, 0.0, 0.0), 0.5, (20, 20, 6))
-    assert fif.field_bytes(g, fif.FP32_COMP) == 2400 * 68 * 4
-    assert fif.field_bytes(g, fif.FP64) == 2400 * 68 * 8
+    assert fif.field_bytes(g, fif.FP32_COMP) == 2400 * 80 * 4
+    assert fif.field_bytes(g, fif.FP64) == 2400 * 80 * 8
     assert fif.field_bytes(g, fif.FP32_NAIVE, fif.KIND_TRACE) == 2400 * 12 * 4
     bad = fif.Grid((0.0, 0.0, 0.0), -1.0, (20, 20, 6))
     assert fif.field_bytes(bad, fif.FP64) == 0
