@@ -32,13 +32,16 @@ __device__ inline void two_sum_into(float& hi, float& lo, float x) {
   lo += err;
 }
 
-// Accumulate one landmark's contribution into the 66 moments.
+// Accumulate one landmark's contribution into the 66 moments.  Degree-4
+// monomials are never formed: each is a degree-3 monomial times one
+// component, folded into the two FMAs that consume it.
 template <typename T>
 __device__ inline void info_pair(T acc[kMom], T dx, T dy, T dz, T rn) {
   T ux = dx * rn, uy = dy * rn, uz = dz * rn;
   T rn2 = rn * rn;
   T u[3] = {ux, uy, uz};
-  T m2[6], m3[10], m4[15];
+  T u2n[3] = {ux * rn2, uy * rn2, uz * rn2};
+  T m2[6], m3[10];
 #pragma unroll
   for (int a = 0; a < 3; ++a)
 #pragma unroll
@@ -56,12 +59,11 @@ __device__ inline void info_pair(T acc[kMom], T dx, T dy, T dz, T rn) {
 #pragma unroll
       for (int c = b; c < 3; ++c)
 #pragma unroll
-        for (int d = c; d < 3; ++d) m4[i4(a, b, c, d)] = m3[i3(a, b, c)] * u[d];
-#pragma unroll
-  for (int i = 0; i < 15; ++i) {
-    acc[O_G0_4 + i] += m4[i];
-    acc[O_G2_4 + i] = fma(m4[i], rn2, acc[O_G2_4 + i]);
-  }
+        for (int d = c; d < 3; ++d) {
+          const int k = i4(a, b, c, d);
+          acc[O_G0_4 + k] = fma(m3[i3(a, b, c)], u[d], acc[O_G0_4 + k]);
+          acc[O_G2_4 + k] = fma(m3[i3(a, b, c)], u2n[d], acc[O_G2_4 + k]);
+        }
 #pragma unroll
   for (int i = 0; i < 10; ++i) {
     acc[O_G0_3 + i] += m3[i];
@@ -164,21 +166,29 @@ __global__ __launch_bounds__(kBuildThreads) void build_kernel(BuildArgs a) {
       s_lm[tid] = v;
     }
     __syncthreads();
-    for (int i = 0; i < nb; ++i) {
-      const L4 p = s_lm[i];
-      // V_t range test in FP32 (same decision in every precision)
-      float ddx = (float)p.x - fx, ddy = (float)p.y - fy, ddz = (float)p.z - fz;
-      float n2 = __fmaf_rn(ddz, ddz, __fmaf_rn(ddy, ddy, ddx * ddx));
-      bool in = valid && (n2 >= a.lo2) && (n2 <= a.hi2);
-      if (in) {
-        T dx = p.x - vx, dy = p.y - vy, dz = p.z - vz;
-        T nn = (PREC == 2) ? (T)fma((double)dz, (double)dz, fma((double)dy, (double)dy, (double)dx * dx))
-                           : (T)n2;
-        T rn = inv_sqrt<T>(nn);
-        if constexpr (KIND == 0)
-          info_pair<T>(acc, dx, dy, dz, rn);
-        else
-          trace_pair<T>(acc, dx, dy, dz, rn, p.x, p.y, p.z, p.w);
+    // landmarks in groups of 4: the LDS reads of a group are issued together
+    for (int i0 = 0; i0 < nb; i0 += 4) {
+      L4 pg[4];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) pg[k] = s_lm[(i0 + k < nb) ? i0 + k : i0];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const L4 p = pg[k];
+        // V_t range test in FP32 (same decision in every precision)
+        float ddx = (float)p.x - fx, ddy = (float)p.y - fy, ddz = (float)p.z - fz;
+        float n2 = __fmaf_rn(ddz, ddz, __fmaf_rn(ddy, ddy, ddx * ddx));
+        bool in = valid && (i0 + k < nb) && (n2 >= a.lo2) && (n2 <= a.hi2);
+        if (in) {
+          T dx = p.x - vx, dy = p.y - vy, dz = p.z - vz;
+          T nn = (PREC == 2)
+                     ? (T)fma((double)dz, (double)dz, fma((double)dy, (double)dy, (double)dx * dx))
+                     : (T)n2;
+          T rn = inv_sqrt<T>(nn);
+          if constexpr (KIND == 0)
+            info_pair<T>(acc, dx, dy, dz, rn);
+          else
+            trace_pair<T>(acc, dx, dy, dz, rn, p.x, p.y, p.z, p.w);
+        }
       }
     }
     if (COMP) {

@@ -69,28 +69,38 @@ __global__ __launch_bounds__(kPcThreads) void pc_kernel(PcArgs a) {
       s_lm[tid] = v;
     }
     __syncthreads();
-    for (int i = 0; i < nb; ++i) {
-      const L4 p = s_lm[i];
-      float ddx = (float)p.x - ftx, ddy = (float)p.y - fty, ddz = (float)p.z - ftz;
-      float n2 = __fmaf_rn(ddz, ddz, __fmaf_rn(ddy, ddy, ddx * ddx));
-      bool in = valid && (n2 >= a.lo2) && (n2 <= a.hi2);
-      T dx = p.x - tx, dy = p.y - ty, dz = p.z - tz;
-      T w = T(0);
-      if (EXACT) {
-        T pcx = R[0] * dx + R[3] * dy + R[6] * dz;
-        T pcy = R[1] * dx + R[4] * dy + R[7] * dz;
-        T pcz = R[2] * dx + R[5] * dy + R[8] * dz;
-        T u = fx * pcx / pcz + cx;
-        T v = fy * pcy / pcz + cy;
-        bool vis = (pcz > T(0)) && (u >= T(0)) && (u < W) && (v >= T(0)) && (v < H);
-        in = in && vis;
-        w = T(1);
+    // Per 64-landmark slice: test every landmark into a per-lane bit mask,
+    // then each lane walks only its own set bits (its landmarks in range and,
+    // in exact mode, in view), so lanes do not wait on each other's work.
+    for (int s0 = 0; s0 < nb; s0 += 64) {
+      const int ns = (nb - s0) < 64 ? (nb - s0) : 64;
+      uint64_t mask = 0;
+      for (int i = 0; i < ns; ++i) {
+        const L4 p = s_lm[s0 + i];
+        float ddx = (float)p.x - ftx, ddy = (float)p.y - fty, ddz = (float)p.z - ftz;
+        float n2 = __fmaf_rn(ddz, ddz, __fmaf_rn(ddy, ddy, ddx * ddx));
+        bool in = valid && (n2 >= a.lo2) && (n2 <= a.hi2);
+        if (EXACT) {
+          T dx = p.x - tx, dy = p.y - ty, dz = p.z - tz;
+          T pcx = R[0] * dx + R[3] * dy + R[6] * dz;
+          T pcy = R[1] * dx + R[4] * dy + R[7] * dz;
+          T pcz = R[2] * dx + R[5] * dy + R[8] * dz;
+          T u = fx * pcx / pcz + cx;
+          T v = fy * pcy / pcz + cy;
+          in = in && (pcz > T(0)) && (u >= T(0)) && (u < W) && (v >= T(0)) && (v < H);
+        }
+        mask |= (uint64_t)in << i;
       }
-      if (in) {
+      while (mask) {
+        const int i = __ffsll((unsigned long long)mask) - 1;
+        mask &= mask - 1;
+        const L4 p = s_lm[s0 + i];
+        T dx = p.x - tx, dy = p.y - ty, dz = p.z - tz;
         T nn = (PREC == 2) ? (T)fma((double)dz, (double)dz, fma((double)dy, (double)dy, (double)dx * dx))
-                           : (T)n2;
+                           : (T)__fmaf_rn((float)dz, (float)dz, __fmaf_rn((float)dy, (float)dy, (float)dx * (float)dx));
         T rn = (PREC == 2) ? (T)(1.0 / sqrt((double)nn)) : (T)rsqrtf((float)nn);
         T ux = dx * rn, uy = dy * rn, uz = dz * rn;
+        T w = T(1);
         if (!EXACT) {
           T c = zx * ux + zy * uy + zz * uz;
           w = fma(fma(k2, c, k1), c, k0);
