@@ -71,6 +71,25 @@ def cpu_model():
     return platform.processor() or "unknown"
 
 
+def counter_traffic(kernel):
+    """HBM bytes per launch from the committed rocprofv3 counters, or None when
+    the kernel sources changed since they were taken."""
+    import glob
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "counters.json")
+    if not os.path.exists(path):
+        return None
+    rec = json.load(open(path))
+    h = hashlib.sha256()
+    for f in sorted(glob.glob(os.path.join(ROOT, "paper_2008_03324_amd", "csrc", "*"))):
+        if os.path.isfile(f):
+            h.update(open(f, "rb").read())
+    if h.hexdigest()[:16] != rec.get("src_hash"):
+        return None
+    gb = rec.get("traffic_GB_per_launch", {}).get(kernel)
+    return None if gb is None else gb * 1e9
+
+
 def contributing_fraction(torch, lm_d, grid, r_max, n_sample=32768, seed=7):
     """Fraction of (voxel, landmark) pairs inside the range (sampled voxels)."""
     g = torch.Generator(device="cpu").manual_seed(seed)
@@ -208,8 +227,9 @@ def main():
         "grad_poses_per_s": mg / (med["grad"] / 1e3),
         "roofline": {"kernel": "query_info_kernel<float>", "bound": "hbm",
                      "achieved": q_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": q_gbs / HBM_PEAK_GBS, "traffic": None,
-                     "bytes_per_query": q_bytes / m},
+                     "frac": q_gbs / HBM_PEAK_GBS,
+                     "traffic": counter_traffic("fif::query_info_kernel<float, false>"),
+                     "algorithmic_bytes": q_bytes, "bytes_per_query": q_bytes / m},
         "roofline_build": {"kernel": "build_kernel<FP32_COMP>", "bound": "fp32 valu",
                            "achieved": b_tfs, "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
                            "frac": b_tfs / FP32_PEAK_TFLOPS},
