@@ -54,6 +54,9 @@ def parse():
     ap.add_argument("--phases", default="build,query,grad,pc",
                     help="comma list of phases to run in each step")
     ap.add_argument("--cpu-sample", type=int, default=2048, help="poses in the oracle sample")
+    ap.add_argument("--no-serve", action="store_true", help="skip the serving leg")
+    ap.add_argument("--serve-seconds", type=float, default=2.0,
+                    help="length of each Poisson stream of the serving leg")
     return ap.parse_args()
 
 
@@ -244,10 +247,79 @@ def main():
                               "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s"}
         res["roofline_pc"]["frac"] = res["roofline_pc"]["achieved"] / FP32_PEAK_TFLOPS
 
+    if not args.no_serve:
+        res["serving"] = serve_leg(args, fif, torch)
+        res["p99_ms_at_60pct_load"] = res["serving"]["rates"][1]["batched"]["p99_ms"]
+
     # ------------------------------------------------ accuracy + CPU baseline
     if not args.no_cpu:
         res.update(cpu_leg(args, fif, torch, lm, g, v, t, q, out, pc_out, metrics))
     print(json.dumps(res), flush=True)
+
+
+def serve_leg(args, fif, torch):
+    """Four resident fields under Poisson streams at 30/60/90 % of the batched
+    loop's saturation rate; continuous batching + hipGraphs versus one request
+    per launch (one stream, no graphs, no co-batching)."""
+    import scenes
+    from paper_2008_03324_amd import serve
+    dev = torch.device("cuda:0")
+    fields, pools = [], []
+    for i, (lm, g, v) in enumerate(scenes.serve_scenes()):
+        grid = fif.Grid(g.origin, g.h, g.shape)
+        vis = fif.Vis(v.half_fov, v.v_alpha, v.sigma, v.r_min, v.r_max)
+        fields.append(fif.build(torch.tensor(lm, device=dev), grid, vis, prec=fif.FP32_COMP))
+        pt, pq = scenes.building_poses(g, 262_144, seed=3000 + i)
+        tt, tq = scenes.trajectories(g, 1024, 64, seed=4000 + i)
+        pools.append({"plan": (torch.from_numpy(pt).to(dev), torch.from_numpy(pq).to(dev)),
+                      "opt": (torch.from_numpy(tt.reshape(-1, 3)).to(dev),
+                              torch.from_numpy(tq.reshape(-1, 4)).to(dev))})
+    torch.cuda.synchronize()
+    hbm = sum(f.nbytes for f in fields)
+    log(f"serving: 4 fields resident ({hbm / 1e9:.2f} GB)")
+
+    def make(specs):
+        reqs = []
+        for sp in specs:
+            t, q = pools[sp.field][sp.kind]
+            reqs.append(serve.Request(sp.rid, sp.arrival, sp.field, sp.kind,
+                                      t[sp.offset:sp.offset + sp.m], q[sp.offset:sp.offset + sp.m]))
+        return reqs
+
+    batched = serve.Server(fields, n_streams=4, max_inflight=64, hbm_budget=2 << 30)
+    batched.warmup()
+    single = serve.Server(fields, n_streams=1, max_inflight=1, use_graphs=False, co_batch=False)
+    # saturation of the batched loop: every request available at t = 0
+    n_sat = 4000
+    sat_reqs = make(scenes.request_stream(4, 1e9, n_sat, 262_144, 1024, seed=5000))
+    batched.run(sat_reqs, realtime=False)
+    el = batched.run(sat_reqs, realtime=False)
+    sat_rate = n_sat / el
+    sat_poses = sum(r.m for r in sat_reqs) / el
+    el1 = single.run(sat_reqs[:1000], realtime=False)
+    single_rate = 1000 / el1
+    log(f"serving saturation: batched {sat_rate:.0f} req/s ({sat_poses / 1e6:.1f} M poses/s), "
+        f"one-request-per-launch {single_rate:.0f} req/s")
+    rates = []
+    for k, frac in enumerate((0.3, 0.6, 0.9)):
+        rate = frac * sat_rate
+        n = max(200, int(rate * args.serve_seconds))
+        specs = scenes.request_stream(4, rate, n, 262_144, 1024, seed=6000 + k)
+        entry = {"load_fraction": frac, "rate_req_per_s": rate, "requests": n}
+        for name, srv in (("batched", batched), ("one_per_launch", single)):
+            reqs = make(specs)
+            el = srv.run(reqs, realtime=True)
+            st = serve.latency_stats(reqs)
+            st["throughput_req_per_s"] = n / el
+            st["throughput_poses_per_s"] = sum(r.m for r in reqs) / el
+            entry[name] = st
+        log(f"serving {int(frac * 100)}%: batched p50 {entry['batched']['p50_ms']:.2f} ms "
+            f"p99 {entry['batched']['p99_ms']:.2f} ms; one-per-launch p50 "
+            f"{entry['one_per_launch']['p50_ms']:.2f} ms p99 {entry['one_per_launch']['p99_ms']:.2f} ms")
+        rates.append(entry)
+    return {"fields": [list(f.grid.shape) for f in fields], "field_bytes": hbm,
+            "saturation_req_per_s": sat_rate, "saturation_poses_per_s": sat_poses,
+            "one_per_launch_saturation_req_per_s": single_rate, "rates": rates}
 
 
 def cpu_leg(args, fif, torch, lm, g, v, t, q, out, pc_out, metrics):

@@ -130,7 +130,11 @@ __device__ inline QSlot<FT> make_slot(const QueryArgs& a, int64_t i) {
   bool cl = false;
 #pragma unroll
   for (int ax = 0; ax < 3; ++ax) {
-    s.t[ax] = (FT)t[ax];
+    // Frame point of the per-corner shifts: the position clamped to the hull of
+    // voxel centres (the result does not depend on it in exact arithmetic; the
+    // clamped point keeps the shifts no longer than a cell diagonal).
+    const double hi = o[ax] + (double)(n[ax] - 1) * a.g.h;
+    s.t[ax] = (FT)fmin(fmax(t[ax], o[ax]), hi);
     s.z[ax] = (FT)z[ax];
     if (a.interp == 1) {
       bool c;

@@ -239,40 +239,36 @@ def serve_scenes(n_landmarks: int = 100_000, seed: int = SEED_SCENE + 5, h: floa
     return out
 
 
-@dataclasses.dataclass
-class Request:
+@dataclasses.dataclass(frozen=True)
+class RequestSpec:
     rid: int
     arrival: float  # seconds from stream start
     field: int
-    kind: str  # "plan" (queries only) or "opt" (queries + gradients)
-    t: np.ndarray
-    q: np.ndarray
+    kind: str       # "plan" (queries only) or "opt" (queries + gradients)
+    offset: int     # first pose in the field's pool for this kind
+    m: int          # number of poses
 
 
-def request_stream(grids, rate_hz: float, duration_s: float, seed: int = SEED_POSES + 5,
-                   dtype=np.float32, max_requests=None):
-    """Poisson arrivals; half planner batches (1-256 random poses), half
-    optimizer batches (8-64 trajectories x 64 poses); field chosen uniformly."""
+def request_stream(n_fields: int, rate_hz: float, n_requests: int, plan_pool: int,
+                   traj_pool: int, n_poses_traj: int = 64, seed: int = SEED_POSES + 5):
+    """Poisson arrivals at `rate_hz`; half planner batches of 1-256 random poses,
+    half optimizer batches of 8-64 trajectories x `n_poses_traj` poses; the
+    field is chosen uniformly.  Poses are slices of per-field pools: the
+    planner pool holds `plan_pool` random poses, the trajectory pool
+    `traj_pool` whole trajectories."""
     rng = np.random.default_rng(seed)
-    reqs = []
-    t_now = 0.0
-    rid = 0
-    while True:
-        t_now += rng.exponential(1.0 / rate_hz)
-        if t_now > duration_s or (max_requests is not None and rid >= max_requests):
-            break
-        f = int(rng.integers(len(grids)))
-        g = grids[f]
+    gaps = rng.exponential(1.0 / rate_hz, n_requests)
+    arrivals = np.cumsum(gaps) - gaps[0]
+    out = []
+    for rid in range(n_requests):
+        f = int(rng.integers(n_fields))
         if rng.random() < 0.5:
             m = int(rng.integers(1, 257))
-            tt = uniform_in_hull(rng, g, m)
-            qq = haar_quaternions(rng, m)
-            kind = "plan"
+            off = int(rng.integers(0, plan_pool - m + 1))
+            out.append(RequestSpec(rid, float(arrivals[rid]), f, "plan", off, m))
         else:
             ntr = int(rng.integers(8, 65))
-            tt, qq = trajectories(g, ntr, 64, seed=int(rng.integers(1 << 31)), dtype=np.float64)
-            tt, qq = tt.reshape(-1, 3), qq.reshape(-1, 4)
-            kind = "opt"
-        reqs.append(Request(rid, t_now, f, kind, tt.astype(dtype), qq.astype(dtype)))
-        rid += 1
-    return reqs
+            first = int(rng.integers(0, traj_pool - ntr + 1))
+            out.append(RequestSpec(rid, float(arrivals[rid]), f, "opt", first * n_poses_traj,
+                                   ntr * n_poses_traj))
+    return out

@@ -1,0 +1,235 @@
+"""GPU parity at the building workload's full size (100k landmarks, 200x200x50
+voxels, 10M poses, the launch configuration bench.py times), on outputs the
+oracle computes one by one, plus properties that hold at any size and the edge
+cases of the method.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+import scenes
+from fifcheck import block_rel_err, e_fim, metric_errors, upper21
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+M7 = 7
+
+
+@pytest.fixture(scope="module")
+def fif():
+    import paper_2008_03324_amd as fif
+    fif.lib()
+    return fif
+
+
+@pytest.fixture(scope="module")
+def bld(fif):
+    print("case: building scene, FP32_COMP field, 10M poses", flush=True)
+    lm, g, v = scenes.building_scene()
+    grid = fif.Grid(g.origin, g.h, g.shape)
+    vis = fif.Vis(v.half_fov, v.v_alpha, v.sigma, v.r_min, v.r_max)
+    t, q = scenes.building_poses(g, 10_000_000)
+    lm_d = torch.tensor(lm, dtype=torch.float64, device="cuda")
+    field = fif.build(lm_d, grid, vis, prec=fif.FP32_COMP)
+    t_d, q_d = torch.from_numpy(t).cuda(), torch.from_numpy(q).cuda()
+    out, flags = fif.query(field, t_d, q_d, M7, want_flags=True)
+    torch.cuda.synchronize()
+    return dict(lm=lm, g=g, v=v, grid=grid, vis=vis, t=t, q=q, lm_d=lm_d, field=field,
+                t_d=t_d, q_d=q_d, out=out, flags=flags)
+
+
+def _oracle_field(b, t64):
+    g, v = b["g"], b["v"]
+    ids = oracle.corner_voxels(g.origin, g.h, g.shape, t64)
+    C = oracle.build(b["lm"], g.origin, g.h, g.shape, v.sigma, v.r_min, v.r_max, voxel_ids=ids)
+    return oracle.Field(C, g.origin, g.h, g.shape, voxel_ids=ids)
+
+
+def test_full_size_queries_sampled_vs_oracle(bld):
+    rng = np.random.default_rng(21)
+    pick = rng.choice(bld["t"].shape[0], 384, replace=False)
+    t64 = bld["t"][pick].astype(np.float64)
+    q64 = bld["q"][pick].astype(np.float64)
+    of = _oracle_field(bld, t64)
+    v = bld["v"]
+    ref, rflags = oracle.query(of, v.half_fov, v.v_alpha, t64, q64, M7 | 8, 0)
+    gpu = bld["out"][torch.from_numpy(pick).cuda()].cpu().numpy()
+    err = metric_errors(gpu, ref[:, :3], ref[:, 3:])
+    print({k: float(np.max(x)) for k, x in err.items()})
+    assert err["trace_rel"].max() <= 1e-3
+    assert err["lmin_weyl"].max() <= 1e-3
+    assert err["lmin_rel"].max() <= 1e-3
+    assert err["logdet_abs"].max() <= 1e-3
+    gflags = bld["flags"][torch.from_numpy(pick).cuda()].cpu().numpy()
+    np.testing.assert_array_equal(gflags & 3, rflags & 3)
+
+
+def test_full_size_properties(bld):
+    """At any size: finite outputs, trace > 0, PSD (v_alpha = 0.8), lmin <= trace/6,
+    logdet <= 6 log(trace/6) (AM-GM), no clamping inside the hull."""
+    out = bld["out"]
+    tr, lmin, ld = out[:, 0], out[:, 1], out[:, 2]
+    assert bool(torch.isfinite(out).all())
+    assert bool((tr > 0).all())
+    assert bool((lmin >= -1e-6 * tr).all())
+    assert bool((lmin <= tr / 6 * (1 + 1e-9)).all())
+    assert bool((ld <= 6 * torch.log(tr / 6) + 1e-6).all())
+    assert int((bld["flags"] & 1).sum()) == 0
+
+
+def test_full_size_blocks_sampled_vs_oracle(fif, bld):
+    rng = np.random.default_rng(22)
+    ids = np.sort(rng.choice(bld["grid"].n_voxels, 200, replace=False))
+    g, v = bld["g"], bld["v"]
+    C = oracle.build(bld["lm"], g.origin, g.h, g.shape, v.sigma, v.r_min, v.r_max, voxel_ids=ids)
+    blocks = fif.export_blocks(bld["field"], torch.from_numpy(ids).cuda()).cpu().numpy()
+    err = block_rel_err(blocks, C)
+    print("building FP32_COMP block err max", err.max(), "median", np.median(err))
+    assert err.max() <= 1e-3
+
+
+def test_point_cloud_sampled_vs_oracle(fif, bld):
+    rng = np.random.default_rng(23)
+    pick = rng.choice(bld["t"].shape[0], 256, replace=False)
+    idx = torch.from_numpy(pick).cuda()
+    t32, q32 = bld["t_d"][idx].contiguous(), bld["q_d"][idx].contiguous()
+    out = fif.pc_query(bld["lm_d"], bld["vis"], t32, q32, M7 | 8, prec=fif.FP32_COMP).cpu().numpy()
+    v = bld["v"]
+    ref = oracle.pc_query(bld["lm"], v.half_fov, v.v_alpha, v.sigma, v.r_min, v.r_max,
+                          bld["t"][pick].astype(np.float64), bld["q"][pick].astype(np.float64),
+                          M7 | 8)
+    err = metric_errors(out[:, :3], ref[:, :3], ref[:, 3:])
+    assert err["trace_rel"].max() <= 1e-4
+    assert err["lmin_weyl"].max() <= 1e-4
+    assert e_fim(out[:, 3:], ref[:, 3:]).max() <= 1e-4
+
+
+def test_nearest_queries_sampled(fif, bld):
+    rng = np.random.default_rng(24)
+    pick = rng.choice(bld["t"].shape[0], 256, replace=False)
+    idx = torch.from_numpy(pick).cuda()
+    out = fif.query(bld["field"], bld["t_d"][idx].contiguous(), bld["q_d"][idx].contiguous(),
+                    M7 | 8, interp=fif.NEAREST).cpu().numpy()
+    t64 = bld["t"][pick].astype(np.float64)
+    q64 = bld["q"][pick].astype(np.float64)
+    of = _oracle_field(bld, t64)
+    v = bld["v"]
+    ref, _ = oracle.query(of, v.half_fov, v.v_alpha, t64, q64, M7 | 8, 1)
+    err = metric_errors(out[:, :3], ref[:, :3], ref[:, 3:])
+    assert err["trace_rel"].max() <= 1e-3
+    assert err["lmin_weyl"].max() <= 1e-3
+    assert e_fim(out[:, 3:], ref[:, 3:]).max() <= 1e-3
+
+
+def test_edge_cases_on_building_field(fif, bld):
+    field = bld["field"]
+    g = bld["g"]
+    lo, hi = g.hull_lo, g.hull_hi
+    # ragged tail and single query
+    for m in (1, 7, 255, 257, 1000):
+        o = fif.query(field, bld["t_d"][:m].contiguous(), bld["q_d"][:m].contiguous(), M7)
+        np.testing.assert_array_equal(o.cpu().numpy(), bld["out"][:m].cpu().numpy())
+    # m = 0: nothing enqueued
+    e = fif.query(field, bld["t_d"][:0], bld["q_d"][:0], M7)
+    assert e.shape == (0, 3)
+    # outside the hull: clamped and flagged, equal to the hull point
+    t = np.array([[lo[0] - 3.0, 0.1, 0.2], [hi[0] + 1.0, hi[1] + 1.0, hi[2] + 1.0],
+                  [0.3, 0.2, 0.1]], np.float32)
+    tc = np.clip(t, lo, hi).astype(np.float32)
+    q = np.array([[1, 0, 0, 0], [0.5, 0.5, 0.5, 0.5], [0, 0, 1, 0]], np.float32)
+    o, fl = fif.query(field, torch.from_numpy(t).cuda(), torch.from_numpy(q).cuda(), M7,
+                      want_flags=True)
+    oc = fif.query(field, torch.from_numpy(tc).cuda(), torch.from_numpy(q).cuda(), M7)
+    assert list(fl.cpu().numpy() & 1) == [1, 1, 0]
+    np.testing.assert_allclose(o.cpu().numpy(), oc.cpu().numpy(), rtol=1e-6)
+    # unnormalised quaternion: same result as the unit quaternion
+    o2 = fif.query(field, torch.from_numpy(tc).cuda(), torch.from_numpy(3.0 * q).cuda(), M7)
+    np.testing.assert_allclose(o2.cpu().numpy(), oc.cpu().numpy(), rtol=1e-5)
+    # NaN pose -> NaN outputs, no error
+    tn = tc.copy()
+    tn[0, 1] = np.nan
+    qn = q.copy()
+    qn[2, 0] = np.nan
+    on = fif.query(field, torch.from_numpy(tn).cuda(), torch.from_numpy(qn).cuda(), M7)
+    on = on.cpu().numpy()
+    assert np.isnan(on[0]).all() and np.isnan(on[2]).all() and np.isfinite(on[1]).all()
+    on1 = fif.query(field, torch.from_numpy(tn).cuda(), torch.from_numpy(qn).cuda(), M7,
+                    interp=fif.NEAREST).cpu().numpy()
+    assert np.isnan(on1[0]).all() and np.isnan(on1[2]).all()
+
+
+def test_empty_landmark_set_and_tiny_grids(fif):
+    print("case: empty landmark set, 1x1x1 and 5x1x3 grids", flush=True)
+    vis = fif.Vis()
+    lm0 = torch.zeros((0, 3), dtype=torch.float64, device="cuda")
+    grid = fif.Grid((0.0, 0.0, 0.0), 0.5, (3, 4, 2))
+    f0 = fif.build(lm0, grid, vis, prec=fif.FP64)
+    t = torch.tensor([[0.3, 0.7, 0.2]], dtype=torch.float64, device="cuda")
+    q = torch.tensor([[1.0, 0, 0, 0]], dtype=torch.float64, device="cuda")
+    o, fl = fif.query(f0, t, q, M7, want_flags=True)
+    o = o.cpu().numpy()
+    assert o[0, 0] == 0.0 and o[0, 1] == 0.0 and math.isnan(o[0, 2])
+    assert fl.cpu().numpy()[0] & 2
+    rng = np.random.default_rng(25)
+    lm = rng.uniform(-2, 2, (50, 3))
+    for shape in ((1, 1, 1), (5, 1, 3), (1, 4, 1)):
+        grid = fif.Grid((-0.5, -0.25, 0.1), 0.4, shape)
+        f = fif.build(torch.from_numpy(lm).cuda(), grid, vis, prec=fif.FP64)
+        C = oracle.build(lm, grid.origin, grid.h, shape, vis.sigma)
+        of = oracle.Field(C, grid.origin, grid.h, shape)
+        tt = rng.uniform(-1.0, 1.5, (40, 3))
+        qq = scenes.haar_quaternions(rng, 40)
+        for interp in (0, 1):
+            go = fif.query(f, torch.from_numpy(tt).cuda(), torch.from_numpy(qq).cuda(), M7 | 8,
+                           interp=interp).cpu().numpy()
+            ref, _ = oracle.query(of, vis.half_fov, vis.v_alpha, tt, qq, M7 | 8, interp)
+            assert e_fim(go[:, 3:], ref[:, 3:]).max() <= 1e-10, shape
+
+
+def test_trace_field_matches_information_field(fif, bld):
+    """Sec. VII-A: the trace factor gives the trace of the information factor."""
+    tf = fif.build(bld["lm_d"], bld["grid"], bld["vis"], prec=fif.FP32_COMP, kind=fif.KIND_TRACE)
+    m = 200_000
+    tr = fif.query(tf, bld["t_d"][:m].contiguous(), bld["q_d"][:m].contiguous(), fif.TRACE)
+    ref = bld["out"][:m, 0]
+    rel = ((tr[:, 0] - ref).abs() / ref.abs()).max().item()
+    assert rel <= 1e-3, rel
+    # and against the oracle trace factor on sampled voxels
+    rng = np.random.default_rng(26)
+    ids = np.sort(rng.choice(bld["grid"].n_voxels, 64, replace=False))
+    g, v = bld["g"], bld["v"]
+    got = fif.export_blocks(tf, torch.from_numpy(ids).cuda()).cpu().numpy()
+    for a, vid in enumerate(ids):
+        t = oracle.voxel_centre(g.origin, g.h, g.shape, vid)
+        CT = oracle.trace_factor(bld["lm"], t, v.sigma, v.r_min, v.r_max)
+        assert np.abs(got[a] - CT).max() <= 1e-4 * np.abs(CT).max()
+
+
+def test_incremental_update_equals_rebuild(fif, bld):
+    """Sec. VI-A: adding then removing landmarks updates the factors additively."""
+    print("case: incremental update", flush=True)
+    lm = bld["lm"]
+    lm_a = torch.from_numpy(np.ascontiguousarray(lm[:60_000])).cuda()
+    lm_b = torch.from_numpy(np.ascontiguousarray(lm[60_000:])).cuda()
+    f = fif.build(lm_a, bld["grid"], bld["vis"], prec=fif.FP64)
+    fif.update(f, lm_b, +1)
+    full = fif.build(bld["lm_d"], bld["grid"], bld["vis"], prec=fif.FP64)
+    rng = np.random.default_rng(27)
+    ids = torch.from_numpy(np.sort(rng.choice(bld["grid"].n_voxels, 500, replace=False))).cuda()
+    a = fif.export_blocks(f, ids).cpu().numpy()
+    b = fif.export_blocks(full, ids).cpu().numpy()
+    assert np.abs(a - b).max() <= 1e-9 * np.abs(b).max()
+    fif.update(f, lm_b, -1)
+    part = fif.build(lm_a, bld["grid"], bld["vis"], prec=fif.FP64)
+    a = fif.export_blocks(f, ids).cpu().numpy()
+    c = fif.export_blocks(part, ids).cpu().numpy()
+    assert np.abs(a - c).max() <= 1e-9 * np.abs(c).max()
+    # the queries see the update through the cell side records as well
+    m = 100_000
+    td = bld["t_d"][:m].double().contiguous()
+    qd = bld["q_d"][:m].double().contiguous()
+    assert e_fim(fif.query(f, td, qd, 8).cpu().numpy(),
+                 fif.query(part, td, qd, 8).cpu().numpy()).max() <= 1e-9

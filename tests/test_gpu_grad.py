@@ -1,0 +1,129 @@
+"""Gradient parity on the trajectory workload (4,096 x 64 B-spline poses on the
+building field): the fused backward against the oracle's analytic gradient, and
+against central finite differences (h = 1e-4) of the forward query on an FP64
+field; the autograd wrapper's quaternion gradient against finite differences.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import scenes
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+M7 = 7
+
+
+@pytest.fixture(scope="module")
+def fif():
+    import paper_2008_03324_amd as fif
+    fif.lib()
+    return fif
+
+
+@pytest.fixture(scope="module")
+def traj(fif):
+    print("case: trajectory gradients on the building field", flush=True)
+    lm, g, v = scenes.building_scene()
+    grid = fif.Grid(g.origin, g.h, g.shape)
+    vis = fif.Vis(v.half_fov, v.v_alpha, v.sigma, v.r_min, v.r_max)
+    t, q = scenes.trajectories(g, 4096, 64)
+    t, q = t.reshape(-1, 3), q.reshape(-1, 4)
+    lm_d = torch.tensor(lm, dtype=torch.float64, device="cuda")
+    return dict(lm=lm, g=g, v=v, grid=grid, vis=vis, t=t, q=q, lm_d=lm_d)
+
+
+def _away_from_faces(g, t, margin):
+    gg = (t - np.asarray(g.origin)) / g.h
+    fr = gg - np.floor(gg)
+    return ((fr > margin) & (fr < 1 - margin)).all(axis=1)
+
+
+def test_fp32_gradient_vs_oracle(fif, traj):
+    field = fif.build(traj["lm_d"], traj["grid"], traj["vis"], prec=fif.FP32_COMP)
+    t_d = torch.from_numpy(traj["t"]).cuda()
+    q_d = torch.from_numpy(traj["q"]).cuda()
+    rng = np.random.default_rng(31)
+    up = rng.standard_normal((traj["t"].shape[0], 3))
+    gt, gphi, out = fif.query_grad(field, t_d, q_d, M7, torch.from_numpy(up).cuda(),
+                                   want_out=True)
+    pick = rng.choice(traj["t"].shape[0], 256, replace=False)
+    t64 = traj["t"][pick].astype(np.float64)
+    q64 = traj["q"][pick].astype(np.float64)
+    g, v = traj["g"], traj["v"]
+    ids = oracle.corner_voxels(g.origin, g.h, g.shape, t64)
+    C = oracle.build(traj["lm"], g.origin, g.h, g.shape, v.sigma, v.r_min, v.r_max, voxel_ids=ids)
+    of = oracle.Field(C, g.origin, g.h, g.shape, voxel_ids=ids)
+    rgt, rgphi = oracle.query_grad(of, v.half_fov, v.v_alpha, t64, q64, M7, up[pick])
+    ok = _away_from_faces(g, t64, 1e-3)
+    for a, b in ((gt.cpu().numpy()[pick], rgt), (gphi.cpu().numpy()[pick], rgphi)):
+        scale = np.abs(b[ok]).max(axis=1, keepdims=True)
+        rel = np.abs(a[ok] - b[ok]) / scale
+        print("fp32 grad rel err max", rel.max(), "median", np.median(rel))
+        assert rel.max() <= 1e-2
+        assert np.median(rel) <= 1e-4
+
+
+def test_fp64_gradient_vs_central_fd(fif, traj):
+    """Central differences of the GPU forward (FP64 field) with h = 1e-4."""
+    field = fif.build(traj["lm_d"], traj["grid"], traj["vis"], prec=fif.FP64)
+    rng = np.random.default_rng(32)
+    pick = rng.choice(traj["t"].shape[0], 512, replace=False)
+    t = traj["t"][pick].astype(np.float64)
+    q = traj["q"][pick].astype(np.float64)
+    ok = _away_from_faces(traj["g"], t, 2e-3)
+    t, q = t[ok], q[ok]
+    up = rng.standard_normal((t.shape[0], 3))
+    td, qd = torch.from_numpy(t).cuda(), torch.from_numpy(q).cuda()
+    gt, gphi = fif.query_grad(field, td, qd, M7, torch.from_numpy(up).cuda())
+    gt, gphi = gt.cpu().numpy(), gphi.cpu().numpy()
+    h = 1e-4
+
+    def L(tt, qq):
+        o = fif.query(field, torch.from_numpy(tt).cuda(), torch.from_numpy(qq).cuda(), M7)
+        return (o.cpu().numpy() * up).sum(axis=1)
+
+    for c in range(3):
+        e = np.zeros(3)
+        e[c] = h
+        fd = (L(t + e, q) - L(t - e, q)) / (2 * h)
+        rel = np.abs(gt[:, c] - fd) / np.abs(gt).max(axis=1)
+        assert rel.max() <= 1e-5, rel.max()
+    R = np.stack([oracle.quat_to_R(qi) for qi in q])
+    for c in range(3):
+        phi = np.zeros(3)
+        phi[c] = h
+        K = np.array([[0, -phi[2], phi[1]], [phi[2], 0, -phi[0]], [-phi[1], phi[0], 0]])
+        th = h
+        E = np.eye(3) + np.sin(th) / th * K + (1 - np.cos(th)) / th ** 2 * K @ K
+        qp = scenes.rotation_to_quaternion(E @ R)
+        qm = scenes.rotation_to_quaternion(E.T @ R)
+        fd = (L(t, qp) - L(t, qm)) / (2 * h)
+        rel = np.abs(gphi[:, c] - fd) / np.abs(gphi).max(axis=1)
+        assert rel.max() <= 1e-5, rel.max()
+
+
+def test_autograd_quaternion_gradient(fif, traj):
+    field = fif.build(traj["lm_d"], traj["grid"], traj["vis"], prec=fif.FP64)
+    rng = np.random.default_rng(33)
+    pick = rng.choice(traj["t"].shape[0], 64, replace=False)
+    t = torch.from_numpy(traj["t"][pick].astype(np.float64)).cuda().requires_grad_(True)
+    q0 = traj["q"][pick].astype(np.float64) * rng.uniform(0.5, 2.0, (64, 1))
+    q = torch.from_numpy(q0).cuda().requires_grad_(True)
+    w = torch.from_numpy(rng.standard_normal((64, 3))).cuda()
+    out = fif.fif_query_autograd(field, t, q)
+    (out * w).sum().backward()
+    gq = q.grad.cpu().numpy()
+    h = 1e-6
+    for c in range(4):
+        e = np.zeros(4)
+        e[c] = h
+        qp = torch.from_numpy(q0 + e).cuda()
+        qm = torch.from_numpy(q0 - e).cuda()
+        lp = (fif.query(field, t.detach(), qp, M7) * w).sum(dim=1).cpu().numpy()
+        lm_ = (fif.query(field, t.detach(), qm, M7) * w).sum(dim=1).cpu().numpy()
+        fd = (lp - lm_) / (2 * h)
+        rel = np.abs(gq[:, c] - fd) / np.abs(gq).max(axis=1)
+        assert rel.max() <= 1e-4, rel.max()
+    assert t.grad is not None and torch.isfinite(t.grad).all()

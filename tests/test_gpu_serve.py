@@ -1,0 +1,83 @@
+"""Serving loop: results are bitwise the same alone and in the mix; admission
+by HBM budget and slots; the one-request-per-launch mode agrees too."""
+import numpy as np
+import pytest
+
+import scenes
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def setup():
+    import paper_2008_03324_amd as fif
+    from paper_2008_03324_amd import serve
+    print("case: serving loop on two small fields", flush=True)
+    fields, pools = [], []
+    for i, shape in enumerate(((24, 24, 12), (40, 30, 10))):
+        lm, g, v = scenes.building_scene(n_landmarks=4000, seed=77 + i, shape=shape, h=0.25,
+                                         r_max=6.0)
+        grid = fif.Grid(g.origin, g.h, g.shape)
+        vis = fif.Vis(v.half_fov, v.v_alpha, v.sigma, v.r_min, v.r_max)
+        fields.append(fif.build(torch.tensor(lm, device="cuda"), grid, vis, prec=fif.FP32_COMP))
+        pt, pq = scenes.building_poses(g, 20_000, seed=90 + i)
+        tt, tq = scenes.trajectories(g, 128, 64, seed=95 + i)
+        pools.append({"plan": (torch.from_numpy(pt).cuda(), torch.from_numpy(pq).cuda()),
+                      "opt": (torch.from_numpy(tt.reshape(-1, 3)).cuda(),
+                              torch.from_numpy(tq.reshape(-1, 4)).cuda())})
+    specs = scenes.request_stream(2, 2000.0, 150, 20_000, 128, seed=99)
+    torch.cuda.synchronize()
+    return fif, serve, fields, pools, specs
+
+
+def _make(serve, pools, specs):
+    reqs = []
+    for sp in specs:
+        t, q = pools[sp.field][sp.kind]
+        reqs.append(serve.Request(sp.rid, sp.arrival, sp.field, sp.kind,
+                                  t[sp.offset:sp.offset + sp.m], q[sp.offset:sp.offset + sp.m]))
+    return reqs
+
+
+def _alone(fif, fields, r):
+    f = fields[r.field]
+    if r.kind == "plan":
+        return fif.query(f, r.t.contiguous(), r.q.contiguous(), 7), None, None
+    up = torch.ones((r.m, 3), dtype=torch.float64, device="cuda")
+    gt, gphi, out = fif.query_grad(f, r.t.contiguous(), r.q.contiguous(), 7, up, want_out=True)
+    return out, gt, gphi
+
+
+@pytest.mark.parametrize("mode", ["batched_graphs", "batched_eager", "one_per_launch"])
+def test_results_identical_alone_and_in_mix(setup, mode):
+    fif, serve, fields, pools, specs = setup
+    kw = {"batched_graphs": dict(n_streams=3, use_graphs=True, co_batch=True, max_batch=16384),
+          "batched_eager": dict(n_streams=2, use_graphs=False, co_batch=True, max_batch=4096),
+          "one_per_launch": dict(n_streams=1, use_graphs=False, co_batch=False,
+                                 max_inflight=1)}[mode]
+    srv = serve.Server(fields, **kw)
+    srv.warmup()
+    reqs = _make(serve, pools, specs)
+    srv.run(reqs, realtime=True)
+    assert all(r.status == "done" for r in reqs)
+    assert srv.reserved == 0 and not srv.inflight
+    for r in reqs:
+        out, gt, gphi = _alone(fif, fields, r)
+        assert torch.equal(r.out, out), (mode, r.rid)
+        if r.kind == "opt":
+            assert torch.equal(r.grad_t, gt) and torch.equal(r.grad_phi, gphi), (mode, r.rid)
+    st = serve.latency_stats(reqs)
+    assert st["n"] == len(reqs) and st["p99_ms"] >= st["p50_ms"] >= 0
+
+
+def test_admission_by_budget(setup):
+    fif, serve, fields, pools, specs = setup
+    reqs = _make(serve, pools, specs)
+    big = max(r.bytes_needed() for r in reqs)
+    srv = serve.Server(fields, n_streams=2, use_graphs=False, hbm_budget=big)
+    srv.run(reqs, realtime=False)
+    assert all(r.status == "done" for r in reqs) and srv.reserved == 0
+    tiny = serve.Server(fields, n_streams=1, use_graphs=False, hbm_budget=big - 1)
+    with pytest.raises(serve.AdmissionError):
+        tiny.run(_make(serve, pools, specs), realtime=False)

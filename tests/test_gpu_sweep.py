@@ -1,0 +1,36 @@
+"""Precision sweep: the building scene at 1M landmarks built in FP32 naive, FP32
+compensated and FP64 on the full 2M-voxel grid; per-voxel block error against
+the FP64 oracle on sampled voxels."""
+import numpy as np
+import pytest
+
+import oracle
+import scenes
+from fifcheck import block_rel_err
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+def test_precision_sweep_1M_landmarks():
+    import paper_2008_03324_amd as fif
+    print("case: 1M-landmark precision sweep", flush=True)
+    lm, g, v = scenes.building_scene(n_landmarks=1_000_000)
+    grid = fif.Grid(g.origin, g.h, g.shape)
+    vis = fif.Vis(v.half_fov, v.v_alpha, v.sigma, v.r_min, v.r_max)
+    lm_d = torch.tensor(lm, dtype=torch.float64, device="cuda")
+    rng = np.random.default_rng(41)
+    ids = np.sort(rng.choice(grid.n_voxels, 48, replace=False))
+    C = oracle.build(lm, g.origin, g.h, g.shape, v.sigma, v.r_min, v.r_max, voxel_ids=ids)
+    ids_d = torch.from_numpy(ids).cuda()
+    errs = {}
+    for prec in (fif.FP32_NAIVE, fif.FP32_COMP, fif.FP64):
+        f = fif.build(lm_d, grid, vis, prec=prec)
+        errs[prec] = block_rel_err(fif.export_blocks(f, ids_d).cpu().numpy(), C)
+        del f
+        torch.cuda.empty_cache()
+    print({p: (float(e.max()), float(np.median(e))) for p, e in errs.items()})
+    assert errs[fif.FP64].max() <= 1e-10
+    assert errs[fif.FP32_COMP].max() <= 1e-3
+    assert errs[fif.FP32_NAIVE].max() <= 1e-3
+    assert np.median(errs[fif.FP32_COMP]) <= np.median(errs[fif.FP32_NAIVE])
