@@ -200,13 +200,34 @@ class Field:
         return f
 
 
+_WORKSPACE = {}
+
+
+def workspace(grid: Grid, n_landmarks: int, prec: int, device) -> torch.Tensor | None:
+    """Scratch for the spatially sorted build (cached per device, grown on demand)."""
+    nbytes = int(lib().fif_workspace_bytes(ctypes.byref(grid.c()), int(n_landmarks), prec))
+    if nbytes == 0:
+        return None
+    key = str(device)
+    ws = _WORKSPACE.get(key)
+    if ws is None or ws.numel() < nbytes:
+        ws = torch.empty(nbytes, dtype=torch.uint8, device=device)
+        _WORKSPACE[key] = ws
+    return ws
+
+
 def build(landmarks: torch.Tensor, grid: Grid, vis: Vis, prec: int = FP32_COMP,
-          kind: int = KIND_INFO, field: Field | None = None, stream=None) -> Field:
+          kind: int = KIND_INFO, field: Field | None = None, sort: bool = True,
+          stream=None) -> Field:
+    """Build a field.  With sort (the default) the landmarks are first ordered
+    spatially in a workspace so that whole landmark batches out of range of a
+    voxel tile are skipped; without it every pair is tested in input order."""
     lm = _dev(landmarks, torch.float64, "landmarks", 3)
     if field is None:
         field = Field(grid, vis, prec, kind, device=lm.device)
-    _check(lib().fif_build(_ptr(lm), lm.shape[0], ctypes.byref(field.cstruct), None, 0,
-                           _stream(stream)), "fif_build")
+    ws = workspace(grid, lm.shape[0], prec, lm.device) if sort else None
+    _check(lib().fif_build(_ptr(lm), lm.shape[0], ctypes.byref(field.cstruct), _ptr(ws),
+                           ws.numel() if ws is not None else 0, _stream(stream)), "fif_build")
     return field
 
 

@@ -105,12 +105,13 @@ size_t fif_field_bytes(const fif_grid* grid, int32_t prec, int32_t kind) {
 }
 
 size_t fif_workspace_bytes(const fif_grid* grid, int64_t n_landmarks, int32_t prec) {
-  (void)grid; (void)n_landmarks; (void)prec;
-  return 0;
+  if (!grid_ok(grid) || !prec_ok(prec) || n_landmarks <= 0) return 0;
+  return fif::sort_workspace_bytes(n_landmarks);
 }
 
 static fif_status build_common(const double* landmarks, int64_t n_landmarks, fif_field* field,
-                               int accumulate, int sign, void* stream, const char* where) {
+                               int accumulate, int sign, void* workspace, size_t ws_bytes,
+                               void* stream, const char* where) {
   fif_status st = check_field(field);
   if (st != FIF_OK) return st;
   if (n_landmarks < 0) return fail(FIF_EINVAL, "n_landmarks < 0%s");
@@ -127,14 +128,25 @@ static fif_status build_common(const double* landmarks, int64_t n_landmarks, fif
   a.out = field->data;
   a.accumulate = accumulate;
   a.sign = sign;
+  a.lm_sorted = nullptr;
+  a.batch_box = nullptr;
+  a.skip2 = INFINITY;
+  if (workspace && n_landmarks > 0) {
+    if (!aligned(workspace, 256)) return fail(FIF_EINVAL, "workspace must be 256-byte aligned%s");
+    const size_t need = fif::sort_workspace_bytes(n_landmarks);
+    if (need == 0) return fail(FIF_EDEVICE, "cannot size the landmark sort%s");
+    if (ws_bytes < need) return fail(FIF_ENOMEM, "workspace smaller than fif_workspace_bytes()%s");
+    hipError_t e = fif::sort_landmarks(a, workspace, ws_bytes, (hipStream_t)stream);
+    if (e != hipSuccess) return device_status(e, where);
+  }
   hipError_t e = fif::launch_build(a, field->prec, field->kind, (hipStream_t)stream);
   return device_status(e, where);
 }
 
 fif_status fif_build(const double* landmarks, int64_t n_landmarks, fif_field* field,
                      void* workspace, size_t workspace_bytes, void* stream) {
-  (void)workspace; (void)workspace_bytes;
-  return build_common(landmarks, n_landmarks, field, 0, 1, stream, "fif_build");
+  return build_common(landmarks, n_landmarks, field, 0, 1, workspace, workspace_bytes, stream,
+                      "fif_build");
 }
 
 fif_status fif_update(const double* landmarks, int64_t n_landmarks, int32_t sign,
@@ -144,7 +156,7 @@ fif_status fif_update(const double* landmarks, int64_t n_landmarks, int32_t sign
     fif_status st = check_field(field);
     return st;
   }
-  return build_common(landmarks, n_landmarks, field, 1, sign, stream, "fif_update");
+  return build_common(landmarks, n_landmarks, field, 1, sign, nullptr, 0, stream, "fif_update");
 }
 
 static int metric_cols(uint32_t metrics) {

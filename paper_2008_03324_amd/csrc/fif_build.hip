@@ -8,6 +8,11 @@
 // folds every landmark in range into its 66 moment sums (see fif_device.h).
 // The summation order is fixed (landmark order), so results are bitwise
 // reproducible.
+#include <cmath>
+#include <cstring>
+
+#include <rocprim/device/device_radix_sort.hpp>
+
 #include "fif_device.h"
 #include "fif_kernels.h"
 
@@ -154,12 +159,38 @@ __global__ __launch_bounds__(kBuildThreads) void build_kernel(BuildArgs a) {
     for (int i = 0; i < NACC; ++i) { hi[i] = 0.f; lo[i] = 0.f; }
   }
 
+  // workgroup tile bounds (voxel centres, FP32 like the range test)
+  float tlo[3], thi[3];
+  if (a.lm_sorted) {
+    const int x0 = blockIdx.x * 8, y0 = blockIdx.y * 8, z0 = blockIdx.z * 4;
+    const int x1 = min(x0 + 7, a.g.nx - 1), y1 = min(y0 + 7, a.g.ny - 1), z1 = min(z0 + 3, a.g.nz - 1);
+    tlo[0] = (float)(a.g.ox + x0 * a.g.h); thi[0] = (float)(a.g.ox + x1 * a.g.h);
+    tlo[1] = (float)(a.g.oy + y0 * a.g.h); thi[1] = (float)(a.g.oy + y1 * a.g.h);
+    tlo[2] = (float)(a.g.oz + z0 * a.g.h); thi[2] = (float)(a.g.oz + z1 * a.g.h);
+  }
   for (int64_t base = 0; base < a.L; base += kBatch) {
     const int nb = (int)((a.L - base) < kBatch ? (a.L - base) : kBatch);
+    if (a.lm_sorted) {
+      // skip a batch whose box is out of range of the whole tile (workgroup-uniform)
+      const float* bb = a.batch_box + 8 * (base / kBatch);
+      float d2 = 0.f;
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        float gap = fmaxf(fmaxf(bb[c] - thi[c], tlo[c] - bb[3 + c]), 0.f);
+        d2 = fmaf(gap, gap, d2);
+      }
+      if (d2 > a.skip2) continue;
+    }
     __syncthreads();
     if (tid < nb) {
-      const double* p = a.lm + 3 * (base + tid);
-      double px = p[0], py = p[1], pz = p[2];
+      double px, py, pz;
+      if (a.lm_sorted) {
+        const double4 p4 = a.lm_sorted[base + tid];
+        px = p4.x; py = p4.y; pz = p4.z;
+      } else {
+        const double* p = a.lm + 3 * (base + tid);
+        px = p[0]; py = p[1]; pz = p[2];
+      }
       L4 v;
       v.x = (T)px; v.y = (T)py; v.z = (T)pz;
       v.w = (T)(px * px + py * py + pz * pz);
@@ -251,6 +282,144 @@ __global__ __launch_bounds__(256) void fill_side_kernel(GridDev g, void* field) 
   // slot 0 is unchanged; rewrite slots 1..7 only
 #pragma unroll
   for (int k = 2; k < kSideRec; ++k) side[v * kSideRec + k] = vals[k];
+}
+
+// ------------------------------------------------------------ spatial sort
+
+// 30-bit Morton code of each landmark inside the box [lo, lo + 1024 q)^3.
+__global__ void morton_kernel(const double* lm, int64_t L, double lox, double loy, double loz,
+                              double inv_q, uint32_t* keys, uint32_t* idx) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= L) return;
+  const double p[3] = {lm[3 * i], lm[3 * i + 1], lm[3 * i + 2]};
+  const double lo[3] = {lox, loy, loz};
+  uint32_t code = 0;
+  uint32_t c[3];
+#pragma unroll
+  for (int ax = 0; ax < 3; ++ax) {
+    double g = (p[ax] - lo[ax]) * inv_q;
+    g = fmin(fmax(g, 0.0), 1023.0);  // NaN -> 0
+    c[ax] = (uint32_t)g;
+  }
+#pragma unroll
+  for (int b = 9; b >= 0; --b)
+#pragma unroll
+    for (int ax = 0; ax < 3; ++ax) code = (code << 1) | ((c[ax] >> b) & 1u);
+  keys[i] = code;
+  idx[i] = (uint32_t)i;
+}
+
+// Sorted landmarks and the FP32 bounding box of each batch of kBatch.
+__global__ __launch_bounds__(kBatch) void gather_box_kernel(const double* lm, int64_t L,
+                                                            const uint32_t* idx, double4* out,
+                                                            float* boxes) {
+  __shared__ float s_min[3][kBatch], s_max[3][kBatch];
+  const int64_t i = (int64_t)blockIdx.x * kBatch + threadIdx.x;
+  float mn[3] = {INFINITY, INFINITY, INFINITY}, mx[3] = {-INFINITY, -INFINITY, -INFINITY};
+  if (i < L) {
+    const int64_t j = idx[i];
+    const double x = lm[3 * j], y = lm[3 * j + 1], z = lm[3 * j + 2];
+    double4 v;
+    v.x = x; v.y = y; v.z = z; v.w = 0.0;
+    out[i] = v;
+    mn[0] = mx[0] = (float)x;
+    mn[1] = mx[1] = (float)y;
+    mn[2] = mx[2] = (float)z;
+  }
+#pragma unroll
+  for (int c = 0; c < 3; ++c) { s_min[c][threadIdx.x] = mn[c]; s_max[c][threadIdx.x] = mx[c]; }
+  __syncthreads();
+  for (int stride = kBatch / 2; stride > 0; stride >>= 1) {
+    if (threadIdx.x < stride) {
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        s_min[c][threadIdx.x] = fminf(s_min[c][threadIdx.x], s_min[c][threadIdx.x + stride]);
+        s_max[c][threadIdx.x] = fmaxf(s_max[c][threadIdx.x], s_max[c][threadIdx.x + stride]);
+      }
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x < 8) {
+    float v = 0.f;
+    if (threadIdx.x < 3) v = s_min[threadIdx.x][0];
+    else if (threadIdx.x < 6) v = s_max[threadIdx.x - 3][0];
+    boxes[8 * blockIdx.x + threadIdx.x] = v;
+  }
+}
+
+namespace {
+struct SortLayout {
+  size_t keys_in, keys_out, idx_in, idx_out, sorted, boxes, tmp, total;
+};
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+SortLayout sort_layout(int64_t L, size_t tmp_bytes) {
+  SortLayout s;
+  size_t off = 0;
+  s.keys_in = off; off = align256(off + 4 * (size_t)L);
+  s.keys_out = off; off = align256(off + 4 * (size_t)L);
+  s.idx_in = off; off = align256(off + 4 * (size_t)L);
+  s.idx_out = off; off = align256(off + 4 * (size_t)L);
+  s.sorted = off; off = align256(off + 32 * (size_t)L);
+  s.boxes = off; off = align256(off + 32 * (size_t)((L + kBatch - 1) / kBatch));
+  s.tmp = off; off = align256(off + tmp_bytes);
+  s.total = off;
+  return s;
+}
+size_t radix_tmp_bytes(int64_t L) {
+  size_t bytes = 0;
+  hipError_t e = rocprim::radix_sort_pairs(nullptr, bytes, (const uint32_t*)nullptr, (uint32_t*)nullptr,
+                                           (const uint32_t*)nullptr, (uint32_t*)nullptr,
+                                           (size_t)L, 0, 30);
+  return e == hipSuccess ? bytes : 0;
+}
+}  // namespace
+
+size_t sort_workspace_bytes(int64_t L) {
+  if (L <= 0) return 0;
+  size_t tmp = radix_tmp_bytes(L);
+  if (tmp == 0) return 0;
+  return sort_layout(L, tmp).total;
+}
+
+hipError_t sort_landmarks(BuildArgs& a, void* ws, size_t ws_bytes, hipStream_t stream) {
+  const size_t tmp = radix_tmp_bytes(a.L);
+  const SortLayout lay = sort_layout(a.L, tmp);
+  if (tmp == 0 || ws_bytes < lay.total) return hipErrorInvalidValue;
+  char* base = reinterpret_cast<char*>(ws);
+  uint32_t* kin = reinterpret_cast<uint32_t*>(base + lay.keys_in);
+  uint32_t* kout = reinterpret_cast<uint32_t*>(base + lay.keys_out);
+  uint32_t* iin = reinterpret_cast<uint32_t*>(base + lay.idx_in);
+  uint32_t* iout = reinterpret_cast<uint32_t*>(base + lay.idx_out);
+  // quantisation box: the voxel-centre hull grown by the range (or by 1/4 of
+  // the hull when the range is unbounded); landmarks outside are clamped
+  const double ext[3] = {(a.g.nx - 1) * a.g.h, (a.g.ny - 1) * a.g.h, (a.g.nz - 1) * a.g.h};
+  double emax = fmax(ext[0], fmax(ext[1], ext[2]));
+  double margin = std::isinf((double)a.hi2) ? 0.25 * emax + a.g.h : sqrt((double)a.hi2) + a.g.h;
+  const double lo[3] = {a.g.ox - margin, a.g.oy - margin, a.g.oz - margin};
+  const double span = emax + 2.0 * margin;
+  const double inv_q = 1024.0 / span;
+  const unsigned nblk = (unsigned)((a.L + 255) / 256);
+  hipLaunchKernelGGL(morton_kernel, dim3(nblk), dim3(256), 0, stream, a.lm, a.L, lo[0], lo[1],
+                     lo[2], inv_q, kin, iin);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  size_t tb = tmp;
+  e = rocprim::radix_sort_pairs(base + lay.tmp, tb, kin, kout, iin, iout, (size_t)a.L, 0, 30,
+                                stream);
+  if (e != hipSuccess) return e;
+  double4* sorted = reinterpret_cast<double4*>(base + lay.sorted);
+  float* boxes = reinterpret_cast<float*>(base + lay.boxes);
+  const unsigned nbatch = (unsigned)((a.L + kBatch - 1) / kBatch);
+  hipLaunchKernelGGL(gather_box_kernel, dim3(nbatch), dim3(kBatch), 0, stream, a.lm, a.L, iout,
+                     sorted, boxes);
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  a.lm_sorted = sorted;
+  a.batch_box = boxes;
+  // conservative skip distance: every landmark of a skipped batch is beyond the
+  // FP32 range test with a margin far above FP32 rounding
+  a.skip2 = std::isinf(a.hi2) ? INFINITY : a.hi2 * 1.0001f + 1e-3f;
+  return hipSuccess;
 }
 
 hipError_t launch_build(const BuildArgs& a, int prec, int kind, hipStream_t stream) {

@@ -12,6 +12,11 @@ namespace fif {
 struct BuildArgs {
   const double* lm;  // [L][3]
   int64_t L;
+  // spatially sorted landmarks (x, y, z, |p|^2) and per-batch bounding boxes
+  // (min xyz, max xyz, 2 pad) in FP32; null for the unsorted path
+  const double4* lm_sorted;
+  const float* batch_box;
+  float skip2;  // a batch is skipped when its box is farther than this (squared)
   GridDev g;
   float lo2, hi2;  // FP32 range bounds on n^2
   void* out;       // field records
@@ -68,6 +73,10 @@ struct ExportArgs {
 };
 
 hipError_t launch_build(const BuildArgs& a, int prec, int kind, hipStream_t stream);
+// Workspace of the sorted build: bytes needed, and the sort itself (fills
+// a.lm_sorted / a.batch_box inside `ws`).
+size_t sort_workspace_bytes(int64_t L);
+hipError_t sort_landmarks(BuildArgs& a, void* ws, size_t ws_bytes, hipStream_t stream);
 hipError_t launch_query(const QueryArgs& a, int prec, int kind, bool grad, hipStream_t stream);
 hipError_t launch_pc(const PcArgs& a, int prec, hipStream_t stream);
 hipError_t launch_export(const ExportArgs& a, int prec, int kind, hipStream_t stream);

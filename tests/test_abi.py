@@ -57,7 +57,8 @@ def test_field_bytes_and_status_strings():
     assert fif.field_bytes(g, 7) == 0
     for s in (0, -1, -2, -3, -4):
         assert L.fif_status_string(s).decode().startswith(fif.STATUS[s])
-    assert L.fif_workspace_bytes(ctypes.byref(g.c()), 1000, fif.FP32_COMP) == 0
+    assert L.fif_workspace_bytes(ctypes.byref(g.c()), 0, fif.FP32_COMP) == 0
+    assert L.fif_workspace_bytes(ctypes.byref(bad.c()), 1000, fif.FP32_COMP) == 0
 
 
 def test_host_side_validation_returns_einval():

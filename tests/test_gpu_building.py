@@ -233,3 +233,25 @@ def test_incremental_update_equals_rebuild(fif, bld):
     qd = bld["q_d"][:m].double().contiguous()
     assert e_fim(fif.query(f, td, qd, 8).cpu().numpy(),
                  fif.query(part, td, qd, 8).cpu().numpy()).max() <= 1e-9
+
+
+def test_sorted_and_unsorted_builds_agree(fif, bld):
+    """The spatially sorted, batch-culled build and the plain build sum the same
+    landmarks in a different order."""
+    g = bld["grid"]
+    rng = np.random.default_rng(28)
+    ids = torch.from_numpy(np.sort(rng.choice(g.n_voxels, 2000, replace=False))).cuda()
+    for prec in (fif.FP64, fif.FP32_COMP):
+        a = fif.build(bld["lm_d"], g, bld["vis"], prec=prec, sort=True)
+        b = fif.build(bld["lm_d"], g, bld["vis"], prec=prec, sort=False)
+        ea = fif.export_blocks(a, ids).cpu().numpy()
+        eb = fif.export_blocks(b, ids).cpu().numpy()
+        tol = 1e-10 if prec == fif.FP64 else 1e-4
+        assert np.abs(ea - eb).max() <= tol * np.abs(eb).max(), prec
+    # a workspace that is too small is rejected before any launch
+    f = fif.Field(g, bld["vis"], fif.FP32_COMP)
+    small = torch.empty(256, dtype=torch.uint8, device="cuda")
+    import ctypes
+    st = fif.lib().fif_build(ctypes.c_void_p(bld["lm_d"].data_ptr()), bld["lm_d"].shape[0],
+                             ctypes.byref(f.cstruct), ctypes.c_void_p(small.data_ptr()), 256, None)
+    assert st == -2
