@@ -55,6 +55,7 @@ def parse():
                     help="comma list of phases to run in each step")
     ap.add_argument("--cpu-sample", type=int, default=2048, help="poses in the oracle sample")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving leg")
+    ap.add_argument("--no-sweep", action="store_true", help="skip the optimal-view sweep leg")
     ap.add_argument("--serve-seconds", type=float, default=2.0,
                     help="length of each Poisson stream of the serving leg")
     return ap.parse_args()
@@ -247,6 +248,9 @@ def main():
                               "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s"}
         res["roofline_pc"]["frac"] = res["roofline_pc"]["achieved"] / FP32_PEAK_TFLOPS
 
+    if not args.no_sweep:
+        res["view_sweep"] = sweep_leg(fif, torch, scenes, g, field, dev)
+
     if not args.no_serve:
         res["serving"] = serve_leg(args, fif, torch)
         res["p99_ms_at_60pct_load"] = res["serving"]["rates"][1]["batched"]["p99_ms"]
@@ -255,6 +259,29 @@ def main():
     if not args.no_cpu:
         res.update(cpu_leg(args, fif, torch, lm, g, v, t, q, out, pc_out, metrics))
     print(json.dumps(res), flush=True)
+
+
+def sweep_leg(fif, torch, scenes, g, field, dev, n_pos=200, n_axes=4096, reps=5):
+    """Optimal views (Sec. VII-A): log-det of every axis of a dense sphere lattice
+    at 200 positions, and the best axis per position, on the resident field."""
+    t = torch.from_numpy(scenes.sweep_positions(g, n_pos)).to(dev)
+    dirs = torch.from_numpy(scenes.sphere_axes(n_axes)).to(dev)
+    vals = torch.empty((n_pos, n_axes), dtype=torch.float64, device=dev)
+    fif.view_sweep(field, t, dirs, fif.LOGDET)
+    torch.cuda.synchronize()
+    ms = []
+    for _ in range(reps):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        vals, best = fif.view_sweep(field, t, dirs, fif.LOGDET)
+        e1.record()
+        torch.cuda.synchronize()
+        ms.append(e0.elapsed_time(e1))
+    med = float(np.median(ms))
+    log(f"view sweep {n_pos} x {n_axes}: {med:.3f} ms")
+    return {"positions": n_pos, "axes": n_axes, "metric": "logdet", "ms": med,
+            "poses_per_s": n_pos * n_axes / (med / 1e3)}
 
 
 def serve_leg(args, fif, torch):

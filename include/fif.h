@@ -109,14 +109,21 @@ typedef struct {
  * an invalid grid, precision or kind. */
 size_t fif_field_bytes(const fif_grid* grid, int32_t prec, int32_t kind);
 
-/* Bytes of scratch device memory fif_build needs (may be 0). */
+/* Bytes of the optional fif_build workspace (0 when n_landmarks <= 0 or the
+ * grid/precision is invalid).  With it, fif_build first orders the landmarks
+ * spatially (Morton keys, stable radix sort) and skips, per voxel tile, every
+ * batch of landmarks whose bounding box is out of range; with a NULL workspace
+ * every (voxel, landmark) pair is tested in input order.  Both orders give the
+ * same field up to rounding, each deterministic. */
 size_t fif_workspace_bytes(const fif_grid* grid, int64_t n_landmarks, int32_t prec);
 
 /* Build a field (Sec. VI-A): for every voxel centre t_v,
  *   C_I(t_v) = sum_{i in V_{t_v}} diag6(vp(u_i)) I_i      (eq:general_info_pif)
  * or, for FIF_KIND_TRACE, C_Tr(t_v) = sum vp(u_i) Tr(I_i)  (eq:general_trace_pif).
  * landmarks: double[n_landmarks][3], world coordinates.  field->data is
- * overwritten.  Deterministic: the summation order is fixed. */
+ * overwritten.  workspace: NULL, or 256-B aligned device memory of at least
+ * fif_workspace_bytes() bytes (FIF_ENOMEM if smaller); it is scratch only.
+ * Deterministic: the summation order is fixed. */
 fif_status fif_build(const double* landmarks, int64_t n_landmarks, fif_field* field,
                      void* workspace, size_t workspace_bytes, void* stream);
 
@@ -157,6 +164,22 @@ fif_status fif_query_grad(const fif_field* field, const void* t, const void* q, 
 fif_status pc_query(const double* landmarks, int64_t n_landmarks, const fif_vis* vis,
                     const fif_pinhole* cam, int32_t prec, const void* t, const void* q,
                     int64_t m, uint32_t metrics, double* out, void* stream);
+
+/* Optimal-view sweep (Sec. VII-A "Relative Measures": the optimal view at a
+ * position is the rotation that maximises the metric).  Under the smooth
+ * visibility models the FIM at a position depends on the rotation only through
+ * the optical axis z (eq:quad_vis_component), so the sweep runs over candidate
+ * axes: for each position the factor blocks are interpolated once and
+ * contracted with vr(z) (eq:fim_separation) for every axis.
+ * t: [n_pos][3] (float for FP32 fields, double for FP64 fields).
+ * dirs: double[n_dir][3] unit optical axes (device).  metric: exactly one of
+ * FIF_TRACE, FIF_LMIN, FIF_LOGDET.  values: double[n_pos][n_dir] or NULL;
+ * best: int64[n_pos] or NULL, the index of the largest value (lowest index
+ * among equal values; NaN values never win; -1 when every value is NaN).
+ * Information fields only. */
+fif_status fif_view_sweep(const fif_field* field, const void* t, int64_t n_pos,
+                          const double* dirs, int64_t n_dir, uint32_t metric, int32_t interp,
+                          double* values, int64_t* best, void* stream);
 
 /* The paper's positional information factor of the listed voxels, recovered
  * from the field: blocks[n][10][21] (double), block k = sum_i vp_k(u_i) I_i in

@@ -251,6 +251,23 @@ def query_grad(field: Field, alpha, v_alpha, t, q, metrics_mask, dL_dout):
     return gt, gphi
 
 
+def view_sweep(field: Field, alpha, v_alpha, t, dirs, metric, interp=0):
+    """Metric of every candidate optical axis at every position, and the index
+    of the best axis per position (first among equal values; -1 if all NaN)."""
+    t = _f64(t, 3)
+    dirs = _f64(dirs, 3)
+    n, nd = t.shape[0], dirs.shape[0]
+    values = np.zeros((n, nd))
+    best = np.zeros(n, np.int64)
+    rc = lib().oracle_view_sweep(*field._args(), ctypes.c_double(alpha),
+                                 ctypes.c_double(v_alpha), _p(t), ctypes.c_int64(n),
+                                 _p(dirs), ctypes.c_int64(nd), ctypes.c_uint32(metric),
+                                 ctypes.c_int(interp), _p(values), _p(best))
+    if rc != 0:
+        raise KeyError("oracle field is missing a voxel the sweep needs")
+    return values, best
+
+
 def corner_voxels(origin, h, shape, t) -> np.ndarray:
     """Voxel ids the trilinear query of each position reads (for sparse builds)."""
     t = _f64(t, 3)

@@ -497,6 +497,49 @@ int oracle_query_fim(const double* field, const int64_t* field_ids, int64_t n_fi
   return err ? -1 : 0;
 }
 
+/* Optimal-view sweep (Sec. VII-A, "Relative Measures": the best view at a
+ * position is the orientation with the largest metric).  With the quadratic
+ * visibility the FIM depends on the orientation only through the optical axis
+ * z (eq:quad_vis_component, eq:fim_separation), so each candidate is an axis:
+ * the factor is interpolated at t once, then F(z) = sum_k vr_k(z) Cbar_k for
+ * every axis (normalised here) and the single metric `which` is taken.
+ * values[n_pos][n_dir] (may be NULL); best[n_pos] (may be NULL) = index of the
+ * largest value, the first one among equal values, NaN never largest, -1 if
+ * all are NaN.  Returns 0, or -1 if a needed voxel is absent. */
+int oracle_view_sweep(const double* field, const int64_t* field_ids, int64_t n_field,
+                      const orc_grid* g, double alpha, double v_alpha, const double* t,
+                      int64_t n_pos, const double* dirs, int64_t n_dir, uint32_t which,
+                      int interp, double* values, int64_t* best) {
+  double k[3];
+  oracle_quad_coeffs(alpha, v_alpha, k);
+  int err = 0;
+#pragma omp parallel for schedule(dynamic, 1)
+  for (int64_t a = 0; a < n_pos; ++a) {
+    /* the identity orientation: only Cbar is used from query_one */
+    const double q_id[4] = {1.0, 0.0, 0.0, 0.0};
+    double F[36], Cbar[360], vr[10], z[3];
+    if (query_one(field, field_ids, n_field, g, k, t + 3 * a, q_id, interp, F, Cbar, vr, z) < 0) {
+      err = 1;
+      continue;
+    }
+    double bv = 0.0;
+    int64_t bi = -1;
+    for (int64_t d = 0; d < n_dir; ++d) {
+      const double* zd = dirs + 3 * d;
+      double nz = sqrt(zd[0] * zd[0] + zd[1] * zd[1] + zd[2] * zd[2]);
+      double zu[3] = {zd[0] / nz, zd[1] / nz, zd[2] / nz};
+      oracle_vr(k, zu, vr);
+      contract(Cbar, vr, F);
+      double val;
+      oracle_metrics(F, which, &val);
+      if (values) values[a * n_dir + d] = val;
+      if (!isnan(val) && (bi < 0 || val > bv)) { bv = val; bi = d; }
+    }
+    if (best) best[a] = bi;
+  }
+  return err ? -1 : 0;
+}
+
 /* ---------------------------------------------------------- gradient */
 
 /* d s / d F for each metric (symmetric 6x6): trace -> I, lmin -> v v^T with v

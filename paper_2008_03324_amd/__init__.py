@@ -76,6 +76,10 @@ EXPORTS = {
                                   ctypes.POINTER(CPinhole), ctypes.c_int32, ctypes.c_void_p,
                                   ctypes.c_void_p, ctypes.c_int64, ctypes.c_uint32,
                                   ctypes.c_void_p, ctypes.c_void_p]),
+    "fif_view_sweep": (ctypes.c_int32, [ctypes.POINTER(CField), ctypes.c_void_p, ctypes.c_int64,
+                                        ctypes.c_void_p, ctypes.c_int64, ctypes.c_uint32,
+                                        ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p,
+                                        ctypes.c_void_p]),
     "fif_field_export": (ctypes.c_int32, [ctypes.POINTER(CField), ctypes.c_void_p, ctypes.c_int64,
                                           ctypes.c_void_p, ctypes.c_void_p]),
     "fif_status_string": (ctypes.c_char_p, [ctypes.c_int32]),
@@ -271,6 +275,23 @@ def query_grad(field: Field, t: torch.Tensor, q: torch.Tensor, metrics: int,
                                 _ptr(up), _ptr(gt), _ptr(gphi), _ptr(out), _stream(stream)),
            "fif_query_grad")
     return (gt, gphi, out) if want_out else (gt, gphi)
+
+
+def view_sweep(field: Field, t: torch.Tensor, dirs: torch.Tensor, metric: int = LOGDET,
+               interp: int = TRILINEAR, want_values: bool = True, stream=None):
+    """Metric of every candidate optical axis (dirs [n_dir, 3], float64) at every
+    position (t [n_pos, 3]) and the index of the best axis per position.
+    Returns (values [n_pos, n_dir] float64 or None, best [n_pos] int64)."""
+    t = _dev(t, field.pose_dtype, "t", 3)
+    dirs = _dev(dirs, torch.float64, "dirs", 3)
+    n, nd = t.shape[0], dirs.shape[0]
+    values = (torch.empty((n, nd), dtype=torch.float64, device=t.device) if want_values
+              else None)
+    best = torch.empty(n, dtype=torch.int64, device=t.device)
+    _check(lib().fif_view_sweep(ctypes.byref(field.cstruct), _ptr(t), n, _ptr(dirs), nd,
+                                metric, interp, _ptr(values), _ptr(best), _stream(stream)),
+           "fif_view_sweep")
+    return values, best
 
 
 def pc_query(landmarks: torch.Tensor, vis: Vis, t: torch.Tensor, q: torch.Tensor,

@@ -277,6 +277,37 @@ fif_status fif_field_export(const fif_field* field, const int64_t* voxel_ids, in
   return device_status(e, "fif_field_export");
 }
 
+fif_status fif_view_sweep(const fif_field* field, const void* t, int64_t n_pos,
+                          const double* dirs, int64_t n_dir, uint32_t metric, int32_t interp,
+                          double* values, int64_t* best, void* stream) {
+  fif_status st = check_field(field);
+  if (st != FIF_OK) return st;
+  if (field->kind != FIF_KIND_INFO) return fail(FIF_EUNSUPPORTED, "sweep needs an information field%s");
+  if (metric != FIF_TRACE && metric != FIF_LMIN && metric != FIF_LOGDET)
+    return fail(FIF_EINVAL, "sweep metric must be one of trace, lmin, logdet%s");
+  if (interp != FIF_TRILINEAR && interp != FIF_NEAREST) return fail(FIF_EINVAL, "invalid interp%s");
+  if (n_pos < 0 || n_dir < 0) return fail(FIF_EINVAL, "negative size%s");
+  if (n_pos > ((int64_t)1 << 31) - 1) return fail(FIF_EINVAL, "n_pos too large%s");
+  if (n_pos == 0) return FIF_OK;
+  if (!t || (n_dir > 0 && !dirs)) return fail(FIF_EINVAL, "t or dirs is NULL%s");
+  if (!aligned(t, scalar_bytes(field->prec)) || (dirs && !aligned(dirs, 8)))
+    return fail(FIF_EINVAL, "misaligned pointer%s");
+  fif::SweepArgs a;
+  a.field = field->data;
+  a.g = grid_dev(&field->grid);
+  a.vis = vis_dev(&field->vis);
+  a.t = t;
+  a.n_pos = n_pos;
+  a.dirs = dirs;
+  a.n_dir = n_dir;
+  a.metric = metric;
+  a.interp = interp;
+  a.values = values;
+  a.best = best;
+  hipError_t e = fif::launch_sweep(a, field->prec, (hipStream_t)stream);
+  return device_status(e, "fif_view_sweep");
+}
+
 const char* fif_status_string(fif_status s) {
   switch (s) {
     case FIF_OK: return "FIF_OK";

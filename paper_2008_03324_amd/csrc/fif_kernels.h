@@ -72,7 +72,22 @@ struct ExportArgs {
   double* out;
 };
 
+struct SweepArgs {
+  const void* field;
+  GridDev g;
+  VisDev vis;
+  const void* t;
+  int64_t n_pos;
+  const double* dirs;
+  int64_t n_dir;
+  uint32_t metric;
+  int32_t interp;
+  double* values;
+  int64_t* best;
+};
+
 hipError_t launch_build(const BuildArgs& a, int prec, int kind, hipStream_t stream);
+hipError_t launch_sweep(const SweepArgs& a, int prec, hipStream_t stream);
 // Workspace of the sorted build: bytes needed, and the sort itself (fills
 // a.lm_sorted / a.batch_box inside `ws`).
 size_t sort_workspace_bytes(int64_t L);

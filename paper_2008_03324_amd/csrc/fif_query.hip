@@ -352,21 +352,10 @@ __device__ constexpr int vp_a(int k) {
 }
 __device__ constexpr int vp_b(int k) { return k < 3 ? k : (k == 3 ? 1 : (k == 4 ? 2 : 2)); }
 
+// The paper's 10 world-frame blocks (eq:general_info_pif, 21 each, scaled by
+// 1/sigma^2 and `w`) of one voxel with centre tv, from its 66 moments.
 template <typename FT>
-__global__ void export_info_kernel(ExportArgs a) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= a.n) return;
-  const int64_t v = a.ids[i];
-  const int64_t nvox = (int64_t)a.g.nx * a.g.ny * a.g.nz;
-  if (v < 0 || v >= nvox) {  // ids live on the device: reject out-of-grid ones here
-    for (int e = 0; e < 210; ++e) a.out[i * 210 + e] = __builtin_nan("");
-    return;
-  }
-  const int64_t ix = v % a.g.nx, iy = (v / a.g.nx) % a.g.ny, iz = v / ((int64_t)a.g.nx * a.g.ny);
-  const double tv[3] = {a.g.ox + (double)ix * a.g.h, a.g.oy + (double)iy * a.g.h,
-                        a.g.oz + (double)iz * a.g.h};
-  FT rec[kMom];
-  load_record<FT>(reinterpret_cast<const FT*>(a.field), (size_t)nvox, (size_t)v, (size_t)v, 0, rec);
+__device__ inline void paper_blocks(const FT* rec, const double tv[3], double scale, double* out) {
   double S4[15], S3[10], S2[6], S1[3], S0;   // G0
   double T4[15], T3[10], T2[6], T1[3], T0;   // G2
   expand_group<FT>(rec + O_G0_4, rec + O_G0_3, S4, S3, S2, S1, &S0);
@@ -378,7 +367,6 @@ __global__ void export_info_kernel(ExportArgs a) {
   for (int e = 0; e < 6; ++e) R2[e] = (double)rec[O_G1_2 + e];
 #pragma unroll
   for (int c = 0; c < 3; ++c) R1[c] = R3[s3(c, 0, 0)] + R3[s3(c, 1, 1)] + R3[s3(c, 2, 2)];
-  double* out = a.out + i * 210;
 #pragma unroll
   for (int k = 0; k < 10; ++k) {
     double sv0, sv2, Q0[6], Q2[6], bv[3];
@@ -427,10 +415,124 @@ __global__ void export_info_kernel(ExportArgs a) {
     B[3] = -bv[2]; B[4] = 0.0;    B[5] = bv[0];
     B[6] = bv[1];  B[7] = -bv[0]; B[8] = 0.0;
     double W[21];
-    shift_frame(A, B, D, tv, W);
+    shift_frame<double>(A, B, D, tv, W);
 #pragma unroll
-    for (int e = 0; e < 21; ++e) out[k * 21 + e] = W[e] * a.inv_s2;
+    for (int e = 0; e < 21; ++e) out[k * 21 + e] = W[e] * scale;
   }
+}
+
+template <typename FT>
+__global__ void export_info_kernel(ExportArgs a) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= a.n) return;
+  const int64_t v = a.ids[i];
+  const int64_t nvox = (int64_t)a.g.nx * a.g.ny * a.g.nz;
+  if (v < 0 || v >= nvox) {  // ids live on the device: reject out-of-grid ones here
+    for (int e = 0; e < 210; ++e) a.out[i * 210 + e] = __builtin_nan("");
+    return;
+  }
+  const int64_t ix = v % a.g.nx, iy = (v / a.g.nx) % a.g.ny, iz = v / ((int64_t)a.g.nx * a.g.ny);
+  const double tv[3] = {a.g.ox + (double)ix * a.g.h, a.g.oy + (double)iy * a.g.h,
+                        a.g.oz + (double)iz * a.g.h};
+  FT rec[kMom];
+  load_record<FT>(reinterpret_cast<const FT*>(a.field), (size_t)nvox, (size_t)v, (size_t)v, 0, rec);
+  paper_blocks<FT>(rec, tv, a.inv_s2, a.out + i * 210);
+}
+
+// ------------------------------------------------------------ view sweep
+
+constexpr int kSweepThreads = 256;
+
+// One workgroup per position: the 8 corner lanes expand their voxel into the
+// paper's world-frame blocks, the workgroup sums them (interpolation done
+// once), then every thread contracts the blocks with vr(z) for its axes.
+template <typename FT>
+__global__ __launch_bounds__(kSweepThreads) void view_sweep_kernel(SweepArgs a) {
+  __shared__ double s_part[8][210];
+  __shared__ double s_cbar[210];
+  __shared__ double s_bv[kSweepThreads];
+  __shared__ int64_t s_bi[kSweepThreads];
+  const int tid = threadIdx.x;
+  const int64_t p = blockIdx.x;
+  const FT* T = reinterpret_cast<const FT*>(a.t);
+  const double t[3] = {(double)T[3 * p], (double)T[3 * p + 1], (double)T[3 * p + 2]};
+  const size_t nvox = (size_t)a.g.nx * a.g.ny * a.g.nz;
+  if (tid < 8) {
+    const Corner c = make_corner(a.g, t, tid, a.interp);
+    if (c.active) {
+      FT rec[kMom];
+      const size_t cell = c.vox;  // own values sit in slot 0 of the voxel's own record
+      load_record<FT>(reinterpret_cast<const FT*>(a.field), nvox, c.vox, cell, 0, rec);
+      const int64_t ix = c.vox % a.g.nx, iy = (c.vox / a.g.nx) % a.g.ny,
+                    iz = c.vox / ((size_t)a.g.nx * a.g.ny);
+      const double tvx[3] = {a.g.ox + (double)ix * a.g.h, a.g.oy + (double)iy * a.g.h,
+                             a.g.oz + (double)iz * a.g.h};
+      paper_blocks<FT>(rec, tvx, a.vis.inv_s2 * c.w, s_part[tid]);
+    } else {
+      for (int e = 0; e < 210; ++e) s_part[tid][e] = 0.0;
+    }
+  }
+  __syncthreads();
+  for (int e = tid; e < 210; e += kSweepThreads) {
+    double sacc = 0.0;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) sacc += s_part[j][e];
+    s_cbar[e] = sacc;
+  }
+  __syncthreads();
+  const double k2 = a.vis.k2, k1 = a.vis.k1, k0 = a.vis.k0;
+  double best = -__builtin_inf();
+  int64_t bi = -1;
+  for (int64_t d = tid; d < a.n_dir; d += kSweepThreads) {
+    double z[3] = {a.dirs[3 * d], a.dirs[3 * d + 1], a.dirs[3 * d + 2]};
+    const double inv = 1.0 / sqrt(z[0] * z[0] + z[1] * z[1] + z[2] * z[2]);
+    z[0] *= inv; z[1] *= inv; z[2] *= inv;
+    const double vr[10] = {k2 * z[0] * z[0],       k2 * z[1] * z[1],       k2 * z[2] * z[2],
+                           2.0 * k2 * z[0] * z[1], 2.0 * k2 * z[0] * z[2], 2.0 * k2 * z[1] * z[2],
+                           k1 * z[0],              k1 * z[1],              k1 * z[2],
+                           k0};
+    double F[21];
+#pragma unroll
+    for (int e = 0; e < 21; ++e) {
+      double f = 0.0;
+#pragma unroll
+      for (int k = 0; k < 10; ++k) f = fma(vr[k], s_cbar[k * 21 + e], f);
+      F[e] = f;
+    }
+    double val;
+    uint8_t flag = 0;
+    eval_metrics<false>(F, a.metric, &val, &flag, nullptr, nullptr, false);
+    if (a.values) a.values[p * a.n_dir + d] = val;
+    if (val > best) {  // NaN never wins; d grows, so the first of equal values stays
+      best = val;
+      bi = d;
+    }
+  }
+  s_bv[tid] = best;
+  s_bi[tid] = bi;
+  __syncthreads();
+  for (int stride = kSweepThreads / 2; stride > 0; stride >>= 1) {
+    if (tid < stride) {
+      const double v2 = s_bv[tid + stride];
+      const int64_t i2v = s_bi[tid + stride];
+      const bool take = (i2v >= 0) && (s_bi[tid] < 0 || v2 > s_bv[tid] ||
+                                       (v2 == s_bv[tid] && i2v < s_bi[tid]));
+      if (take) {
+        s_bv[tid] = v2;
+        s_bi[tid] = i2v;
+      }
+    }
+    __syncthreads();
+  }
+  if (tid == 0 && a.best) a.best[p] = s_bi[0];
+}
+
+hipError_t launch_sweep(const SweepArgs& a, int prec, hipStream_t stream) {
+  if (a.n_pos <= 0) return hipSuccess;
+  dim3 grid((unsigned)a.n_pos), block(kSweepThreads);
+  if (prec == 2) hipLaunchKernelGGL((view_sweep_kernel<double>), grid, block, 0, stream, a);
+  else hipLaunchKernelGGL((view_sweep_kernel<float>), grid, block, 0, stream, a);
+  return hipGetLastError();
 }
 
 template <typename FT>

@@ -272,3 +272,21 @@ def request_stream(n_fields: int, rate_hz: float, n_requests: int, plan_pool: in
             out.append(RequestSpec(rid, float(arrivals[rid]), f, "opt", first * n_poses_traj,
                                    ntr * n_poses_traj))
     return out
+
+
+def sphere_axes(n: int) -> np.ndarray:
+    """n unit vectors spread evenly over the sphere (Fibonacci lattice): the
+    candidate optical axes of a dense view sweep."""
+    i = np.arange(n, dtype=np.float64) + 0.5
+    zc = 1.0 - 2.0 * i / n
+    r = np.sqrt(np.maximum(0.0, 1.0 - zc * zc))
+    phi = i * math.pi * (3.0 - math.sqrt(5.0))
+    return np.stack([r * np.cos(phi), r * np.sin(phi), zc], axis=1)
+
+
+def sweep_positions(grid: Grid, n: int = 200, seed: int = 2006,
+                    dtype=np.float32) -> np.ndarray:
+    """n positions for an optimal-view sweep (200 in Sec. VII-A), uniform in the
+    hull of the voxel centres like the building poses."""
+    rng = np.random.default_rng(seed)
+    return uniform_in_hull(rng, grid, n).astype(dtype)

@@ -90,6 +90,15 @@ def test_host_side_validation_returns_einval():
     assert L.pc_query(None, 0, ctypes.byref(vis.c()), ctypes.byref(cam), 2, None, None, 1, 1,
                       None, None) == -1
     assert L.fif_field_export(ctypes.byref(f), None, 3, None, None) == -1
+    # view sweep: exactly one metric, information fields, valid interp, t/dirs
+    assert L.fif_view_sweep(ctypes.byref(f), None, 4, None, 8, 3, 0, None, None, None) == -1
+    assert L.fif_view_sweep(ctypes.byref(f), None, 4, None, 8, 8, 0, None, None, None) == -1
+    assert L.fif_view_sweep(ctypes.byref(f), None, 4, None, 8, 1, 2, None, None, None) == -1
+    assert L.fif_view_sweep(ctypes.byref(f), None, 4, None, 8, 1, 0, None, None, None) == -1
+    assert L.fif_view_sweep(ctypes.byref(f), None, -1, None, 8, 1, 0, None, None, None) == -1
+    assert L.fif_view_sweep(ctypes.byref(f), None, 0, None, 8, 4, 0, None, None, None) == 0
+    assert L.fif_view_sweep(ctypes.byref(ftr), None, 4, None, 8, 1, 0, None, None,
+                            None) == -4
     gb = g.c()
     gb.reserved = 1
     fb = fif.CField(gb, vis.c(), fif.FP64, fif.KIND_INFO, 4096)

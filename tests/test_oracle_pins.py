@@ -451,3 +451,69 @@ def test_gradient_matches_central_fd():
             qm.append(scenes.rotation_to_quaternion(so3_exp(-e) @ R))
         fd = (L(t, np.array(qp)) - L(t, np.array(qm))) / (2 * hh)
         np.testing.assert_allclose(gphi[:, c], fd, rtol=2e-5, atol=1e-6 * np.abs(fd).max())
+
+
+# ------------------------------------------------------------ optimal-view sweep
+
+def axis_rotation(z):
+    """A rotation R_wc whose optical axis R e3 is the unit vector along z."""
+    z = np.asarray(z, float) / np.linalg.norm(z)
+    a = np.array([1.0, 0, 0]) if abs(z[0]) < 0.9 else np.array([0, 1.0, 0])
+    x = np.cross(a, z)
+    x /= np.linalg.norm(x)
+    return np.stack([x, np.cross(z, x), z], axis=1)
+
+
+def test_view_sweep_equals_pc_bruteforce_at_voxel_centres():
+    """Sec. VII-A relative measures: every swept value equals the point-cloud sum
+    (eq:vis_fim under the quadratic visibility) of the pose that looks along that
+    axis, at voxel centres where the interpolation is exact; the best index is
+    the first maximiser."""
+    lm, grid, vis = scenes.tiny_scene(n_landmarks=300)
+    ids = np.array([0, 57, 1234, 2399])
+    C = oracle.build(lm, grid.origin, grid.h, grid.shape, vis.sigma, voxel_ids=ids)
+    field = oracle.Field(C, grid.origin, grid.h, grid.shape, voxel_ids=ids)
+    rng = np.random.default_rng(60)
+    dirs = rng.standard_normal((24, 3))
+    dirs[5] = dirs[2]                  # an exact tie
+    dirs[7] = dirs[1] * 3.0            # same axis, unnormalised
+    t = np.stack([oracle.voxel_centre(grid.origin, grid.h, grid.shape, v) for v in ids])
+    for metric in (oracle.TRACE, oracle.LMIN, oracle.LOGDET):
+        values, best = oracle.view_sweep(field, vis.half_fov, vis.v_alpha, t, dirs, metric,
+                                         interp=1)
+        for a in range(len(ids)):
+            q = np.stack([scenes.rotation_to_quaternion(axis_rotation(d)) for d in dirs])
+            ref = oracle.pc_query(lm, vis.half_fov, vis.v_alpha, vis.sigma, vis.r_min,
+                                  vis.r_max, np.repeat(t[a:a + 1], len(dirs), 0), q, metric)[:, 0]
+            scale = np.abs(ref).max()
+            assert np.abs(values[a] - ref).max() <= 1e-9 * scale
+            assert values[a, 5] == values[a, 2]
+            assert abs(values[a, 7] - values[a, 1]) <= 1e-12 * scale
+            assert best[a] == int(np.argmax(values[a]))
+
+
+def test_view_sweep_roll_invariance_and_nan_rules():
+    """The swept value depends on the axis only (eq:quad_vis_component): a query
+    with any roll about that axis gives the same FIM metric; NaN axes never win,
+    and a position where every axis is NaN gets -1."""
+    lm, grid, vis = scenes.tiny_scene(n_landmarks=300)
+    C = oracle.build(lm, grid.origin, grid.h, grid.shape, vis.sigma)
+    field = oracle.Field(C, grid.origin, grid.h, grid.shape)
+    rng = np.random.default_rng(61)
+    dirs = rng.standard_normal((10, 3))
+    t = rng.uniform(-3, 3, (3, 3)) * np.array([1, 1, 0.3])
+    values, best = oracle.view_sweep(field, vis.half_fov, vis.v_alpha, t, dirs, oracle.LOGDET)
+    for a in range(3):
+        for d in range(10):
+            R = axis_rotation(dirs[d]) @ so3_exp(np.array([0, 0, rng.uniform(-3, 3)]))
+            q = scenes.rotation_to_quaternion(R)
+            ref, _ = oracle.query(field, vis.half_fov, vis.v_alpha, t[a:a + 1], q[None],
+                                  oracle.LOGDET)
+            assert abs(values[a, d] - ref[0, 0]) <= 1e-9 * max(1.0, abs(ref[0, 0]))
+    dz = np.concatenate([np.zeros((1, 3)), dirs[:3]])      # the zero axis gives NaN
+    v2, b2 = oracle.view_sweep(field, vis.half_fov, vis.v_alpha, t, dz, oracle.TRACE)
+    assert np.isnan(v2[:, 0]).all()
+    assert (b2 == 1 + np.argmax(v2[:, 1:], axis=1)).all()
+    v3, b3 = oracle.view_sweep(field, vis.half_fov, vis.v_alpha, t, np.zeros((2, 3)),
+                               oracle.TRACE)
+    assert np.isnan(v3).all() and (b3 == -1).all()
