@@ -211,26 +211,62 @@ __global__ __launch_bounds__(kQThreads) void query_info_kernel(QueryArgs a) {
   s_q[tid] = make_slot<FT>(a, ql);
   __syncthreads();
 
+  // Each lane handles corner j of the 8 queries of its group in turn.  With
+  // FP32 records on the forward path the next query's record is loaded before
+  // the current one is contracted, so the gathers of one wave stay in flight
+  // during its arithmetic (two waves per SIMD at this register count).
   CT Z[21];
 #pragma unroll
   for (int e = 0; e < 21; ++e) Z[e] = 0;
-  for (int it = 0; it < 8; ++it) {
-    const QSlot<CT> sl = s_q[wbase + grp * 8 + it];
-    const CornerC<CT> c = slot_corner(sl, a.g, j);
-    CT Y[21];
-    if (c.active) {
-      FT rec[kMom];
-      load_record<FT>(field, nvox, c.vox, c.cell, j, rec);
-      corner_fim<CT>(rec, vis_weights<CT>(sl.z, k2, k1, k0), c.dl, Y);
-#pragma unroll
-      for (int e = 0; e < 21; ++e) Y[e] *= c.w;
-    } else {
-#pragma unroll
-      for (int e = 0; e < 21; ++e) Y[e] = 0;
+  if constexpr (!GRAD && sizeof(FT) == 4) {
+    FT recN[kMom];
+    {
+      const CornerC<CT> c0 = slot_corner(s_q[wbase + grp * 8], a.g, j);
+      if (c0.active) load_record<FT>(field, nvox, c0.vox, c0.cell, j, recN);
     }
-    sum8_arr<21>(Y);
+#pragma unroll 1
+    for (int it = 0; it < 8; ++it) {
+      const QSlot<CT> sl = s_q[wbase + grp * 8 + it];
+      const CornerC<CT> c = slot_corner(sl, a.g, j);
+      FT rec[kMom];
 #pragma unroll
-    for (int e = 0; e < 21; ++e) Z[e] = (j == it) ? Y[e] : Z[e];
+      for (int e = 0; e < kMom; ++e) rec[e] = recN[e];
+      if (it < 7) {
+        const CornerC<CT> cn = slot_corner(s_q[wbase + grp * 8 + it + 1], a.g, j);
+        if (cn.active) load_record<FT>(field, nvox, cn.vox, cn.cell, j, recN);
+      }
+      CT Y[21];
+      if (c.active) {
+        corner_fim<CT>(rec, vis_weights<CT>(sl.z, k2, k1, k0), c.dl, Y);
+#pragma unroll
+        for (int e = 0; e < 21; ++e) Y[e] *= c.w;
+      } else {
+#pragma unroll
+        for (int e = 0; e < 21; ++e) Y[e] = 0;
+      }
+      sum8_arr<21>(Y);
+#pragma unroll
+      for (int e = 0; e < 21; ++e) Z[e] = (j == it) ? Y[e] : Z[e];
+    }
+  } else {
+    for (int it = 0; it < 8; ++it) {
+      const QSlot<CT> sl = s_q[wbase + grp * 8 + it];
+      const CornerC<CT> c = slot_corner(sl, a.g, j);
+      CT Y[21];
+      if (c.active) {
+        FT rec[kMom];
+        load_record<FT>(field, nvox, c.vox, c.cell, j, rec);
+        corner_fim<CT>(rec, vis_weights<CT>(sl.z, k2, k1, k0), c.dl, Y);
+#pragma unroll
+        for (int e = 0; e < 21; ++e) Y[e] *= c.w;
+      } else {
+#pragma unroll
+        for (int e = 0; e < 21; ++e) Y[e] = 0;
+      }
+      sum8_arr<21>(Y);
+#pragma unroll
+      for (int e = 0; e < 21; ++e) Z[e] = (j == it) ? Y[e] : Z[e];
+    }
   }
 
   const QSlot<CT> own = s_q[tid];
