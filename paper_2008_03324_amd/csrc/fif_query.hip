@@ -111,7 +111,7 @@ __device__ inline void load_pose(const QueryArgs& a, int64_t i, double t[3], dou
 // the 8 corner lanes of its group through LDS.
 template <typename CT>
 struct QSlot {
-  CT t[3];   // position (exact copy of the input)
+  CT t[3];   // frame point: the position clamped to the hull of voxel centres
   CT z[3];   // optical axis
   CT f[3];   // trilinear fractions
   CT df[3];  // d f / d t (1/h, or 0 where clamped)
@@ -120,10 +120,18 @@ struct QSlot {
 };
 
 template <typename FT>
+__device__ inline QSlot<FT> make_slot_from(const QueryArgs& a, double t[3], double z[3]);
+
+template <typename FT>
 __device__ inline QSlot<FT> make_slot(const QueryArgs& a, int64_t i) {
-  QSlot<FT> s;
   double t[3], z[3];
   load_pose<FT>(a, i, t, z);
+  return make_slot_from<FT>(a, t, z);
+}
+
+template <typename FT>
+__device__ inline QSlot<FT> make_slot_from(const QueryArgs& a, double t[3], double z[3]) {
+  QSlot<FT> s;
   const double o[3] = {a.g.ox, a.g.oy, a.g.oz};
   const int32_t n[3] = {a.g.nx, a.g.ny, a.g.nz};
   int32_t bits = 0;
@@ -328,6 +336,115 @@ __global__ __launch_bounds__(kQThreads) void query_info_kernel(QueryArgs a) {
   for (int c = 0; c < 3; ++c) {
     gt_out[3 * ql + c] = (FT)keep[c];
     gp_out[3 * ql + c] = (FT)gphi[c];
+  }
+}
+
+// Forward query on FP32 fields with persistent waves.  Each wave takes
+// batches of 64 queries in turn (the same per-query arithmetic and order as
+// query_info_kernel, so the results are bitwise identical).  The records of a
+// batch's next corner step are loaded before the current step is contracted,
+// and the first step of the wave's next batch is loaded before the current
+// batch's FP64 metric step, so the gathers stay in flight throughout.  The LDS
+// slots are private to a wave and no workgroup barrier is used: a wave leaves
+// as soon as its batches are done.
+constexpr int kPipeWaves = kQThreads / 64;
+
+__device__ inline void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+__global__ __launch_bounds__(kQThreads) void query_info_pipe_kernel(QueryArgs a, int64_t nbatch) {
+  using FT = float;
+  using CT = float;
+  __shared__ QSlot<CT> s_q[kPipeWaves][2][64];
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wv = tid >> 6;
+  const int grp = lane >> 3, j = lane & 7;
+  const int64_t gw = (int64_t)blockIdx.x * kPipeWaves + wv;
+  const int64_t nw = (int64_t)gridDim.x * kPipeWaves;
+  if (gw >= nbatch) return;  // whole wave
+  const FT* field = reinterpret_cast<const FT*>(a.field);
+  const size_t nvox = (size_t)a.g.nx * a.g.ny * a.g.nz;
+  const CT k2 = (CT)a.vis.k2, k1 = (CT)a.vis.k1, k0 = (CT)a.vis.k0;
+  const FT* T = reinterpret_cast<const FT*>(a.t);
+  const FT* Q = reinterpret_cast<const FT*>(a.q);
+  auto raw_pose = [&](int64_t b, FT tr[7]) {
+    const int64_t i = min(b * 64 + lane, a.m - 1);
+    tr[0] = T[3 * i]; tr[1] = T[3 * i + 1]; tr[2] = T[3 * i + 2];
+    tr[3] = Q[4 * i]; tr[4] = Q[4 * i + 1]; tr[5] = Q[4 * i + 2]; tr[6] = Q[4 * i + 3];
+  };
+  auto slot_of = [&](const FT tr[7]) {
+    double t[3] = {(double)tr[0], (double)tr[1], (double)tr[2]}, z[3];
+    quat_axis((double)tr[3], (double)tr[4], (double)tr[5], (double)tr[6], z);
+    return make_slot_from<FT>(a, t, z);
+  };
+  auto fetch = [&](const QSlot<CT>* sq, int it, FT* rec) {
+    const CornerC<CT> c = slot_corner(sq[grp * 8 + it], a.g, j);
+    if (c.active) load_record<FT>(field, nvox, c.vox, c.cell, j, rec);
+  };
+
+  int buf = 0;
+  {
+    FT tr[7];
+    raw_pose(gw, tr);
+    s_q[wv][0][lane] = slot_of(tr);
+  }
+  wave_sync();
+  FT recN[kMom];
+  fetch(s_q[wv][0], 0, recN);
+
+  for (int64_t b = gw; b < nbatch; b += nw) {
+    const QSlot<CT>* sq = s_q[wv][buf];
+    const bool more = b + nw < nbatch;
+    FT trn[7];
+    if (more) raw_pose(b + nw, trn);
+    CT Z[21];
+#pragma unroll
+    for (int e = 0; e < 21; ++e) Z[e] = 0;
+#pragma unroll 1
+    for (int it = 0; it < 8; ++it) {
+      const QSlot<CT> sl = sq[grp * 8 + it];
+      const CornerC<CT> c = slot_corner(sl, a.g, j);
+      FT rec[kMom];
+#pragma unroll
+      for (int e = 0; e < kMom; ++e) rec[e] = recN[e];
+      if (it < 7) fetch(sq, it + 1, recN);
+      CT Y[21];
+      if (c.active) {
+        corner_fim<CT>(rec, vis_weights<CT>(sl.z, k2, k1, k0), c.dl, Y);
+#pragma unroll
+        for (int e = 0; e < 21; ++e) Y[e] *= c.w;
+      } else {
+#pragma unroll
+        for (int e = 0; e < 21; ++e) Y[e] = 0;
+      }
+      sum8_arr<21>(Y);
+#pragma unroll
+      for (int e = 0; e < 21; ++e) Z[e] = (j == it) ? Y[e] : Z[e];
+    }
+    const QSlot<CT> own = sq[lane];
+    if (more) {
+      s_q[wv][buf ^ 1][lane] = slot_of(trn);
+      wave_sync();
+      fetch(s_q[wv][buf ^ 1], 0, recN);
+    }
+
+    const int64_t qi = b * 64 + lane;
+    const bool valid = qi < a.m;
+    double td[3] = {(double)own.t[0], (double)own.t[1], (double)own.t[2]};
+    double Zd[21], F[21];
+#pragma unroll
+    for (int e = 0; e < 21; ++e) Zd[e] = (double)Z[e];
+    shift21<double>(Zd, td, F);
+#pragma unroll
+    for (int e = 0; e < 21; ++e) F[e] *= a.vis.inv_s2;
+    uint8_t flag = (own.bits & 8) ? FL_CLAMPED : 0;
+    double* row = (valid && a.out) ? a.out + qi * a.ncols : nullptr;
+    eval_metrics<false>(F, a.metrics, row, &flag, nullptr, nullptr, a.flags != nullptr);
+    if (valid && a.flags) a.flags[qi] = flag;
+    buf ^= 1;
   }
 }
 
@@ -585,6 +702,18 @@ __global__ void export_trace_kernel(ExportArgs a) {
   for (int k = 0; k < 10; ++k) a.out[i * 10 + k] = (double)rec[k] * a.inv_s2;
 }
 
+// Workgroups of the persistent query: 8 per CU of the current device (two are
+// resident per CU at this kernel's register count; the rest even out the tail).
+static int64_t pipe_blocks() {
+  int dev = 0, cus = 256;
+  if (hipGetDevice(&dev) == hipSuccess) {
+    int v = 0;
+    if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && v > 0)
+      cus = v;
+  }
+  return (int64_t)cus * 8;
+}
+
 hipError_t launch_query(const QueryArgs& a, int prec, int kind, bool grad, hipStream_t stream) {
   if (a.m <= 0) return hipSuccess;
   const bool dbl = (prec == 2);
@@ -594,8 +723,15 @@ hipError_t launch_query(const QueryArgs& a, int prec, int kind, bool grad, hipSt
       if (dbl) hipLaunchKernelGGL((query_info_kernel<double, true>), grid, dim3(kQThreads), 0, stream, a);
       else hipLaunchKernelGGL((query_info_kernel<float, true>), grid, dim3(kQThreads), 0, stream, a);
     } else {
-      if (dbl) hipLaunchKernelGGL((query_info_kernel<double, false>), grid, dim3(kQThreads), 0, stream, a);
-      else hipLaunchKernelGGL((query_info_kernel<float, false>), grid, dim3(kQThreads), 0, stream, a);
+      if (dbl) {
+        hipLaunchKernelGGL((query_info_kernel<double, false>), grid, dim3(kQThreads), 0, stream, a);
+      } else {
+        const int64_t nbatch = (a.m + 63) / 64;
+        const int64_t want = (nbatch + kPipeWaves - 1) / kPipeWaves;
+        const int64_t cap = pipe_blocks();
+        dim3 pgrid((unsigned)(want < cap ? want : cap));
+        hipLaunchKernelGGL(query_info_pipe_kernel, pgrid, dim3(kQThreads), 0, stream, a, nbatch);
+      }
     }
   } else {
     dim3 grid((unsigned)((a.m + kQThreads - 1) / kQThreads));

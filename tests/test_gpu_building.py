@@ -255,3 +255,24 @@ def test_sorted_and_unsorted_builds_agree(fif, bld):
     st = fif.lib().fif_build(ctypes.c_void_p(bld["lm_d"].data_ptr()), bld["lm_d"].shape[0],
                              ctypes.byref(f.cstruct), ctypes.c_void_p(small.data_ptr()), 256, None)
     assert st == -2
+
+
+def test_forward_query_agrees_with_gradient_kernel_forward(fif, bld):
+    """The forward FP32 query (persistent waves, batches of 64 poses) and the
+    forward part of the gradient kernel (one batch per workgroup) evaluate the
+    same per-pose arithmetic: their metrics agree on ragged sizes, including a
+    size whose batches outnumber the resident waves many times over."""
+    print("case: forward vs gradient-kernel forward, ragged sizes", flush=True)
+    f = bld["field"]
+    for m in (1, 63, 64, 65, 1000, 4097, 300_001):
+        t = bld["t_d"][:m].contiguous()
+        q = bld["q_d"][:m].contiguous()
+        out = fif.query(f, t, q, M7)
+        _, _, out_g = fif.query_grad(f, t, q, M7, torch.zeros((m, 3), dtype=torch.float64,
+                                                              device="cuda"), want_out=True)
+        a, b = out.cpu().numpy(), out_g.cpu().numpy()
+        assert np.array_equal(np.isnan(a), np.isnan(b))
+        ok = ~np.isnan(a)
+        d = np.abs(a - b)[ok] / np.maximum(np.abs(b[ok]), 1e-300)
+        print(m, "bitwise" if np.array_equal(a[ok], b[ok]) else f"max rel {d.max():.2e}")
+        assert d.max() <= 1e-12
