@@ -268,6 +268,148 @@ def view_sweep(field: Field, alpha, v_alpha, t, dirs, metric, interp=0):
     return values, best
 
 
+# ------------------------------------------------------------ GP visibility
+
+def sigmoid_vis(ks, alpha, cos_theta) -> float:
+    f = lib().oracle_sigmoid_vis
+    f.restype = ctypes.c_double
+    return f(ctypes.c_double(ks), ctypes.c_double(alpha), ctypes.c_double(cos_theta))
+
+
+def gp_inverse(Z, length, noise) -> np.ndarray:
+    Z = _f64(Z, 3)
+    ns = Z.shape[0]
+    A = np.zeros((ns, ns))
+    if lib().oracle_gp_inverse(ctypes.c_int(ns), _p(Z), ctypes.c_double(length),
+                               ctypes.c_double(noise), _p(A)) != 0:
+        raise np.linalg.LinAlgError("K^s + noise I is not positive definite")
+    return A
+
+
+def gp_vr(Z, length, z) -> np.ndarray:
+    Z = _f64(Z, 3)
+    out = np.zeros(Z.shape[0])
+    lib().oracle_gp_vr(ctypes.c_int(Z.shape[0]), _p(Z), ctypes.c_double(length),
+                       _p(_f64(z).reshape(3)), _p(out))
+    return out
+
+
+def gp_vp(Z, ks, alpha, Ainv, u) -> np.ndarray:
+    Z = _f64(Z, 3)
+    out = np.zeros(Z.shape[0])
+    lib().oracle_gp_vp(ctypes.c_int(Z.shape[0]), _p(Z), ctypes.c_double(ks), ctypes.c_double(alpha),
+                       _p(_f64(Ainv)), _p(_f64(u).reshape(3)), _p(out))
+    return out
+
+
+def gp_build(landmarks, origin, h, shape, sigma, Z, ks, alpha, Ainv, r_min=0.0, r_max=np.inf,
+             trace=False, voxel_ids=None) -> np.ndarray:
+    """GP factors: [n_vox][ns][6][6] (information) or [n_vox][ns] (trace)."""
+    lm = _f64(landmarks, 3)
+    Z = _f64(Z, 3)
+    ns = Z.shape[0]
+    g = _grid(origin, h, shape)
+    if voxel_ids is None:
+        ids = None
+        n = int(np.prod(shape))
+    else:
+        ids = np.ascontiguousarray(voxel_ids, dtype=np.int64)
+        n = ids.shape[0]
+    per = ns if trace else ns * 36
+    C = np.zeros((n, per))
+    lib().oracle_gp_build(_p(lm), ctypes.c_int64(lm.shape[0]), ctypes.byref(g),
+                          ctypes.c_double(sigma), ctypes.c_double(r_min), ctypes.c_double(r_max),
+                          ctypes.c_int(ns), _p(Z), ctypes.c_double(ks), ctypes.c_double(alpha),
+                          _p(_f64(Ainv)), ctypes.c_int(1 if trace else 0), _p(ids),
+                          ctypes.c_int64(n), _p(C))
+    return C.reshape(n, ns) if trace else C.reshape(n, ns, 6, 6)
+
+
+class GPField:
+    """A GP factor field held by the oracle (all voxels, or a sparse subset)."""
+
+    def __init__(self, C, origin, h, shape, Z, length, trace=False, voxel_ids=None):
+        self.Z = _f64(Z, 3)
+        self.ns = self.Z.shape[0]
+        self.trace = bool(trace)
+        per = self.ns if trace else self.ns * 36
+        self.C = np.ascontiguousarray(C, dtype=np.float64).reshape(-1, per)
+        self.origin, self.h, self.shape = tuple(origin), float(h), tuple(int(s) for s in shape)
+        self.length = float(length)
+        if voxel_ids is not None:
+            order = np.argsort(voxel_ids, kind="stable")
+            self.ids = np.ascontiguousarray(np.asarray(voxel_ids, np.int64)[order])
+            self.C = np.ascontiguousarray(self.C[order])
+        else:
+            self.ids = None
+        self.grid = _grid(self.origin, self.h, self.shape)
+
+
+def gp_query(field: GPField, t, q, metrics_mask=7, interp=0, want_fim=False):
+    t = _f64(t, 3)
+    q = _f64(q, 4)
+    m = t.shape[0]
+    nc = 1 if field.trace else ncols(metrics_mask)
+    out = np.zeros((m, nc))
+    flags = np.zeros(m, np.uint8)
+    F = np.zeros((m, 36)) if (want_fim and not field.trace) else None
+    n = field.ids.shape[0] if field.ids is not None else field.C.shape[0]
+    rc = lib().oracle_gp_query(_p(field.C), _p(field.ids), ctypes.c_int64(n),
+                               ctypes.byref(field.grid), ctypes.c_int(field.ns),
+                               ctypes.c_int(1 if field.trace else 0), _p(field.Z),
+                               ctypes.c_double(field.length), _p(t), _p(q), ctypes.c_int64(m),
+                               ctypes.c_uint32(metrics_mask), ctypes.c_int(interp), _p(out),
+                               _p(flags), _p(F))
+    if rc != 0:
+        raise KeyError("oracle GP field is missing a voxel the query needs")
+    if want_fim and F is not None:
+        return out, flags, F.reshape(m, 6, 6)
+    return out, flags
+
+
+def gp_pc_fim(landmarks, sigma, r_min, r_max, Z, ks, alpha, length, Ainv, t, q) -> np.ndarray:
+    lm = _f64(landmarks, 3)
+    Z = _f64(Z, 3)
+    t = _f64(t, 3)
+    q = _f64(q, 4)
+    m = t.shape[0]
+    F = np.zeros((m, 36))
+    lib().oracle_gp_pc_fim(_p(lm), ctypes.c_int64(lm.shape[0]), ctypes.c_double(sigma),
+                           ctypes.c_double(r_min), ctypes.c_double(r_max), ctypes.c_int(Z.shape[0]),
+                           _p(Z), ctypes.c_double(ks), ctypes.c_double(alpha),
+                           ctypes.c_double(length), _p(_f64(Ainv)), _p(t), _p(q),
+                           ctypes.c_int64(m), _p(F))
+    return F.reshape(m, 6, 6)
+
+
+def gp_lml(Z, ks, alpha, length, noise, U) -> float:
+    f = lib().oracle_gp_lml
+    f.restype = ctypes.c_double
+    Z = _f64(Z, 3)
+    U = _f64(U, 3)
+    return f(ctypes.c_int(Z.shape[0]), _p(Z), ctypes.c_double(ks), ctypes.c_double(alpha),
+             ctypes.c_double(length), ctypes.c_double(noise), _p(U), ctypes.c_int(U.shape[0]))
+
+
+def gp_fit_length(Z, ks, alpha, noise, U, lo=0.05, hi=3.0, iters=60) -> float:
+    """ML-II length scale (Sec. V-B): golden-section search of gp_lml over
+    log l in [lo, hi] (the evidence is unimodal in l for these data)."""
+    a, b = np.log(lo), np.log(hi)
+    gr = (np.sqrt(5.0) - 1.0) / 2.0
+    c, d = b - gr * (b - a), a + gr * (b - a)
+    fc, fd = gp_lml(Z, ks, alpha, np.exp(c), noise, U), gp_lml(Z, ks, alpha, np.exp(d), noise, U)
+    for _ in range(iters):
+        if fc > fd:
+            b, d, fd = d, c, fc
+            c = b - gr * (b - a)
+            fc = gp_lml(Z, ks, alpha, np.exp(c), noise, U)
+        else:
+            a, c, fc = c, d, fd
+            d = a + gr * (b - a)
+            fd = gp_lml(Z, ks, alpha, np.exp(d), noise, U)
+    return float(np.exp((a + b) / 2))
+
+
 def corner_voxels(origin, h, shape, t) -> np.ndarray:
     """Voxel ids the trilinear query of each position reads (for sparse builds)."""
     t = _f64(t, 3)

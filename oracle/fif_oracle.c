@@ -540,6 +540,287 @@ int oracle_view_sweep(const double* field, const int64_t* field_ids, int64_t n_f
   return err ? -1 : 0;
 }
 
+/* ------------------------------------------------- GP visibility (f2) */
+
+/* Smooth visibility of eq:sigmoid_vis_func: 1 / (1 + exp(-k_s (cos theta -
+ * cos alpha))), the function the GP is trained to reproduce (Sec. V-B). */
+double oracle_sigmoid_vis(double ks, double alpha, double cos_theta) {
+  return 1.0 / (1.0 + exp(-ks * (cos_theta - cos(alpha))));
+}
+
+/* Squared-exponential kernel on unit vectors (Sec. V-B), signal variance 1:
+ * k(z1, z2) = exp(-|z1 - z2|^2 / (2 l^2)).  The posterior mean does not depend
+ * on the signal variance once the noise is expressed relative to it. */
+double oracle_gp_kernel(double l, const double z1[3], const double z2[3]) {
+  double d0 = z1[0] - z2[0], d1 = z1[1] - z2[1], d2 = z1[2] - z2[2];
+  return exp(-(d0 * d0 + d1 * d1 + d2 * d2) / (2.0 * l * l));
+}
+
+/* Lower Cholesky factor of the n x n symmetric matrix A (row-major, in place
+ * in L).  Returns 0, or -1 if A is not positive definite. */
+static int cholesky(int n, const double* A, double* L) {
+  memset(L, 0, (size_t)n * n * sizeof(double));
+  for (int j = 0; j < n; ++j) {
+    double s = A[j * n + j];
+    for (int k = 0; k < j; ++k) s -= L[j * n + k] * L[j * n + k];
+    if (!(s > 0.0)) return -1;
+    L[j * n + j] = sqrt(s);
+    for (int i = j + 1; i < n; ++i) {
+      double t = A[i * n + j];
+      for (int k = 0; k < j; ++k) t -= L[i * n + k] * L[j * n + k];
+      L[i * n + j] = t / L[j * n + j];
+    }
+  }
+  return 0;
+}
+
+/* K^s + noise I over the sample axes Z[ns][3] (Sec. V-B). */
+static void gp_ks(int ns, const double* Z, double l, double noise, double* K) {
+  for (int a = 0; a < ns; ++a)
+    for (int b = 0; b < ns; ++b)
+      K[a * ns + b] = oracle_gp_kernel(l, Z + 3 * a, Z + 3 * b) + (a == b ? noise : 0.0);
+}
+
+/* (K^s + noise I)^-1 (row-major ns x ns).  eq:gp_vis_approx prints
+ * K_z K^s v^s; the GP posterior mean it names (eq:gp_regress) is
+ * K_z (K^s + noise I)^-1 v^s, which is the reading taken here.  Columns of the
+ * inverse by two triangular solves per unit vector.  Returns 0 or -1. */
+int oracle_gp_inverse(int ns, const double* Z, double l, double noise, double* Ainv) {
+  double* K = (double*)malloc((size_t)ns * ns * sizeof(double));
+  double* L = (double*)malloc((size_t)ns * ns * sizeof(double));
+  double* y = (double*)malloc((size_t)ns * sizeof(double));
+  gp_ks(ns, Z, l, noise, K);
+  int rc = cholesky(ns, K, L);
+  for (int c = 0; rc == 0 && c < ns; ++c) {
+    for (int i = 0; i < ns; ++i) { /* L y = e_c */
+      double s = (i == c) ? 1.0 : 0.0;
+      for (int k = 0; k < i; ++k) s -= L[i * ns + k] * y[k];
+      y[i] = s / L[i * ns + i];
+    }
+    for (int i = ns - 1; i >= 0; --i) { /* L^T x = y */
+      double s = y[i];
+      for (int k = i + 1; k < ns; ++k) s -= L[k * ns + i] * Ainv[k * ns + c];
+      Ainv[i * ns + c] = s / L[i * ns + i];
+    }
+  }
+  free(K); free(L); free(y);
+  return rc;
+}
+
+/* vr = K_z = [k(z, z_g)]_g (Sec. V-B: vr depends only on the rotation). */
+void oracle_gp_vr(int ns, const double* Z, double l, const double z[3], double* vr) {
+  for (int g = 0; g < ns; ++g) vr[g] = oracle_gp_kernel(l, z, Z + 3 * g);
+}
+
+/* vp = (K^s + noise I)^-1 v^s(u), v^s_g = sigmoid visibility of z_g . u. */
+void oracle_gp_vp(int ns, const double* Z, double ks, double alpha, const double* Ainv,
+                  const double u[3], double* vp) {
+  double* vs = (double*)malloc((size_t)ns * sizeof(double));
+  for (int g = 0; g < ns; ++g) {
+    const double* zg = Z + 3 * g;
+    vs[g] = oracle_sigmoid_vis(ks, alpha, zg[0] * u[0] + zg[1] * u[1] + zg[2] * u[2]);
+  }
+  for (int g = 0; g < ns; ++g) {
+    double s = 0.0;
+    for (int h = 0; h < ns; ++h) s += Ainv[g * ns + h] * vs[h];
+    vp[g] = s;
+  }
+  free(vs);
+}
+
+/* GP information factor at t (eq:general_info_pif with N_v = N_s):
+ *   C_g = sum_{i in V_t} vp_g(u_i) I_i,  C[ns][36] row-major blocks;
+ * with trace != 0 the trace factor C_Tr,g = sum vp_g(u_i) Tr(I_i), C[ns]. */
+void oracle_gp_factor(const double* lm, int64_t L, const double t[3], double sigma, double r_min,
+                      double r_max, int ns, const double* Z, double ks, double alpha,
+                      const double* Ainv, int trace, double* C) {
+  static const double Rid[9] = {1, 0, 0, 0, 1, 0, 0, 0, 1};
+  const int blk = trace ? 1 : 36;
+  memset(C, 0, (size_t)ns * blk * sizeof(double));
+  double* vp = (double*)malloc((size_t)ns * sizeof(double));
+  for (int64_t i = 0; i < L; ++i) {
+    const double* p = lm + 3 * i;
+    if (!oracle_in_range(p, t, r_min, r_max)) continue;
+    double d[3] = {p[0] - t[0], p[1] - t[1], p[2] - t[2]};
+    double n = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+    double u[3] = {d[0] / n, d[1] / n, d[2] / n};
+    double I[36];
+    oracle_landmark_fim(p, t, Rid, sigma, I);
+    oracle_gp_vp(ns, Z, ks, alpha, Ainv, u, vp);
+    if (trace) {
+      double tr = 0.0;
+      for (int a = 0; a < 6; ++a) tr += I[a * 6 + a];
+      for (int g = 0; g < ns; ++g) C[g] += vp[g] * tr;
+    } else {
+      for (int g = 0; g < ns; ++g)
+        for (int e = 0; e < 36; ++e) C[g * 36 + e] += vp[g] * I[e];
+    }
+  }
+  free(vp);
+}
+
+/* GP factors of the listed voxels (all when voxel_ids == NULL). */
+void oracle_gp_build(const double* lm, int64_t L, const orc_grid* g, double sigma, double r_min,
+                     double r_max, int ns, const double* Z, double ks, double alpha,
+                     const double* Ainv, int trace, const int64_t* voxel_ids, int64_t n_vox,
+                     double* C) {
+  const int64_t per = (int64_t)ns * (trace ? 1 : 36);
+#pragma omp parallel for schedule(dynamic, 1)
+  for (int64_t a = 0; a < n_vox; ++a) {
+    int64_t v = voxel_ids ? voxel_ids[a] : a;
+    double t[3];
+    oracle_voxel_centre(g, v, t);
+    oracle_gp_factor(lm, L, t, sigma, r_min, r_max, ns, Z, ks, alpha, Ainv, trace, C + a * per);
+  }
+}
+
+static const double* gp_field_at(const double* field, const int64_t* ids, int64_t n_field,
+                                 int64_t per, int64_t v) {
+  if (!ids) return field + v * per;
+  int64_t lo = 0, hi = n_field - 1;
+  while (lo <= hi) {
+    int64_t mid = (lo + hi) / 2;
+    if (ids[mid] == v) return field + mid * per;
+    if (ids[mid] < v) lo = mid + 1; else hi = mid - 1;
+  }
+  return NULL;
+}
+
+/* GP field query (eq:fim_separation with vr = K_z): the factor is interpolated
+ * at t (trilinear over the 8 voxel centres, or the nearest one), then
+ *   F = sum_g vr_g(z) Cbar_g,   or for trace fields Tr = sum_g vr_g Cbar_Tr,g.
+ * Information fields: out[m][ncols] per the metric mask and F_out[m][36] if
+ * non-NULL; trace fields: out[m][1].  Returns 0 or -1 if a voxel is absent. */
+int oracle_gp_query(const double* field, const int64_t* ids, int64_t n_field, const orc_grid* g,
+                    int ns, int trace, const double* Z, double l, const double* t,
+                    const double* q, int64_t m, uint32_t metrics, int interp, double* out,
+                    uint8_t* flags, double* F_out) {
+  const int64_t per = (int64_t)ns * (trace ? 1 : 36);
+  int ncols = trace ? 1 : ((metrics & 1) != 0) + ((metrics & 2) != 0) + ((metrics & 4) != 0) +
+                              ((metrics & 8) ? 21 : 0);
+  int err = 0;
+#pragma omp parallel for schedule(static)
+  for (int64_t a = 0; a < m; ++a) {
+    double R[9], z[3];
+    oracle_quat_to_R(q + 4 * a, R);
+    z[0] = R[2]; z[1] = R[5]; z[2] = R[8];
+    double* vr = (double*)malloc((size_t)ns * sizeof(double));
+    double* Cbar = (double*)calloc((size_t)per, sizeof(double));
+    oracle_gp_vr(ns, Z, l, z, vr);
+    int clamped = 0, missing = 0;
+    if (interp == 1) {
+      int64_t id;
+      clamped = nearest(g, t + 3 * a, &id);
+      const double* C = gp_field_at(field, ids, n_field, per, id);
+      if (!C) missing = 1; else memcpy(Cbar, C, (size_t)per * sizeof(double));
+    } else {
+      int64_t vid[8];
+      double w[8], dw[8][3];
+      clamped = trilinear(g, t + 3 * a, vid, w, dw);
+      for (int j = 0; j < 8 && !missing; ++j) {
+        const double* C = gp_field_at(field, ids, n_field, per, vid[j]);
+        if (!C) { missing = 1; break; }
+        for (int64_t e = 0; e < per; ++e) Cbar[e] += w[j] * C[e];
+      }
+    }
+    if (missing) {
+      err = 1;
+    } else if (trace) {
+      double s = 0.0;
+      for (int k = 0; k < ns; ++k) s += vr[k] * Cbar[k];
+      out[a] = s;
+      if (flags) flags[a] = (uint8_t)(clamped ? 1 : 0);
+    } else {
+      double F[36];
+      for (int e = 0; e < 36; ++e) {
+        double s = 0.0;
+        for (int k = 0; k < ns; ++k) s += vr[k] * Cbar[k * 36 + e];
+        F[e] = s;
+      }
+      if (out) oracle_metrics(F, metrics, out + a * ncols);
+      if (F_out) memcpy(F_out + 36 * a, F, sizeof F);
+      if (flags) {
+        double ld = oracle_logdet6(F, NULL);
+        flags[a] = (uint8_t)((clamped ? 1 : 0) | (isnan(ld) ? 2 : 0));
+      }
+    }
+    free(vr);
+    free(Cbar);
+  }
+  return err ? -1 : 0;
+}
+
+/* Point-cloud FIM under the GP visibility (eq:vis_fim with v = v_gp(z, u_i) =
+ * vr(z) . vp(u_i), eq:gp_vis_approx): F = sum_{i in V_t} v_gp I_i. */
+void oracle_gp_pc_fim(const double* lm, int64_t L, double sigma, double r_min, double r_max,
+                      int ns, const double* Z, double ks, double alpha, double l,
+                      const double* Ainv, const double* t, const double* q, int64_t m,
+                      double* F_out) {
+#pragma omp parallel for schedule(static)
+  for (int64_t a = 0; a < m; ++a) {
+    double R[9], z[3];
+    oracle_quat_to_R(q + 4 * a, R);
+    z[0] = R[2]; z[1] = R[5]; z[2] = R[8];
+    double* vr = (double*)malloc((size_t)ns * sizeof(double));
+    double* vp = (double*)malloc((size_t)ns * sizeof(double));
+    oracle_gp_vr(ns, Z, l, z, vr);
+    double F[36] = {0};
+    const double* ta = t + 3 * a;
+    for (int64_t i = 0; i < L; ++i) {
+      const double* p = lm + 3 * i;
+      if (!oracle_in_range(p, ta, r_min, r_max)) continue;
+      double d[3] = {p[0] - ta[0], p[1] - ta[1], p[2] - ta[2]};
+      double n = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+      double u[3] = {d[0] / n, d[1] / n, d[2] / n};
+      double I[36];
+      oracle_landmark_fim(p, ta, R, sigma, I);
+      oracle_gp_vp(ns, Z, ks, alpha, Ainv, u, vp);
+      double v = 0.0;
+      for (int k = 0; k < ns; ++k) v += vr[k] * vp[k];
+      for (int e = 0; e < 36; ++e) F[e] += v * I[e];
+    }
+    memcpy(F_out + 36 * a, F, sizeof F);
+    free(vr);
+    free(vp);
+  }
+}
+
+/* Log marginal likelihood of the length scale l (Sec. V-B hyperparameters; the
+ * standard GP evidence): with K_y = K^s + noise I and one output vector per
+ * training direction u_t, y_t[g] = sigmoid visibility of z_g . u_t,
+ *   log p = sum_t (-1/2 y_t^T K_y^-1 y_t) - n_train/2 log|K_y| - n_train ns/2 log 2 pi.
+ * U[n_train][3].  Returns -INFINITY if K_y is not positive definite. */
+double oracle_gp_lml(int ns, const double* Z, double ks, double alpha, double l, double noise,
+                     const double* U, int n_train) {
+  double* K = (double*)malloc((size_t)ns * ns * sizeof(double));
+  double* L = (double*)malloc((size_t)ns * ns * sizeof(double));
+  double* y = (double*)malloc((size_t)ns * sizeof(double));
+  double* w = (double*)malloc((size_t)ns * sizeof(double));
+  gp_ks(ns, Z, l, noise, K);
+  double res = -INFINITY;
+  if (cholesky(ns, K, L) == 0) {
+    double logdet = 0.0;
+    for (int i = 0; i < ns; ++i) logdet += 2.0 * log(L[i * ns + i]);
+    double quad = 0.0;
+    for (int tt = 0; tt < n_train; ++tt) {
+      const double* u = U + 3 * tt;
+      for (int g = 0; g < ns; ++g) {
+        const double* zg = Z + 3 * g;
+        y[g] = oracle_sigmoid_vis(ks, alpha, zg[0] * u[0] + zg[1] * u[1] + zg[2] * u[2]);
+      }
+      for (int i = 0; i < ns; ++i) { /* L w = y, then y^T K^-1 y = |w|^2 */
+        double s = y[i];
+        for (int k = 0; k < i; ++k) s -= L[i * ns + k] * w[k];
+        w[i] = s / L[i * ns + i];
+      }
+      for (int i = 0; i < ns; ++i) quad += w[i] * w[i];
+    }
+    res = -0.5 * quad - 0.5 * n_train * logdet - 0.5 * n_train * ns * log(2.0 * M_PI);
+  }
+  free(K); free(L); free(y); free(w);
+  return res;
+}
+
 /* ---------------------------------------------------------- gradient */
 
 /* d s / d F for each metric (symmetric 6x6): trace -> I, lmin -> v v^T with v

@@ -517,3 +517,137 @@ def test_view_sweep_roll_invariance_and_nan_rules():
     v3, b3 = oracle.view_sweep(field, vis.half_fov, vis.v_alpha, t, np.zeros((2, 3)),
                                oracle.TRACE)
     assert np.isnan(v3).all() and (b3 == -1).all()
+
+
+# ------------------------------------------------------------ GP visibility (f2)
+
+KS = 15.0
+NOISE = 1e-10
+
+
+def _unit(rng, n):
+    u = rng.standard_normal((n, 3))
+    return u / np.linalg.norm(u, axis=1, keepdims=True)
+
+
+def _np_gp(Z, length):
+    """numpy reference pieces: K^s + noise I and its solve (library routines)."""
+    K = np.exp(-((Z[:, None, :] - Z[None, :, :]) ** 2).sum(-1) / (2 * length * length))
+    return K + NOISE * np.eye(len(Z))
+
+
+def _np_vgp(Z, length, z, u):
+    """v_gp(z, u) = K_z (K^s + noise I)^-1 v^s(u) with numpy's solver."""
+    Ky = _np_gp(Z, length)
+    kz = np.exp(-((z[None, :] - Z) ** 2).sum(-1) / (2 * length * length))
+    vs = 1.0 / (1.0 + np.exp(-KS * (Z @ u - math.cos(ALPHA))))
+    return kz @ np.linalg.solve(Ky, vs)
+
+
+@pytest.fixture(scope="module")
+def gp30():
+    Z = scenes.sphere_axes(30)
+    U = _unit(np.random.default_rng(90), 200)
+    length = oracle.gp_fit_length(Z, KS, ALPHA, NOISE, U)
+    return Z, U, length, oracle.gp_inverse(Z, length, NOISE)
+
+
+def test_gp_sigmoid_and_inverse(gp30):
+    Z, U, length, A = gp30
+    # eq:sigmoid_vis_func: 1/2 at the FoV boundary, -> 1 on axis, -> 0 behind
+    assert abs(oracle.sigmoid_vis(KS, ALPHA, math.cos(ALPHA)) - 0.5) < 1e-15
+    assert oracle.sigmoid_vis(KS, ALPHA, 1.0) > 0.98 and oracle.sigmoid_vis(KS, ALPHA, -1.0) < 1e-10
+    Ky = _np_gp(Z, length)
+    assert np.abs(A @ Ky - np.eye(len(Z))).max() < 1e-8
+    assert np.abs(A - np.linalg.inv(Ky)).max() <= 1e-9 * np.abs(A).max()
+
+
+def test_gp_lml_and_ml2_length(gp30):
+    """Evidence vs numpy (slogdet, solve); the fitted length maximises it over
+    a dense grid (brute force)."""
+    Z, U, length, _ = gp30
+    Ky = _np_gp(Z, length)
+    Y = 1.0 / (1.0 + np.exp(-KS * (U @ Z.T - math.cos(ALPHA))))
+    ref = (-0.5 * np.einsum("tg,tg->", Y, np.linalg.solve(Ky, Y.T).T)
+           - 0.5 * len(U) * np.linalg.slogdet(Ky)[1] - 0.5 * len(U) * len(Z) * math.log(2 * math.pi))
+    got = oracle.gp_lml(Z, KS, ALPHA, length, NOISE, U)
+    assert abs(got - ref) <= 1e-9 * abs(ref)
+    grid = np.geomspace(0.1, 2.5, 200)
+    vals = [oracle.gp_lml(Z, KS, ALPHA, l, NOISE, U) for l in grid]
+    assert got >= max(vals) - 1e-6 * abs(got)
+    assert 0.5 < length < 1.5
+
+
+def test_gp_visibility_interpolates_and_approximates(gp30):
+    """The GP mean reproduces the training values at the sample axes and
+    approximates the sigmoid between them, better with more samples."""
+    Z, U, length, A = gp30
+    rng = np.random.default_rng(91)
+    for u in _unit(rng, 5):
+        vp = oracle.gp_vp(Z, KS, ALPHA, A, u)
+        for g in (0, 7, 29):
+            v = oracle.gp_vr(Z, length, Z[g]) @ vp
+            assert abs(v - oracle.sigmoid_vis(KS, ALPHA, Z[g] @ u)) < 1e-4
+        z = _unit(rng, 1)[0]
+        assert abs(oracle.gp_vr(Z, length, z) @ vp - _np_vgp(Z, length, z, u)) < 1e-8
+    errs = {}
+    for ns in (30, 150):
+        Zn = scenes.sphere_axes(ns)
+        ln = oracle.gp_fit_length(Zn, KS, ALPHA, NOISE, U)
+        An = oracle.gp_inverse(Zn, ln, NOISE)
+        e = 0.0
+        for u, z in zip(_unit(rng, 40), _unit(rng, 40)):
+            v = oracle.gp_vr(Zn, ln, z) @ oracle.gp_vp(Zn, KS, ALPHA, An, u)
+            e = max(e, abs(v - oracle.sigmoid_vis(KS, ALPHA, z @ u)))
+        errs[ns] = e
+    assert errs[150] < errs[30] and errs[150] < 0.15
+
+
+def test_gp_field_at_voxel_centre_equals_bruteforce(gp30):
+    """eq:fim_separation with the GP model: at a voxel centre the field equals
+    sum_i v_gp(z, u_i) J_i^T J_i / sigma^2 with FD Jacobians and numpy's GP."""
+    Z, U, length, A = gp30
+    rng = np.random.default_rng(92)
+    lm = rng.uniform(-2, 2, (8, 3))
+    origin, h, shape = (-0.5, -0.5, -0.5), 1.0, (2, 2, 2)
+    C = oracle.gp_build(lm, origin, h, shape, SIG, Z, KS, ALPHA, A)
+    field = oracle.GPField(C, origin, h, shape, Z, length)
+    for v in (0, 5):
+        t = oracle.voxel_centre(origin, h, shape, v)
+        for _ in range(2):
+            R = random_rotation(rng)
+            q = scenes.rotation_to_quaternion(R)
+            F_bf = np.zeros((6, 6))
+            for p in lm:
+                u = (p - t) / np.linalg.norm(p - t)
+                J = fd_jacobian(R, t, p)
+                F_bf += _np_vgp(Z, length, R[:, 2], u) * (J.T @ J) / SIG ** 2
+            for interp in (0, 1):
+                _, _, F = oracle.gp_query(field, t[None], q[None], 7, interp, want_fim=True)
+                assert np.abs(F[0] - F_bf).max() < 1e-6 * np.abs(F_bf).max()
+            F_pc = oracle.gp_pc_fim(lm, SIG, 0.0, np.inf, Z, KS, ALPHA, length, A, t[None],
+                                    q[None])[0]
+            assert np.abs(F_pc - F_bf).max() < 1e-6 * np.abs(F_bf).max()
+            # roll about the optical axis leaves the GP FIM unchanged
+            q2 = scenes.rotation_to_quaternion(R @ so3_exp(np.array([0, 0, 1.1])))
+            _, _, F2 = oracle.gp_query(field, t[None], q2[None], 7, 0, want_fim=True)
+            assert np.abs(F2[0] - F_bf).max() < 1e-6 * np.abs(F_bf).max()
+
+
+def test_gp_trace_factor_is_trace_of_information_factor(gp30):
+    Z, U, length, A = gp30
+    lm, grid, vis = scenes.tiny_scene(n_landmarks=200)
+    ids = np.array([3, 777, 2000])
+    CI = oracle.gp_build(lm, grid.origin, grid.h, grid.shape, vis.sigma, Z, KS, ALPHA, A,
+                         voxel_ids=ids)
+    CT = oracle.gp_build(lm, grid.origin, grid.h, grid.shape, vis.sigma, Z, KS, ALPHA, A,
+                         trace=True, voxel_ids=ids)
+    tr = np.trace(CI, axis1=2, axis2=3)
+    assert np.abs(CT - tr).max() <= 1e-12 * np.abs(tr).max()
+    fi = oracle.GPField(CI, grid.origin, grid.h, grid.shape, Z, length, voxel_ids=ids)
+    ft = oracle.GPField(CT, grid.origin, grid.h, grid.shape, Z, length, trace=True, voxel_ids=ids)
+    t = np.stack([oracle.voxel_centre(grid.origin, grid.h, grid.shape, v) for v in ids])
+    q = scenes.haar_quaternions(np.random.default_rng(93), 3)
+    a, _ = oracle.gp_query(fi, t, q, 1, interp=1)
+    b, _ = oracle.gp_query(ft, t, q, 1, interp=1)
+    assert np.abs(a - b).max() <= 1e-12 * np.abs(a).max()
