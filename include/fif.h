@@ -188,6 +188,87 @@ fif_status fif_view_sweep(const fif_field* field, const void* t, int64_t n_pos,
 fif_status fif_field_export(const fif_field* field, const int64_t* voxel_ids, int64_t n,
                             double* blocks, void* stream);
 
+/* ------------------------------------------------------------------------
+ * GP visibility fields (Sec. V-B "GP Regression"; G-I-N_s / G-T-N_s of Sec.
+ * VII-A).  The visibility of a landmark with bearing u seen along optical axis
+ * z is the GP posterior mean
+ *   v_gp(z, u) = K_z (K^s + noise I)^-1 v^s(u),
+ *   K_z[g] = k(z, z_g),  K^s[g][h] = k(z_g, z_h),  k(a, b) = exp(-|a - b|^2 / (2 l^2)),
+ *   v^s_g(u) = 1 / (1 + exp(-k_s (z_g . u - cos alpha)))      (eq:sigmoid_vis_func)
+ * over N_s sample axes z_g.  eq:gp_vis_approx prints K_z K^s v^s; the inverse
+ * of the posterior mean is the reading taken here.  So vr = K_z and
+ * vp = (K^s + noise I)^-1 v^s in eq:fim_separation, N_v = N_s.
+ *
+ * The device buffer stores, per voxel and sample axis, the sums of v^s_g(u_i)
+ * times the camera-frame terms of I_i (information fields) or of v^s_g(u_i)
+ * Tr(I_i) (trace fields); the inverse is applied on the query side.  The field
+ * therefore depends on the axes, k_s, alpha, the range bounds and the
+ * precision, but not on l or the noise.  fif_gp_export recovers the paper's
+ * factors C_g = sum_i vp_g(u_i) I_i.
+ * ---------------------------------------------------------------------- */
+
+#define FIF_GP_MAX_NS 160 /* largest N_s (the paper uses 30..150) */
+
+typedef struct {
+  int32_t n_s;        /* number of sample axes, 1..FIF_GP_MAX_NS */
+  int32_t reserved;   /* must be 0 */
+  double k_s;         /* sigmoid slope (15 in the paper) */
+  double length;      /* SE length scale l > 0 */
+  double noise;       /* variance added to the diagonal of K^s (1e-10 in the paper) */
+  const double* axes; /* device double[n_s][3], unit sample axes */
+  double* kinv;       /* device double[n_s][n_s]: (K^s + noise I)^-1, filled by fif_gp_setup */
+} fif_gp;
+
+typedef struct {
+  fif_grid grid;
+  fif_vis vis;  /* half_fov = alpha of the sigmoid, sigma_bearing, r_min, r_max (v_alpha unused) */
+  fif_gp gp;
+  int32_t prec; /* FIF_FP32_NAIVE | FIF_FP32_COMP | FIF_FP64 */
+  int32_t kind; /* FIF_KIND_INFO | FIF_KIND_TRACE */
+  void* data;   /* device buffer of fif_gp_field_bytes() bytes, 256-B aligned */
+} fif_gp_field;
+
+/* Bytes of the device buffer of a GP field; 0 for invalid arguments. */
+size_t fif_gp_field_bytes(const fif_grid* grid, int32_t n_s, int32_t prec, int32_t kind);
+
+/* (K^s + noise I)^-1 of the model into gp->kinv (FP64 Cholesky on the device).
+ * FIF_EINVAL for n_s out of range, NULL pointers or l <= 0.  A matrix that is
+ * not positive definite gives NaN in kinv (no error: detected on the device). */
+fif_status fif_gp_setup(const fif_gp* gp, void* stream);
+
+/* Log marginal likelihood of each candidate length scale (Sec. V-B: l is
+ * chosen by maximising it), for training outputs y_t[g] = v^s_g(u_t) at the
+ * training bearings u_t (unit, device double[n_train][3]):
+ *   sum_t -1/2 y_t^T K_y^-1 y_t - n_train/2 log|K_y| - n_train n_s/2 log 2 pi,
+ * K_y = K^s(l) + noise I.  lengths: device double[n_len]; lml: device
+ * double[n_len] (-inf where K_y is not positive definite).  gp->length and
+ * gp->kinv are not used. */
+fif_status fif_gp_evidence(const fif_gp* gp, double half_fov, const double* train_u,
+                           int32_t n_train, const double* lengths, int32_t n_len, double* lml,
+                           void* stream);
+
+/* Build a GP field (eq:general_info_pif / eq:general_trace_pif with the GP vp)
+ * at every voxel centre from the landmarks in range (same V_t predicate as
+ * fif_build).  workspace: NULL or fif_workspace_bytes(grid, n_landmarks, prec)
+ * bytes (spatial ordering and batch culling, as fif_build).  field->gp.axes
+ * must be set; kinv is not used by the build. */
+fif_status fif_gp_build(const double* landmarks, int64_t n_landmarks, fif_gp_field* field,
+                        void* workspace, size_t workspace_bytes, void* stream);
+
+/* Batched pose query of a GP field: F = sum_g K_z[g] Cbar_g with the factors
+ * interpolated at t (eq:fim_separation), metrics and layouts as fif_query
+ * (trace fields: FIF_TRACE only).  field->gp.kinv must hold fif_gp_setup's
+ * result for field->gp. */
+fif_status fif_gp_query(const fif_gp_field* field, const void* t, const void* q, int64_t m,
+                        uint32_t metrics, int32_t interp, double* out, uint8_t* flags,
+                        void* stream);
+
+/* The paper's GP factors of the listed voxels: information fields
+ * blocks[n][n_s][21] = C_g = sum_i vp_g(u_i) I_i in world coordinates (upper
+ * triangle row-major); trace fields blocks[n][n_s].  Needs kinv. */
+fif_status fif_gp_export(const fif_gp_field* field, const int64_t* voxel_ids, int64_t n,
+                         double* blocks, void* stream);
+
 /* Static string for a status code. */
 const char* fif_status_string(fif_status status);
 

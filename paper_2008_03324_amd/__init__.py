@@ -58,6 +58,17 @@ class CField(ctypes.Structure):
                 ("kind", ctypes.c_int32), ("data", ctypes.c_void_p)]
 
 
+class CGP(ctypes.Structure):
+    _fields_ = [("n_s", ctypes.c_int32), ("reserved", ctypes.c_int32), ("k_s", ctypes.c_double),
+                ("length", ctypes.c_double), ("noise", ctypes.c_double),
+                ("axes", ctypes.c_void_p), ("kinv", ctypes.c_void_p)]
+
+
+class CGPField(ctypes.Structure):
+    _fields_ = [("grid", CGrid), ("vis", CVis), ("gp", CGP), ("prec", ctypes.c_int32),
+                ("kind", ctypes.c_int32), ("data", ctypes.c_void_p)]
+
+
 EXPORTS = {
     "fif_field_bytes": (ctypes.c_size_t, [ctypes.POINTER(CGrid), ctypes.c_int32, ctypes.c_int32]),
     "fif_workspace_bytes": (ctypes.c_size_t, [ctypes.POINTER(CGrid), ctypes.c_int64, ctypes.c_int32]),
@@ -82,6 +93,19 @@ EXPORTS = {
                                         ctypes.c_void_p]),
     "fif_field_export": (ctypes.c_int32, [ctypes.POINTER(CField), ctypes.c_void_p, ctypes.c_int64,
                                           ctypes.c_void_p, ctypes.c_void_p]),
+    "fif_gp_field_bytes": (ctypes.c_size_t, [ctypes.POINTER(CGrid), ctypes.c_int32,
+                                             ctypes.c_int32, ctypes.c_int32]),
+    "fif_gp_setup": (ctypes.c_int32, [ctypes.POINTER(CGP), ctypes.c_void_p]),
+    "fif_gp_evidence": (ctypes.c_int32, [ctypes.POINTER(CGP), ctypes.c_double, ctypes.c_void_p,
+                                         ctypes.c_int32, ctypes.c_void_p, ctypes.c_int32,
+                                         ctypes.c_void_p, ctypes.c_void_p]),
+    "fif_gp_build": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int64, ctypes.POINTER(CGPField),
+                                      ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p]),
+    "fif_gp_query": (ctypes.c_int32, [ctypes.POINTER(CGPField), ctypes.c_void_p, ctypes.c_void_p,
+                                      ctypes.c_int64, ctypes.c_uint32, ctypes.c_int32,
+                                      ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
+    "fif_gp_export": (ctypes.c_int32, [ctypes.POINTER(CGPField), ctypes.c_void_p, ctypes.c_int64,
+                                       ctypes.c_void_p, ctypes.c_void_p]),
     "fif_status_string": (ctypes.c_char_p, [ctypes.c_int32]),
     "fif_last_error": (ctypes.c_char_p, []),
 }
@@ -320,6 +344,130 @@ def export_blocks(field: Field, voxel_ids: torch.Tensor, stream=None) -> torch.T
     out = torch.empty(shape, dtype=torch.float64, device=ids.device)
     _check(lib().fif_field_export(ctypes.byref(field.cstruct), _ptr(ids), n, _ptr(out),
                                   _stream(stream)), "fif_field_export")
+    return out
+
+
+# ------------------------------------------------------------ GP visibility fields
+
+class GPModel:
+    """GP visibility model (Sec. V-B): sample axes [n_s, 3] (float64, device),
+    sigmoid slope k_s, SE length scale and noise; holds (K^s + noise I)^-1."""
+
+    def __init__(self, axes: torch.Tensor, k_s: float = 15.0, length: float | None = None,
+                 noise: float = 1e-10):
+        self.axes = _dev(axes, torch.float64, "axes", 3)
+        self.n_s = int(self.axes.shape[0])
+        self.k_s, self.noise = float(k_s), float(noise)
+        self.kinv = torch.empty((self.n_s, self.n_s), dtype=torch.float64, device=self.axes.device)
+        self.length = None
+        if length is not None:
+            self.set_length(length)
+
+    def c(self) -> CGP:
+        return CGP(self.n_s, 0, self.k_s, float(self.length or 0.0), self.noise,
+                   self.axes.data_ptr(), self.kinv.data_ptr())
+
+    def set_length(self, length: float, stream=None) -> "GPModel":
+        self.length = float(length)
+        _check(lib().fif_gp_setup(ctypes.byref(self.c()), _stream(stream)), "fif_gp_setup")
+        return self
+
+    def evidence(self, half_fov: float, train_u: torch.Tensor, lengths: torch.Tensor,
+                 stream=None) -> torch.Tensor:
+        u = _dev(train_u, torch.float64, "train_u", 3)
+        ls = _dev(lengths.reshape(-1).contiguous(), torch.float64, "lengths")
+        out = torch.empty(ls.numel(), dtype=torch.float64, device=ls.device)
+        _check(lib().fif_gp_evidence(ctypes.byref(self.c()), float(half_fov), _ptr(u), u.shape[0],
+                                     _ptr(ls), ls.numel(), _ptr(out), _stream(stream)),
+               "fif_gp_evidence")
+        return out
+
+    def fit_length(self, half_fov: float, train_u: torch.Tensor, lo: float = 0.05,
+                   hi: float = 3.0, n: int = 64, rounds: int = 4) -> float:
+        """ML-II length scale (Sec. V-B): the evidence of a log-spaced grid of
+        candidates is evaluated on the device, and the grid is narrowed around
+        the best one each round; then the model is set up with it."""
+        a, b = math.log(lo), math.log(hi)
+        best = None
+        for _ in range(rounds):
+            ls = torch.exp(torch.linspace(a, b, n, dtype=torch.float64, device=self.axes.device))
+            ev = self.evidence(half_fov, train_u, ls).cpu()
+            i = int(torch.argmax(ev))
+            best = float(ls[i])
+            step = (b - a) / (n - 1)
+            a, b = math.log(best) - step, math.log(best) + step
+        self.set_length(best)
+        return best
+
+
+def gp_field_bytes(grid: Grid, n_s: int, prec: int, kind: int = KIND_INFO) -> int:
+    return int(lib().fif_gp_field_bytes(ctypes.byref(grid.c()), int(n_s), prec, kind))
+
+
+class GPField:
+    """A GP field resident in HBM (buffer + header) with its model."""
+
+    def __init__(self, grid: Grid, vis: Vis, model: GPModel, prec: int = FP32_COMP,
+                 kind: int = KIND_INFO, device=None):
+        nbytes = gp_field_bytes(grid, model.n_s, prec, kind)
+        if nbytes == 0:
+            raise ValueError("invalid grid, n_s, precision or kind")
+        self.grid, self.vis, self.model, self.prec, self.kind = grid, vis, model, prec, kind
+        self.buffer = torch.empty(nbytes, dtype=torch.uint8, device=device or model.axes.device)
+
+    @property
+    def cstruct(self) -> CGPField:
+        return CGPField(self.grid.c(), self.vis.c(), self.model.c(), self.prec, self.kind,
+                        self.buffer.data_ptr())
+
+    @property
+    def pose_dtype(self):
+        return torch.float64 if self.prec == FP64 else torch.float32
+
+    @property
+    def nbytes(self) -> int:
+        return self.buffer.numel()
+
+
+def gp_build(landmarks: torch.Tensor, grid: Grid, vis: Vis, model: GPModel,
+             prec: int = FP32_COMP, kind: int = KIND_INFO, field: GPField | None = None,
+             sort: bool = True, stream=None) -> GPField:
+    lm = _dev(landmarks, torch.float64, "landmarks", 3)
+    if field is None:
+        field = GPField(grid, vis, model, prec, kind, device=lm.device)
+    ws = workspace(grid, lm.shape[0], prec, lm.device) if sort else None
+    cs = field.cstruct
+    _check(lib().fif_gp_build(_ptr(lm), lm.shape[0], ctypes.byref(cs), _ptr(ws),
+                              ws.numel() if ws is not None else 0, _stream(stream)), "fif_gp_build")
+    return field
+
+
+def gp_query(field: GPField, t: torch.Tensor, q: torch.Tensor,
+             metrics: int = TRACE | LMIN | LOGDET, interp: int = TRILINEAR,
+             out: torch.Tensor | None = None, want_flags: bool = False, stream=None):
+    dt = field.pose_dtype
+    t = _dev(t, dt, "t", 3)
+    q = _dev(q, dt, "q", 4)
+    m = t.shape[0]
+    if q.shape[0] != m:
+        raise ValueError("t and q differ in length")
+    if out is None:
+        out = torch.empty((m, ncols(metrics)), dtype=torch.float64, device=t.device)
+    flags = torch.empty(m, dtype=torch.uint8, device=t.device) if want_flags else None
+    cs = field.cstruct
+    _check(lib().fif_gp_query(ctypes.byref(cs), _ptr(t), _ptr(q), m, metrics, interp, _ptr(out),
+                              _ptr(flags), _stream(stream)), "fif_gp_query")
+    return (out, flags) if want_flags else out
+
+
+def gp_export(field: GPField, voxel_ids: torch.Tensor, stream=None) -> torch.Tensor:
+    ids = _dev(voxel_ids, torch.int64, "voxel_ids")
+    n, ns = ids.numel(), field.model.n_s
+    shape = (n, ns, 21) if field.kind == KIND_INFO else (n, ns)
+    out = torch.empty(shape, dtype=torch.float64, device=ids.device)
+    cs = field.cstruct
+    _check(lib().fif_gp_export(ctypes.byref(cs), _ptr(ids), n, _ptr(out), _stream(stream)),
+           "fif_gp_export")
     return out
 
 

@@ -84,6 +84,47 @@ size_t record_scalars(int32_t kind) {
 }
 size_t scalar_bytes(int32_t prec) { return prec == FIF_FP64 ? 8 : 4; }
 
+bool gp_model_ok(const fif_gp* gp, bool need_kinv) {
+  if (!gp) return false;
+  if (gp->n_s < 1 || gp->n_s > FIF_GP_MAX_NS || gp->reserved != 0) return false;
+  if (!(gp->k_s > 0.0) || !isfinite(gp->k_s)) return false;
+  if (!(gp->noise >= 0.0) || !isfinite(gp->noise)) return false;
+  if (!gp->axes || !aligned(gp->axes, 8)) return false;
+  if (need_kinv) {
+    if (!(gp->length > 0.0) || !isfinite(gp->length)) return false;
+    if (!gp->kinv || !aligned(gp->kinv, 8)) return false;
+  }
+  return true;
+}
+
+int64_t gp_stride(int32_t n_s, int32_t kind) {
+  return kind == FIF_KIND_INFO ? (int64_t)n_s * 16 : (int64_t)((n_s + 3) / 4) * 4;
+}
+
+fif::GPDev gp_dev(const fif_gp* gp, double half_fov) {
+  fif::GPDev d;
+  d.ns = gp->n_s;
+  d.ks = gp->k_s;
+  d.cos_a = cos(half_fov);
+  d.inv_2l2 = (gp->length > 0.0) ? 1.0 / (2.0 * gp->length * gp->length) : 0.0;
+  d.noise = gp->noise;
+  d.axes = gp->axes;
+  d.kinv = gp->kinv;
+  return d;
+}
+
+fif_status check_gp_field(const fif_gp_field* f, bool need_kinv) {
+  if (!f) return fail(FIF_EINVAL, "field is NULL%s");
+  if (!grid_ok(&f->grid)) return fail(FIF_EINVAL, "invalid grid%s");
+  if (!prec_ok(f->prec)) return fail(FIF_EINVAL, "invalid precision%s");
+  if (!kind_ok(f->kind)) return fail(FIF_EINVAL, "invalid field kind%s");
+  if (!vis_ok(&f->vis)) return fail(FIF_EINVAL, "invalid visibility parameters%s");
+  if (!gp_model_ok(&f->gp, need_kinv)) return fail(FIF_EINVAL, "invalid GP model%s");
+  if (!f->data) return fail(FIF_EINVAL, "field data is NULL%s");
+  if (!aligned(f->data, 16)) return fail(FIF_EINVAL, "field data must be 16-byte aligned%s");
+  return FIF_OK;
+}
+
 fif_status check_field(const fif_field* f) {
   if (!f) return fail(FIF_EINVAL, "field is NULL%s");
   if (!grid_ok(&f->grid)) return fail(FIF_EINVAL, "invalid grid%s");
@@ -306,6 +347,129 @@ fif_status fif_view_sweep(const fif_field* field, const void* t, int64_t n_pos,
   a.best = best;
   hipError_t e = fif::launch_sweep(a, field->prec, (hipStream_t)stream);
   return device_status(e, "fif_view_sweep");
+}
+
+size_t fif_gp_field_bytes(const fif_grid* grid, int32_t n_s, int32_t prec, int32_t kind) {
+  if (!grid_ok(grid) || !prec_ok(prec) || !kind_ok(kind)) return 0;
+  if (n_s < 1 || n_s > FIF_GP_MAX_NS) return 0;
+  return (size_t)grid->nx * grid->ny * grid->nz * (size_t)gp_stride(n_s, kind) * scalar_bytes(prec);
+}
+
+fif_status fif_gp_setup(const fif_gp* gp, void* stream) {
+  if (!gp_model_ok(gp, true)) return fail(FIF_EINVAL, "invalid GP model%s");
+  hipError_t e = fif::launch_gp_setup(gp_dev(gp, 0.0), gp->kinv, (hipStream_t)stream);
+  return device_status(e, "fif_gp_setup");
+}
+
+fif_status fif_gp_evidence(const fif_gp* gp, double half_fov, const double* train_u,
+                           int32_t n_train, const double* lengths, int32_t n_len, double* lml,
+                           void* stream) {
+  if (!gp_model_ok(gp, false)) return fail(FIF_EINVAL, "invalid GP model%s");
+  if (!(half_fov > 0.0 && half_fov < M_PI)) return fail(FIF_EINVAL, "invalid half_fov%s");
+  if (n_train < 0 || n_len < 0) return fail(FIF_EINVAL, "negative size%s");
+  if (n_len == 0) return FIF_OK;
+  if ((n_train > 0 && !train_u) || !lengths || !lml) return fail(FIF_EINVAL, "NULL buffer%s");
+  if ((train_u && !aligned(train_u, 8)) || !aligned(lengths, 8) || !aligned(lml, 8))
+    return fail(FIF_EINVAL, "misaligned buffer%s");
+  hipError_t e = fif::launch_gp_evidence(gp_dev(gp, half_fov), train_u, n_train, lengths, n_len,
+                                         lml, (hipStream_t)stream);
+  return device_status(e, "fif_gp_evidence");
+}
+
+fif_status fif_gp_build(const double* landmarks, int64_t n_landmarks, fif_gp_field* field,
+                        void* workspace, size_t workspace_bytes, void* stream) {
+  fif_status st = check_gp_field(field, false);
+  if (st != FIF_OK) return st;
+  if (n_landmarks < 0) return fail(FIF_EINVAL, "n_landmarks < 0%s");
+  if (n_landmarks > 0 && !landmarks) return fail(FIF_EINVAL, "landmarks is NULL%s");
+  if (landmarks && !aligned(landmarks, 8)) return fail(FIF_EINVAL, "landmarks must be 8-byte aligned%s");
+  if (n_landmarks > ((int64_t)1 << 40)) return fail(FIF_EINVAL, "too many landmarks%s");
+  fif::BuildArgs b;
+  memset(&b, 0, sizeof(b));
+  b.lm = landmarks;
+  b.L = n_landmarks;
+  b.g = grid_dev(&field->grid);
+  range_bounds(&field->vis, &b.lo2, &b.hi2);
+  b.skip2 = INFINITY;
+  if (workspace && n_landmarks > 0) {
+    if (!aligned(workspace, 256)) return fail(FIF_EINVAL, "workspace must be 256-byte aligned%s");
+    const size_t need = fif::sort_workspace_bytes(n_landmarks);
+    if (need == 0) return fail(FIF_EDEVICE, "cannot size the landmark sort%s");
+    if (workspace_bytes < need) return fail(FIF_ENOMEM, "workspace smaller than fif_workspace_bytes()%s");
+    hipError_t e = fif::sort_landmarks(b, workspace, workspace_bytes, (hipStream_t)stream);
+    if (e != hipSuccess) return device_status(e, "fif_gp_build");
+  }
+  fif::GPBuildArgs a;
+  a.lm = landmarks;
+  a.L = n_landmarks;
+  a.lm_sorted = b.lm_sorted;
+  a.batch_box = b.batch_box;
+  a.skip2 = b.skip2;
+  a.g = b.g;
+  a.lo2 = b.lo2;
+  a.hi2 = b.hi2;
+  a.gp = gp_dev(&field->gp, field->vis.half_fov);
+  a.out = field->data;
+  a.stride = gp_stride(field->gp.n_s, field->kind);
+  hipError_t e = fif::launch_gp_build(a, field->prec, field->kind, (hipStream_t)stream);
+  return device_status(e, "fif_gp_build");
+}
+
+fif_status fif_gp_query(const fif_gp_field* field, const void* t, const void* q, int64_t m,
+                        uint32_t metrics, int32_t interp, double* out, uint8_t* flags,
+                        void* stream) {
+  fif_status st = check_gp_field(field, true);
+  if (st != FIF_OK) return st;
+  if (m < 0) return fail(FIF_EINVAL, "m < 0%s");
+  if (m > ((int64_t)1 << 40)) return fail(FIF_EINVAL, "m too large%s");
+  if (metrics == 0 || (metrics & ~15u)) return fail(FIF_EINVAL, "invalid metric mask%s");
+  if (interp != FIF_TRILINEAR && interp != FIF_NEAREST) return fail(FIF_EINVAL, "invalid interp%s");
+  if (field->kind == FIF_KIND_TRACE && metrics != FIF_TRACE)
+    return fail(FIF_EINVAL, "a trace field only answers FIF_TRACE%s");
+  if (m == 0) return FIF_OK;
+  const size_t sb = scalar_bytes(field->prec);
+  if (!t || !q || !out) return fail(FIF_EINVAL, "t, q or out is NULL%s");
+  if (!aligned(t, sb) || !aligned(q, sb)) return fail(FIF_EINVAL, "t/q misaligned for the field precision%s");
+  if (!aligned(out, 8)) return fail(FIF_EINVAL, "out must be 8-byte aligned%s");
+  fif::GPQueryArgs a;
+  memset(&a, 0, sizeof(a));
+  a.q.field = field->data;
+  a.q.g = grid_dev(&field->grid);
+  a.q.vis = vis_dev(&field->vis);
+  a.q.t = t;
+  a.q.q = q;
+  a.q.m = m;
+  a.q.metrics = metrics;
+  a.q.ncols = metric_cols(metrics);
+  a.q.interp = interp;
+  a.q.out = out;
+  a.q.flags = flags;
+  a.gp = gp_dev(&field->gp, field->vis.half_fov);
+  a.stride = gp_stride(field->gp.n_s, field->kind);
+  hipError_t e = fif::launch_gp_query(a, field->prec, field->kind, (hipStream_t)stream);
+  return device_status(e, "fif_gp_query");
+}
+
+fif_status fif_gp_export(const fif_gp_field* field, const int64_t* voxel_ids, int64_t n,
+                         double* blocks, void* stream) {
+  fif_status st = check_gp_field(field, true);
+  if (st != FIF_OK) return st;
+  if (n < 0) return fail(FIF_EINVAL, "n < 0%s");
+  if (n == 0) return FIF_OK;
+  if (!voxel_ids || !blocks) return fail(FIF_EINVAL, "voxel_ids or blocks is NULL%s");
+  if (!aligned(voxel_ids, 8) || !aligned(blocks, 8)) return fail(FIF_EINVAL, "misaligned buffer%s");
+  if (n > ((int64_t)1 << 31) / FIF_GP_MAX_NS) return fail(FIF_EINVAL, "n too large%s");
+  fif::GPExportArgs a;
+  a.field = field->data;
+  a.g = grid_dev(&field->grid);
+  a.inv_s2 = 1.0 / (field->vis.sigma_bearing * field->vis.sigma_bearing);
+  a.gp = gp_dev(&field->gp, field->vis.half_fov);
+  a.stride = gp_stride(field->gp.n_s, field->kind);
+  a.ids = voxel_ids;
+  a.n = n;
+  a.out = blocks;
+  hipError_t e = fif::launch_gp_export(a, field->prec, field->kind, (hipStream_t)stream);
+  return device_status(e, "fif_gp_export");
 }
 
 const char* fif_status_string(fif_status s) {

@@ -1,0 +1,632 @@
+// GP visibility fields (Sec. V-B "GP Regression"; G-I-N_s and G-T-N_s).
+//
+// Model setup: (K^s + noise I)^-1 by an FP64 Cholesky factor held in LDS (one
+// workgroup); the evidence of candidate length scales likewise.
+//
+// Build: for every voxel, S_g = sum_i v^s_g(u_i) X_i over the landmarks in
+// range, X_i the camera-frame terms of I_i about the voxel centre (P/n^2, u/n,
+// P with P = I - u u^T; information fields) or Tr(I_i) (trace fields).  Per
+// voxel this is a (sample axes x landmarks) . (landmarks x terms) product whose
+// operands are formed on the fly, so one wave owns one voxel and feeds the
+// matrix cores: per group of 4 landmarks in range, each 16-axis tile is one
+// 16x16x4 MFMA with the sigmoid visibilities as A and the 15 terms as B.  The
+// landmarks in range of a batch are first compacted into the wave's LDS list.
+//
+// Query: the GP weights w = (K^s + noise I)^-1 K_z of the pose are formed once
+// (FP64), each corner block is contracted with w, moved to the query frame and
+// interpolated; the FP64 world shift and metrics follow per query.
+#include <cmath>
+
+#include "fif_kernels.h"
+#include "fif_metrics.h"
+#include "fif_slot.h"
+
+namespace fif {
+
+namespace {
+
+constexpr int kGPThreads = 256;
+constexpr int kGPWaves = kGPThreads / 64;
+constexpr int kGPBatch = 256;
+constexpr int kGPTiles = 5;  // 16-axis tiles per pass (80 axes)
+constexpr int kMaxNs = 160;  // FIF_GP_MAX_NS
+constexpr int kPackedL = kMaxNs * (kMaxNs + 1) / 2;
+
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+
+template <typename T>
+struct Vec4;
+template <>
+struct Vec4<float> { using acc = f32x4; using lm = float4; };
+template <>
+struct Vec4<double> { using acc = f64x4; using lm = double4; };
+
+// D += A B for A 16x4 (lane l: A[l%16][l/16]), B 4x16 (lane l: B[l/16][l%16]),
+// D 16x16 (lane l, element r: D[4(l/16) + r][l%16]).  FP32: the matrix core.
+__device__ inline f32x4 mma16(float a, float b, f32x4 c, double*) {
+  return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+// FP64: the same product through LDS (the FP64 path is the precision
+// reference), with the same operand and result layout.
+__device__ inline f64x4 mma16(double a, double b, f64x4 c, double* s) {
+  const int l = threadIdx.x & 63;
+  s[l] = a;
+  s[64 + l] = b;
+  wave_sync();
+  const int j = l & 15, i0 = 4 * (l >> 4);
+  double bk[4];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) bk[k] = s[64 + 16 * k + j];
+#pragma unroll
+  for (int r = 0; r < 4; ++r)
+#pragma unroll
+    for (int k = 0; k < 4; ++k) c[r] = fma(s[i0 + r + 16 * k], bk[k], c[r]);
+  wave_sync();
+  return c;
+}
+
+// Sigmoid visibility (eq:sigmoid_vis_func).
+__device__ inline float sigmoid_vis(float c, float ks, float cos_a) {
+  const float x = ks * (c - cos_a);
+  return __builtin_amdgcn_rcpf(1.0f + __builtin_amdgcn_exp2f(-1.4426950408889634f * x));
+}
+__device__ inline double sigmoid_vis(double c, double ks, double cos_a) {
+  return 1.0 / (1.0 + exp(-ks * (c - cos_a)));
+}
+
+__device__ inline void two_sum_acc(float& hi, float& lo, float x) {
+  float s = hi + x;
+  float bb = s - hi;
+  float err = (hi - (s - bb)) + (x - bb);
+  hi = s;
+  lo += err;
+}
+
+// Packed lower-triangular index of (i, j), j <= i.
+__device__ inline int tri(int i, int j) { return i * (i + 1) / 2 + j; }
+
+__device__ inline double se_kernel(const double* za, const double* zb, double inv_2l2) {
+  const double d0 = za[0] - zb[0], d1 = za[1] - zb[1], d2 = za[2] - zb[2];
+  return exp(-(d0 * d0 + d1 * d1 + d2 * d2) * inv_2l2);
+}
+
+// Cholesky factor of K^s + noise I (packed, in LDS) by the workgroup.  The
+// axes are in s_z[ns][3].  Returns false (uniformly) if not positive definite.
+__device__ bool cholesky_lds(int ns, const double* s_z, double inv_2l2, double noise,
+                             double* L, double* s_diag) {
+  const int tid = threadIdx.x;
+  bool ok = true;
+  for (int j = 0; j < ns; ++j) {
+    if (tid == 0) {
+      double d = se_kernel(s_z + 3 * j, s_z + 3 * j, inv_2l2) + noise;
+      for (int k = 0; k < j; ++k) d -= L[tri(j, k)] * L[tri(j, k)];
+      *s_diag = (d > 0.0) ? sqrt(d) : __builtin_nan("");
+      L[tri(j, j)] = *s_diag;
+    }
+    __syncthreads();
+    const double ljj = *s_diag;
+    ok = ok && (ljj > 0.0);
+    for (int i = j + 1 + tid; i < ns; i += blockDim.x) {
+      double v = se_kernel(s_z + 3 * i, s_z + 3 * j, inv_2l2);
+      for (int k = 0; k < j; ++k) v -= L[tri(i, k)] * L[tri(j, k)];
+      L[tri(i, j)] = v / ljj;
+    }
+    __syncthreads();
+  }
+  return ok;
+}
+
+__global__ __launch_bounds__(256) void gp_setup_kernel(GPDev gp, double* kinv) {
+  __shared__ double s_L[kPackedL];
+  __shared__ double s_z[3 * kMaxNs];
+  __shared__ double s_diag;
+  const int ns = gp.ns, tid = threadIdx.x;
+  for (int i = tid; i < 3 * ns; i += blockDim.x) s_z[i] = gp.axes[i];
+  __syncthreads();
+  const bool ok = cholesky_lds(ns, s_z, gp.inv_2l2, gp.noise, s_L, &s_diag);
+  // column c of the inverse: L y = e_c, then L^T x = y (x overwrites y in
+  // column c of kinv, which only this thread touches)
+  for (int c = tid; c < ns; c += blockDim.x) {
+    for (int i = 0; i < ns; ++i) {
+      double s = (i == c) ? 1.0 : 0.0;
+      for (int k = c; k < i; ++k) s -= s_L[tri(i, k)] * kinv[(size_t)k * ns + c];
+      kinv[(size_t)i * ns + c] = (i < c) ? 0.0 : s / s_L[tri(i, i)];
+    }
+    for (int i = ns - 1; i >= 0; --i) {
+      double s = kinv[(size_t)i * ns + c];
+      for (int k = i + 1; k < ns; ++k) s -= s_L[tri(k, i)] * kinv[(size_t)k * ns + c];
+      kinv[(size_t)i * ns + c] = ok ? s / s_L[tri(i, i)] : __builtin_nan("");
+    }
+  }
+}
+
+// One workgroup per candidate length.  The quadratic terms solve L w = y_t in
+// LDS columns: as many solver threads as the remaining LDS holds.
+constexpr int kEvidenceW = 5120;  // doubles of solver scratch
+
+__global__ __launch_bounds__(256) void gp_evidence_kernel(GPDev gp, const double* train_u,
+                                                          int n_train, const double* lengths,
+                                                          double* lml) {
+  __shared__ double s_L[kPackedL];
+  __shared__ double s_z[3 * kMaxNs];
+  __shared__ double s_w[kEvidenceW];
+  __shared__ double s_red[256];
+  __shared__ double s_diag;
+  const int ns = gp.ns, tid = threadIdx.x;
+  const double l = lengths[blockIdx.x];
+  const double inv_2l2 = 1.0 / (2.0 * l * l);
+  for (int i = tid; i < 3 * ns; i += blockDim.x) s_z[i] = gp.axes[i];
+  __syncthreads();
+  const bool ok = (l > 0.0) && cholesky_lds(ns, s_z, inv_2l2, gp.noise, s_L, &s_diag);
+  const int nsolve = min((int)blockDim.x, kEvidenceW / ns);
+  double quad = 0.0;
+  if (ok && tid < nsolve) {
+    double* w = s_w + tid;  // column tid, stride nsolve
+    for (int t = tid; t < n_train; t += nsolve) {
+      const double* u = train_u + 3 * t;
+      double q = 0.0;
+      for (int i = 0; i < ns; ++i) {
+        const double* zi = s_z + 3 * i;
+        double s = sigmoid_vis(zi[0] * u[0] + zi[1] * u[1] + zi[2] * u[2], gp.ks, gp.cos_a);
+        for (int k = 0; k < i; ++k) s -= s_L[tri(i, k)] * w[k * nsolve];
+        s /= s_L[tri(i, i)];
+        w[i * nsolve] = s;
+        q = fma(s, s, q);
+      }
+      quad += q;
+    }
+  }
+  s_red[tid] = quad;
+  __syncthreads();
+  for (int st = 128; st > 0; st >>= 1) {
+    if (tid < st) s_red[tid] += s_red[tid + st];
+    __syncthreads();
+  }
+  if (tid == 0) {
+    double logdet = 0.0;
+    for (int i = 0; i < ns; ++i) logdet += 2.0 * log(s_L[tri(i, i)]);
+    lml[blockIdx.x] = ok ? -0.5 * s_red[0] - 0.5 * n_train * logdet -
+                               0.5 * (double)n_train * ns * log(2.0 * M_PI)
+                         : -__builtin_inf();
+  }
+}
+
+// ---------------------------------------------------------------- build
+
+// Per-lane term of the B operand: f = lane % 16 selects
+//   0..5  (delta_ab - u_a u_b) / n^2   (i2 order 00 01 02 11 12 22)
+//   6..8  u_a / n
+//   9..14 delta_ab - u_a u_b
+//   15    0
+struct TermSel {
+  int ia, ib, kind;  // kind: 0 P/n^2, 1 u/n, 2 P, 3 zero
+  float delta;
+};
+
+__device__ inline TermSel term_sel(int f) {
+  TermSel t;
+  const int pa[6] = {0, 0, 0, 1, 1, 2}, pb[6] = {0, 1, 2, 1, 2, 2};
+  if (f < 6) {
+    t.ia = pa[f]; t.ib = pb[f]; t.kind = 0;
+  } else if (f < 9) {
+    t.ia = f - 6; t.ib = 0; t.kind = 1;
+  } else if (f < 15) {
+    t.ia = pa[f - 9]; t.ib = pb[f - 9]; t.kind = 2;
+  } else {
+    t.ia = 0; t.ib = 0; t.kind = 3;
+  }
+  t.delta = (t.ia == t.ib) ? 1.f : 0.f;
+  return t;
+}
+
+template <typename T>
+__device__ inline T pick3(const T u[3], int i) {
+  return i == 0 ? u[0] : (i == 1 ? u[1] : u[2]);
+}
+
+template <int PREC, int KIND>
+__global__ __launch_bounds__(kGPThreads) void gp_build_kernel(GPBuildArgs a) {
+  using T = typename std::conditional<PREC == 2, double, float>::type;
+  using A4 = typename Vec4<T>::acc;
+  using R4 = typename Vec4<T>::lm;
+  constexpr bool COMP = (PREC == 1);
+  __shared__ R4 s_rec[kGPWaves][kGPBatch];
+  __shared__ double s_mm[kGPWaves][PREC == 2 ? 128 : 1];
+
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int ns = a.gp.ns;
+  const int g0 = blockIdx.y * 16 * kGPTiles;
+  const int ntile = min(kGPTiles, (ns - g0 + 15) / 16);
+  const T ks = (T)a.gp.ks, cos_a = (T)a.gp.cos_a;
+  // A operand axes of this lane, per tile
+  T zx[kGPTiles], zy[kGPTiles], zz[kGPTiles];
+  bool zok[kGPTiles];
+#pragma unroll
+  for (int t = 0; t < kGPTiles; ++t) {
+    const int g = g0 + 16 * t + (lane & 15);
+    zok[t] = g < ns;
+    zx[t] = zok[t] ? (T)a.gp.axes[3 * g] : T(0);
+    zy[t] = zok[t] ? (T)a.gp.axes[3 * g + 1] : T(0);
+    zz[t] = zok[t] ? (T)a.gp.axes[3 * g + 2] : T(0);
+  }
+  const TermSel sel = term_sel(lane & 15);
+  const size_t nvox = (size_t)a.g.nx * a.g.ny * a.g.nz;
+  const int64_t gw = (int64_t)blockIdx.x * kGPWaves + wv;
+  const int64_t nw = (int64_t)gridDim.x * kGPWaves;
+
+  for (int64_t v = gw; v < (int64_t)nvox; v += nw) {
+    const int64_t ix = v % a.g.nx, iy = (v / a.g.nx) % a.g.ny, iz = v / ((int64_t)a.g.nx * a.g.ny);
+    const double tx = a.g.ox + (double)ix * a.g.h, ty = a.g.oy + (double)iy * a.g.h,
+                 tz = a.g.oz + (double)iz * a.g.h;
+    const float fx = (float)tx, fy = (float)ty, fz = (float)tz;
+    const T vx = (T)tx, vy = (T)ty, vz = (T)tz;
+    A4 acc[kGPTiles];
+    float hi[COMP ? kGPTiles : 1][4], lo[COMP ? kGPTiles : 1][4];
+#pragma unroll
+    for (int t = 0; t < kGPTiles; ++t) {
+      acc[t] = A4{0, 0, 0, 0};
+      if (COMP) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) { hi[t][r] = 0.f; lo[t][r] = 0.f; }
+      }
+    }
+    for (int64_t base = 0; base < a.L; base += kGPBatch) {
+      const int nb = (int)((a.L - base) < kGPBatch ? (a.L - base) : kGPBatch);
+      if (a.lm_sorted) {
+        // skip a batch whose box is out of range of this voxel (wave-uniform)
+        const float* bb = a.batch_box + 8 * (base / kGPBatch);
+        const float pv[3] = {fx, fy, fz};
+        float d2 = 0.f;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          const float gap = fmaxf(fmaxf(bb[c] - pv[c], pv[c] - bb[3 + c]), 0.f);
+          d2 = fmaf(gap, gap, d2);
+        }
+        if (d2 > a.skip2) continue;
+      }
+      // compact the landmarks in range into this wave's list
+      int cnt = 0;
+#pragma unroll
+      for (int s = 0; s < kGPBatch / 64; ++s) {
+        const int k = s * 64 + lane;
+        bool in = false;
+        R4 rec;
+        if (k < nb) {
+          double px, py, pz;
+          if (a.lm_sorted) {
+            const double4 p4 = a.lm_sorted[base + k];
+            px = p4.x; py = p4.y; pz = p4.z;
+          } else {
+            const double* p = a.lm + 3 * (base + k);
+            px = p[0]; py = p[1]; pz = p[2];
+          }
+          // V_t range test in FP32 (same decision in every precision)
+          const float ddx = (float)px - fx, ddy = (float)py - fy, ddz = (float)pz - fz;
+          const float n2 = __fmaf_rn(ddz, ddz, __fmaf_rn(ddy, ddy, ddx * ddx));
+          in = (n2 >= a.lo2) && (n2 <= a.hi2);
+          if (in) {
+            const T dx = (T)px - vx, dy = (T)py - vy, dz = (T)pz - vz;
+            const T nn = (PREC == 2) ? (T)fma((double)dz, (double)dz,
+                                              fma((double)dy, (double)dy, (double)dx * dx))
+                                     : (T)n2;
+            const T rn = (PREC == 2) ? (T)(1.0 / sqrt((double)nn)) : (T)rsqrtf((float)nn);
+            rec.x = dx * rn; rec.y = dy * rn; rec.z = dz * rn;
+            if constexpr (KIND == 0) {
+              rec.w = rn;
+            } else {
+              // Tr(I_i) sigma^2 = (2 + |p|^2 + (u.p)^2) / n^2 for the global perturbation
+              const T pxx = (T)px, pyy = (T)py, pzz = (T)pz;
+              const T up = rec.x * pxx + rec.y * pyy + rec.z * pzz;
+              rec.w = (T(2) + (pxx * pxx + pyy * pyy + pzz * pzz) + up * up) * (rn * rn);
+            }
+          }
+        }
+        const uint64_t m = __ballot(in);
+        if (in) s_rec[wv][cnt + __popcll(m & ((1ull << lane) - 1))] = rec;
+        cnt += __popcll(m);
+      }
+      wave_sync();
+      for (int e0 = 0; e0 < cnt; e0 += 4) {
+        const int e = e0 + (lane >> 4);
+        const bool ok = e < cnt;
+        const R4 r = s_rec[wv][ok ? e : e0];
+        const T u[3] = {r.x, r.y, r.z};
+        T bval;
+        if constexpr (KIND == 0) {
+          const T ua = pick3(u, sel.ia), ub = pick3(u, sel.ib);
+          const T pab = (T)sel.delta - ua * ub;
+          bval = sel.kind == 0 ? pab * (r.w * r.w)
+                               : (sel.kind == 1 ? ua * r.w : (sel.kind == 2 ? pab : T(0)));
+        } else {
+          bval = (lane & 15) == 0 ? r.w : T(0);
+        }
+#pragma unroll
+        for (int t = 0; t < kGPTiles; ++t) {
+          if (t < ntile) {
+            const T c = zx[t] * u[0] + zy[t] * u[1] + zz[t] * u[2];
+            const T vis = (ok && zok[t]) ? sigmoid_vis(c, ks, cos_a) : T(0);
+            acc[t] = mma16(vis, bval, acc[t], s_mm[wv]);
+          }
+        }
+      }
+      wave_sync();  // the list is rewritten by the next batch
+      if (COMP) {
+#pragma unroll
+        for (int t = 0; t < kGPTiles; ++t)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            two_sum_acc(hi[t][r], lo[t][r], (float)acc[t][r]);
+            acc[t][r] = 0;
+          }
+      }
+    }
+    // lane l, element r of tile t: axis g0 + 16 t + 4 (l / 16) + r, term l % 16
+    T* out = reinterpret_cast<T*>(a.out) + (size_t)v * a.stride;
+    const int f = lane & 15;
+#pragma unroll
+    for (int t = 0; t < kGPTiles; ++t)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int g = g0 + 16 * t + 4 * (lane >> 4) + r;
+        const T val = COMP ? (T)(hi[t][r] + lo[t][r]) : (T)acc[t][r];
+        if (t < ntile && g < ns) {
+          if constexpr (KIND == 0) out[(size_t)g * 16 + f] = val;
+          else if (f == 0) out[g] = val;
+        }
+      }
+  }
+}
+
+// ---------------------------------------------------------------- query
+
+// Camera-frame block of one voxel from its 15 GP-weighted terms, moved by dl.
+template <typename CT>
+__device__ inline void gp_block(const CT s[15], const CT dl[3], CT out[21]) {
+  CT A[6], D[6], B[9];
+#pragma unroll
+  for (int e = 0; e < 6; ++e) { A[e] = s[e]; D[e] = s[9 + e]; }
+  // B = -[b]x with b = s[6..8]
+  B[0] = 0;     B[1] = s[8];  B[2] = -s[7];
+  B[3] = -s[8]; B[4] = 0;     B[5] = s[6];
+  B[6] = s[7];  B[7] = -s[6]; B[8] = 0;
+  shift_frame<CT>(A, B, D, dl, out);
+}
+
+template <typename FT, int KIND>
+__global__ __launch_bounds__(kGPThreads) void gp_query_kernel(GPQueryArgs ga) {
+  using CT = FT;
+  const QueryArgs& a = ga.q;
+  __shared__ QSlot<CT> s_q[kGPWaves][64];
+  __shared__ double s_kz[kGPWaves][kMaxNs];
+  __shared__ CT s_w[kGPWaves][kMaxNs];
+  __shared__ CT s_c[kGPWaves][8][22];
+  __shared__ CT s_F[kGPWaves][64][22];
+
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int grp = lane >> 3, c8 = lane & 7;
+  const int ns = ga.gp.ns;
+  const FT* field = reinterpret_cast<const FT*>(a.field);
+  const int64_t nbatch = (a.m + 63) / 64;
+  const int64_t gw = (int64_t)blockIdx.x * kGPWaves + wv;
+  const int64_t nw = (int64_t)gridDim.x * kGPWaves;
+
+  for (int64_t b = gw; b < nbatch; b += nw) {
+    const int64_t qown = b * 64 + lane;
+    const bool valid = qown < a.m;
+    const int64_t ql = valid ? qown : a.m - 1;
+    s_q[wv][lane] = make_slot<FT>(a, ql);
+    wave_sync();
+    for (int k = 0; k < 64; ++k) {
+      const QSlot<CT> sl = s_q[wv][k];
+      // GP weights of this pose: w = (K^s + noise I)^-1 K_z, FP64
+      const double z[3] = {(double)sl.z[0], (double)sl.z[1], (double)sl.z[2]};
+      for (int g = lane; g < ns; g += 64) s_kz[wv][g] = se_kernel(z, ga.gp.axes + 3 * g, ga.gp.inv_2l2);
+      wave_sync();
+      for (int g = lane; g < ns; g += 64) {
+        double w = 0.0;
+        for (int h = 0; h < ns; ++h) w = fma(ga.gp.kinv[(size_t)h * ns + g], s_kz[wv][h], w);
+        s_w[wv][g] = (CT)w;
+      }
+      wave_sync();
+      const CornerC<CT> c = slot_corner(sl, a.g, grp);
+      if constexpr (KIND == 0) {
+        CT acc[15];
+#pragma unroll
+        for (int e = 0; e < 15; ++e) acc[e] = 0;
+        if (c.active) {
+          const FT* rec = field + c.vox * (size_t)ga.stride;
+          for (int g = c8; g < ns; g += 8) {
+            const CT wg = s_w[wv][g];
+            const FT* row = rec + (size_t)g * 16;
+            FT x[16];
+#pragma unroll
+            for (int e = 0; e < 16; e += 4) {
+              if constexpr (sizeof(FT) == 4) {
+                const float4 v4 = *reinterpret_cast<const float4*>(row + e);
+                x[e] = v4.x; x[e + 1] = v4.y; x[e + 2] = v4.z; x[e + 3] = v4.w;
+              } else {
+                const double2 v0 = *reinterpret_cast<const double2*>(row + e);
+                const double2 v1 = *reinterpret_cast<const double2*>(row + e + 2);
+                x[e] = v0.x; x[e + 1] = v0.y; x[e + 2] = v1.x; x[e + 3] = v1.y;
+              }
+            }
+#pragma unroll
+            for (int e = 0; e < 15; ++e) acc[e] = fma(wg, (CT)x[e], acc[e]);
+          }
+        }
+        sum8_arr<15>(acc);
+        if (c8 == 0) {
+          CT Y[21];
+          if (c.active) {
+            gp_block<CT>(acc, c.dl, Y);
+#pragma unroll
+            for (int e = 0; e < 21; ++e) Y[e] *= c.w;
+          } else {
+#pragma unroll
+            for (int e = 0; e < 21; ++e) Y[e] = 0;
+          }
+#pragma unroll
+          for (int e = 0; e < 21; ++e) s_c[wv][grp][e] = Y[e];
+        }
+      } else {
+        CT acc = 0;
+        if (c.active) {
+          const FT* rec = field + c.vox * (size_t)ga.stride;
+          for (int g = c8; g < ns; g += 8) acc = fma(s_w[wv][g], (CT)rec[g], acc);
+        }
+        acc = sum8(acc);
+        if (c8 == 0) s_c[wv][grp][0] = c.active ? acc * c.w : CT(0);
+      }
+      wave_sync();
+      if (lane < (KIND == 0 ? 21 : 1)) {
+        CT s = 0;
+#pragma unroll
+        for (int j = 0; j < 8; ++j) s += s_c[wv][j][lane];
+        s_F[wv][k][lane] = s;
+      }
+      wave_sync();
+    }
+    // metrics of this lane's own pose
+    const QSlot<CT> own = s_q[wv][lane];
+    uint8_t flag = (own.bits & 8) ? FL_CLAMPED : 0;
+    if constexpr (KIND == 0) {
+      double td[3] = {(double)own.t[0], (double)own.t[1], (double)own.t[2]};
+      double Zd[21], F[21];
+#pragma unroll
+      for (int e = 0; e < 21; ++e) Zd[e] = (double)s_F[wv][lane][e];
+      shift21<double>(Zd, td, F);
+#pragma unroll
+      for (int e = 0; e < 21; ++e) F[e] *= a.vis.inv_s2;
+      double* row = (valid && a.out) ? a.out + ql * a.ncols : nullptr;
+      eval_metrics<false>(F, a.metrics, row, &flag, nullptr, nullptr, a.flags != nullptr);
+    } else {
+      if (valid && a.out) a.out[ql * a.ncols] = (double)s_F[wv][lane][0] * a.vis.inv_s2;
+    }
+    if (valid && a.flags) a.flags[ql] = flag;
+    wave_sync();  // s_q and s_F are rewritten by the next batch
+  }
+}
+
+// ---------------------------------------------------------------- export
+
+// One thread per (voxel, axis g): C_g = sum_h kinv[g][h] world(S_h) / sigma^2.
+template <typename FT, int KIND>
+__global__ void gp_export_kernel(GPExportArgs a) {
+  const int ns = a.gp.ns;
+  const int64_t it = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (it >= a.n * ns) return;
+  const int64_t i = it / ns;
+  const int g = (int)(it % ns);
+  const int64_t v = a.ids[i];
+  const int64_t nvox = (int64_t)a.g.nx * a.g.ny * a.g.nz;
+  const int per = KIND == 0 ? 21 : 1;
+  double* out = a.out + (i * ns + g) * per;
+  if (v < 0 || v >= nvox) {
+    for (int e = 0; e < per; ++e) out[e] = __builtin_nan("");
+    return;
+  }
+  const FT* rec = reinterpret_cast<const FT*>(a.field) + (size_t)v * a.stride;
+  if constexpr (KIND == 0) {
+    const int64_t ix = v % a.g.nx, iy = (v / a.g.nx) % a.g.ny, iz = v / ((int64_t)a.g.nx * a.g.ny);
+    const double tv[3] = {a.g.ox + (double)ix * a.g.h, a.g.oy + (double)iy * a.g.h,
+                          a.g.oz + (double)iz * a.g.h};
+    double C[21];
+#pragma unroll
+    for (int e = 0; e < 21; ++e) C[e] = 0.0;
+    for (int h = 0; h < ns; ++h) {
+      double s[15], W[21];
+#pragma unroll
+      for (int e = 0; e < 15; ++e) s[e] = (double)rec[(size_t)h * 16 + e];
+      gp_block<double>(s, tv, W);
+      const double k = a.gp.kinv[(size_t)g * ns + h];
+#pragma unroll
+      for (int e = 0; e < 21; ++e) C[e] = fma(k, W[e], C[e]);
+    }
+#pragma unroll
+    for (int e = 0; e < 21; ++e) out[e] = C[e] * a.inv_s2;
+  } else {
+    double c = 0.0;
+    for (int h = 0; h < ns; ++h) c = fma(a.gp.kinv[(size_t)g * ns + h], (double)rec[h], c);
+    out[0] = c * a.inv_s2;
+  }
+}
+
+int64_t resident_blocks(int per_cu) {
+  int dev = 0, cus = 256;
+  if (hipGetDevice(&dev) == hipSuccess) {
+    int v = 0;
+    if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && v > 0)
+      cus = v;
+  }
+  return (int64_t)cus * per_cu;
+}
+
+}  // namespace
+
+hipError_t launch_gp_setup(const GPDev& gp, double* kinv, hipStream_t stream) {
+  hipLaunchKernelGGL(gp_setup_kernel, dim3(1), dim3(256), 0, stream, gp, kinv);
+  return hipGetLastError();
+}
+
+hipError_t launch_gp_evidence(const GPDev& gp, const double* train_u, int32_t n_train,
+                              const double* lengths, int32_t n_len, double* lml,
+                              hipStream_t stream) {
+  if (n_len <= 0) return hipSuccess;
+  hipLaunchKernelGGL(gp_evidence_kernel, dim3((unsigned)n_len), dim3(256), 0, stream, gp, train_u,
+                     n_train, lengths, lml);
+  return hipGetLastError();
+}
+
+hipError_t launch_gp_build(const GPBuildArgs& a, int prec, int kind, hipStream_t stream) {
+  const int64_t nvox = (int64_t)a.g.nx * a.g.ny * a.g.nz;
+  const int passes = (a.gp.ns + 16 * kGPTiles - 1) / (16 * kGPTiles);
+  const int64_t want = (nvox + kGPWaves - 1) / kGPWaves;
+  const int64_t cap = resident_blocks(8);
+  dim3 grid((unsigned)(want < cap ? want : cap), (unsigned)passes);
+  dim3 block(kGPThreads);
+#define FIF_GP_LAUNCH(P, K) hipLaunchKernelGGL((gp_build_kernel<P, K>), grid, block, 0, stream, a)
+  if (kind == 0) {
+    if (prec == 0) FIF_GP_LAUNCH(0, 0);
+    else if (prec == 1) FIF_GP_LAUNCH(1, 0);
+    else FIF_GP_LAUNCH(2, 0);
+  } else {
+    if (prec == 0) FIF_GP_LAUNCH(0, 1);
+    else if (prec == 1) FIF_GP_LAUNCH(1, 1);
+    else FIF_GP_LAUNCH(2, 1);
+  }
+#undef FIF_GP_LAUNCH
+  return hipGetLastError();
+}
+
+hipError_t launch_gp_query(const GPQueryArgs& a, int prec, int kind, hipStream_t stream) {
+  if (a.q.m <= 0) return hipSuccess;
+  const int64_t nbatch = (a.q.m + 63) / 64;
+  const int64_t want = (nbatch + kGPWaves - 1) / kGPWaves;
+  const int64_t cap = resident_blocks(8);
+  dim3 grid((unsigned)(want < cap ? want : cap)), block(kGPThreads);
+  if (prec == 2) {
+    if (kind == 0) hipLaunchKernelGGL((gp_query_kernel<double, 0>), grid, block, 0, stream, a);
+    else hipLaunchKernelGGL((gp_query_kernel<double, 1>), grid, block, 0, stream, a);
+  } else {
+    if (kind == 0) hipLaunchKernelGGL((gp_query_kernel<float, 0>), grid, block, 0, stream, a);
+    else hipLaunchKernelGGL((gp_query_kernel<float, 1>), grid, block, 0, stream, a);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_gp_export(const GPExportArgs& a, int prec, int kind, hipStream_t stream) {
+  const int64_t total = a.n * a.gp.ns;
+  if (total <= 0) return hipSuccess;
+  dim3 grid((unsigned)((total + 127) / 128)), block(128);
+  if (prec == 2) {
+    if (kind == 0) hipLaunchKernelGGL((gp_export_kernel<double, 0>), grid, block, 0, stream, a);
+    else hipLaunchKernelGGL((gp_export_kernel<double, 1>), grid, block, 0, stream, a);
+  } else {
+    if (kind == 0) hipLaunchKernelGGL((gp_export_kernel<float, 0>), grid, block, 0, stream, a);
+    else hipLaunchKernelGGL((gp_export_kernel<float, 1>), grid, block, 0, stream, a);
+  }
+  return hipGetLastError();
+}
+
+}  // namespace fif

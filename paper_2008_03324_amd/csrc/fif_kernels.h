@@ -86,7 +86,55 @@ struct SweepArgs {
   int64_t* best;
 };
 
+// GP visibility model on the device (Sec. V-B).
+struct GPDev {
+  int32_t ns;
+  double ks;          // sigmoid slope
+  double cos_a;       // cos(alpha)
+  double inv_2l2;     // 1 / (2 l^2)
+  double noise;
+  const double* axes;  // [ns][3]
+  const double* kinv;  // [ns][ns]
+};
+
+struct GPBuildArgs {
+  const double* lm;
+  int64_t L;
+  const double4* lm_sorted;  // null for the unsorted path
+  const float* batch_box;
+  float skip2;
+  GridDev g;
+  float lo2, hi2;
+  GPDev gp;
+  void* out;
+  int64_t stride;  // scalars per voxel
+};
+
+struct GPQueryArgs {
+  QueryArgs q;  // field, grid, vis (inv_s2), poses, metrics, outputs
+  GPDev gp;
+  int64_t stride;
+};
+
+struct GPExportArgs {
+  const void* field;
+  GridDev g;
+  double inv_s2;
+  GPDev gp;
+  int64_t stride;
+  const int64_t* ids;
+  int64_t n;
+  double* out;
+};
+
 hipError_t launch_build(const BuildArgs& a, int prec, int kind, hipStream_t stream);
+hipError_t launch_gp_setup(const GPDev& gp, double* kinv, hipStream_t stream);
+hipError_t launch_gp_evidence(const GPDev& gp, const double* train_u, int32_t n_train,
+                              const double* lengths, int32_t n_len, double* lml,
+                              hipStream_t stream);
+hipError_t launch_gp_build(const GPBuildArgs& a, int prec, int kind, hipStream_t stream);
+hipError_t launch_gp_query(const GPQueryArgs& a, int prec, int kind, hipStream_t stream);
+hipError_t launch_gp_export(const GPExportArgs& a, int prec, int kind, hipStream_t stream);
 hipError_t launch_sweep(const SweepArgs& a, int prec, hipStream_t stream);
 // Workspace of the sorted build: bytes needed, and the sort itself (fills
 // a.lm_sorted / a.batch_box inside `ws`).

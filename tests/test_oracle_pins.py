@@ -651,3 +651,12 @@ def test_gp_trace_factor_is_trace_of_information_factor(gp30):
     a, _ = oracle.gp_query(fi, t, q, 1, interp=1)
     b, _ = oracle.gp_query(ft, t, q, 1, interp=1)
     assert np.abs(a - b).max() <= 1e-12 * np.abs(a).max()
+
+
+def test_gp_length_inputs_are_the_ml2_fit():
+    """The length scales the GP workloads use are the oracle's ML-II fit on the
+    stated training bearings (to the 4 digits stored)."""
+    U = scenes.gp_training_directions()
+    for ns, l in scenes.GP_LENGTH.items():
+        fit = oracle.gp_fit_length(scenes.sphere_axes(ns), KS, ALPHA, NOISE, U)
+        assert abs(fit - l) < 1e-4, (ns, fit, l)
