@@ -56,6 +56,7 @@ def parse():
     ap.add_argument("--cpu-sample", type=int, default=2048, help="poses in the oracle sample")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving leg")
     ap.add_argument("--no-sweep", action="store_true", help="skip the optimal-view sweep leg")
+    ap.add_argument("--no-gp", action="store_true", help="skip the GP visibility leg")
     ap.add_argument("--serve-seconds", type=float, default=2.0,
                     help="length of each Poisson stream of the serving leg")
     return ap.parse_args()
@@ -251,6 +252,9 @@ def main():
     if not args.no_sweep:
         res["view_sweep"] = sweep_leg(fif, torch, scenes, g, field, dev)
 
+    if not args.no_gp:
+        res["gp"] = gp_leg(fif, torch, scenes, lm_d, grid, vis, t_d, q_d, contrib, dev)
+
     if not args.no_serve:
         res["serving"] = serve_leg(args, fif, torch)
         res["p99_ms_at_60pct_load"] = res["serving"]["rates"][1]["batched"]["p99_ms"]
@@ -259,6 +263,60 @@ def main():
     if not args.no_cpu:
         res.update(cpu_leg(args, fif, torch, lm, g, v, t, q, out, pc_out, metrics))
     print(json.dumps(res), flush=True)
+
+
+def gp_leg(fif, torch, scenes, lm_d, grid, vis, t_d, q_d, contrib, dev, ns=70, m=1_000_000,
+           reps=3):
+    """GP visibility fields (Sec. V-B; G-I-70 and G-T-70 of Sec. VII-A) on the
+    resident building scene: the ML-II length on the device, the FP32-
+    compensated information and trace builds, and 1M-pose queries."""
+    import math
+    axes = torch.from_numpy(scenes.sphere_axes(ns)).to(dev)
+    model = fif.GPModel(axes, 15.0, None, 1e-10)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    length = model.fit_length(vis.half_fov, torch.from_numpy(scenes.gp_training_directions()).to(dev))
+    e1.record()
+    torch.cuda.synchronize()
+    fit_ms = e0.elapsed_time(e1)
+    fi = fif.GPField(grid, vis, model, fif.FP32_COMP, fif.KIND_INFO, device=dev)
+    ft = fif.GPField(grid, vis, model, fif.FP32_COMP, fif.KIND_TRACE, device=dev)
+    tq, qq = t_d[:m], q_d[:m]
+    out = torch.empty((m, 3), dtype=torch.float64, device=dev)
+    out1 = torch.empty((m, 1), dtype=torch.float64, device=dev)
+
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        ms = []
+        for _ in range(reps):
+            a = torch.cuda.Event(enable_timing=True)
+            b = torch.cuda.Event(enable_timing=True)
+            a.record()
+            fn()
+            b.record()
+            torch.cuda.synchronize()
+            ms.append(a.elapsed_time(b))
+        return float(np.median(ms))
+
+    b_info = timed(lambda: fif.gp_build(lm_d, grid, vis, model, field=fi))
+    b_tr = timed(lambda: fif.gp_build(lm_d, grid, vis, model, kind=fif.KIND_TRACE, field=ft))
+    q_info = timed(lambda: fif.gp_query(fi, tq, qq, fif.TRACE | fif.LMIN | fif.LOGDET, out=out))
+    q_tr = timed(lambda: fif.gp_query(ft, tq, qq, fif.TRACE, out=out1))
+    qbytes = 8 * ns * 15 * 4 + POSE_BYTES + OUT_BYTES_3  # 15 terms per axis and corner
+    gbs = m * qbytes / (q_info / 1e3) / 1e9
+    log(f"GP N_s={ns}: length {length:.4f} ({fit_ms:.1f} ms), build info {b_info:.1f} ms, "
+        f"trace {b_tr:.1f} ms; query info {q_info:.3f} ms ({gbs:.0f} GB/s), trace {q_tr:.3f} ms")
+    # matrix-core work of the information build: 2 * 16 terms * N_s per pair
+    mfma_tflops = contrib * 2.0 * 16 * ns / (b_info / 1e3) / 1e12
+    return {"n_s": ns, "length": length, "fit_ms": fit_ms, "field_bytes": fi.nbytes,
+            "build_info_ms": b_info, "build_trace_ms": b_tr,
+            "build_pairs_per_s": contrib / (b_info / 1e3),
+            "build_mfma_tflops": mfma_tflops,
+            "query_poses": m, "query_info_ms": q_info, "query_trace_ms": q_tr,
+            "query_info_per_s": m / (q_info / 1e3), "query_bytes_per_pose": qbytes,
+            "query_info_gbs": gbs, "query_info_hbm_frac": gbs / HBM_PEAK_GBS}
 
 
 def sweep_leg(fif, torch, scenes, g, field, dev, n_pos=200, n_axes=4096, reps=5):

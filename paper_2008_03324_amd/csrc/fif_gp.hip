@@ -75,6 +75,14 @@ __device__ inline double sigmoid_vis(double c, double ks, double cos_a) {
   return 1.0 / (1.0 + exp(-ks * (c - cos_a)));
 }
 
+// The same from a prepared exponent: e = 2^x (FP32) or e^x (FP64) with
+// x = -k_s (z . u - cos alpha) already formed; 1 / (1 + e).  An exponent of
+// +1e4 gives exactly 0 (the padding axes of a tile).
+__device__ inline float sigmoid_from(float x) {
+  return __builtin_amdgcn_rcpf(1.0f + __builtin_amdgcn_exp2f(x));
+}
+__device__ inline double sigmoid_from(double x) { return 1.0 / (1.0 + exp(x)); }
+
 __device__ inline void two_sum_acc(float& hi, float& lo, float x) {
   float s = hi + x;
   float bb = s - hi;
@@ -199,34 +207,36 @@ __global__ __launch_bounds__(256) void gp_evidence_kernel(GPDev gp, const double
 //   6..8  u_a / n
 //   9..14 delta_ab - u_a u_b
 //   15    0
+// as  m_pn2 (delta - u_a u_b) / n^2 + m_un u_a / n + m_p (delta - u_a u_b).
 struct TermSel {
-  int ia, ib, kind;  // kind: 0 P/n^2, 1 u/n, 2 P, 3 zero
-  float delta;
+  int ia, ib;
+  float delta, m_pn2, m_un, m_p;
+  float a[3], b[3];  // one-hot weights selecting u_a and u_b
 };
 
 __device__ inline TermSel term_sel(int f) {
   TermSel t;
   const int pa[6] = {0, 0, 0, 1, 1, 2}, pb[6] = {0, 1, 2, 1, 2, 2};
+  t.m_pn2 = t.m_un = t.m_p = 0.f;
   if (f < 6) {
-    t.ia = pa[f]; t.ib = pb[f]; t.kind = 0;
+    t.ia = pa[f]; t.ib = pb[f]; t.m_pn2 = 1.f;
   } else if (f < 9) {
-    t.ia = f - 6; t.ib = 0; t.kind = 1;
+    t.ia = f - 6; t.ib = 0; t.m_un = 1.f;
   } else if (f < 15) {
-    t.ia = pa[f - 9]; t.ib = pb[f - 9]; t.kind = 2;
+    t.ia = pa[f - 9]; t.ib = pb[f - 9]; t.m_p = 1.f;
   } else {
-    t.ia = 0; t.ib = 0; t.kind = 3;
+    t.ia = 0; t.ib = 0;
   }
-  t.delta = (t.ia == t.ib) ? 1.f : 0.f;
+  t.delta = (t.ia == t.ib && f != 15 && !(f >= 6 && f < 9)) ? 1.f : 0.f;
+  for (int c = 0; c < 3; ++c) {
+    t.a[c] = (c == t.ia) ? 1.f : 0.f;
+    t.b[c] = (c == t.ib) ? 1.f : 0.f;
+  }
   return t;
 }
 
-template <typename T>
-__device__ inline T pick3(const T u[3], int i) {
-  return i == 0 ? u[0] : (i == 1 ? u[1] : u[2]);
-}
-
-template <int PREC, int KIND>
-__global__ __launch_bounds__(kGPThreads) void gp_build_kernel(GPBuildArgs a) {
+template <int PREC, int KIND, int NT>
+__global__ __launch_bounds__(kGPThreads) void gp_build_kernel(GPBuildArgs a, int pass0) {
   using T = typename std::conditional<PREC == 2, double, float>::type;
   using A4 = typename Vec4<T>::acc;
   using R4 = typename Vec4<T>::lm;
@@ -236,19 +246,20 @@ __global__ __launch_bounds__(kGPThreads) void gp_build_kernel(GPBuildArgs a) {
 
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int ns = a.gp.ns;
-  const int g0 = blockIdx.y * 16 * kGPTiles;
-  const int ntile = min(kGPTiles, (ns - g0 + 15) / 16);
-  const T ks = (T)a.gp.ks, cos_a = (T)a.gp.cos_a;
+  const int g0 = (pass0 + (int)blockIdx.y) * 16 * kGPTiles;
   // A operand axes of this lane, per tile
-  T zx[kGPTiles], zy[kGPTiles], zz[kGPTiles];
-  bool zok[kGPTiles];
+  // exponent of the sigmoid as K (z . u) + x0 with K = -k_s (times log2 e in
+  // FP32, where the exponential is base 2), folded into the axis components
+  const double kexp = (PREC == 2) ? -a.gp.ks : -a.gp.ks * 1.4426950408889634;
+  T zx[NT], zy[NT], zz[NT], z0[NT];
 #pragma unroll
-  for (int t = 0; t < kGPTiles; ++t) {
+  for (int t = 0; t < NT; ++t) {
     const int g = g0 + 16 * t + (lane & 15);
-    zok[t] = g < ns;
-    zx[t] = zok[t] ? (T)a.gp.axes[3 * g] : T(0);
-    zy[t] = zok[t] ? (T)a.gp.axes[3 * g + 1] : T(0);
-    zz[t] = zok[t] ? (T)a.gp.axes[3 * g + 2] : T(0);
+    const bool ok = g < ns;
+    zx[t] = ok ? (T)(kexp * a.gp.axes[3 * g]) : T(0);
+    zy[t] = ok ? (T)(kexp * a.gp.axes[3 * g + 1]) : T(0);
+    zz[t] = ok ? (T)(kexp * a.gp.axes[3 * g + 2]) : T(0);
+    z0[t] = ok ? (T)(-kexp * a.gp.cos_a) : T(1e4);
   }
   const TermSel sel = term_sel(lane & 15);
   const size_t nvox = (size_t)a.g.nx * a.g.ny * a.g.nz;
@@ -261,10 +272,10 @@ __global__ __launch_bounds__(kGPThreads) void gp_build_kernel(GPBuildArgs a) {
                  tz = a.g.oz + (double)iz * a.g.h;
     const float fx = (float)tx, fy = (float)ty, fz = (float)tz;
     const T vx = (T)tx, vy = (T)ty, vz = (T)tz;
-    A4 acc[kGPTiles];
-    float hi[COMP ? kGPTiles : 1][4], lo[COMP ? kGPTiles : 1][4];
+    A4 acc[NT];
+    float hi[COMP ? NT : 1][4], lo[COMP ? NT : 1][4];
 #pragma unroll
-    for (int t = 0; t < kGPTiles; ++t) {
+    for (int t = 0; t < NT; ++t) {
       acc[t] = A4{0, 0, 0, 0};
       if (COMP) {
 #pragma unroll
@@ -329,31 +340,29 @@ __global__ __launch_bounds__(kGPThreads) void gp_build_kernel(GPBuildArgs a) {
       wave_sync();
       for (int e0 = 0; e0 < cnt; e0 += 4) {
         const int e = e0 + (lane >> 4);
-        const bool ok = e < cnt;
-        const R4 r = s_rec[wv][ok ? e : e0];
+        const T okm = (e < cnt) ? T(1) : T(0);  // padding landmarks: zero terms
+        const R4 r = s_rec[wv][e < cnt ? e : e0];
         const T u[3] = {r.x, r.y, r.z};
         T bval;
         if constexpr (KIND == 0) {
-          const T ua = pick3(u, sel.ia), ub = pick3(u, sel.ib);
+          const T ua = (T)sel.a[0] * u[0] + (T)sel.a[1] * u[1] + (T)sel.a[2] * u[2];
+          const T ub = (T)sel.b[0] * u[0] + (T)sel.b[1] * u[1] + (T)sel.b[2] * u[2];
           const T pab = (T)sel.delta - ua * ub;
-          bval = sel.kind == 0 ? pab * (r.w * r.w)
-                               : (sel.kind == 1 ? ua * r.w : (sel.kind == 2 ? pab : T(0)));
+          const T rn = r.w;
+          bval = (pab * ((T)sel.m_pn2 * (rn * rn) + (T)sel.m_p) + (T)sel.m_un * (ua * rn)) * okm;
         } else {
-          bval = (lane & 15) == 0 ? r.w : T(0);
+          bval = (lane & 15) == 0 ? r.w * okm : T(0);
         }
 #pragma unroll
-        for (int t = 0; t < kGPTiles; ++t) {
-          if (t < ntile) {
-            const T c = zx[t] * u[0] + zy[t] * u[1] + zz[t] * u[2];
-            const T vis = (ok && zok[t]) ? sigmoid_vis(c, ks, cos_a) : T(0);
-            acc[t] = mma16(vis, bval, acc[t], s_mm[wv]);
-          }
+        for (int t = 0; t < NT; ++t) {
+          const T x = fma(zz[t], u[2], fma(zy[t], u[1], fma(zx[t], u[0], z0[t])));
+          acc[t] = mma16(sigmoid_from(x), bval, acc[t], s_mm[wv]);
         }
       }
       wave_sync();  // the list is rewritten by the next batch
       if (COMP) {
 #pragma unroll
-        for (int t = 0; t < kGPTiles; ++t)
+        for (int t = 0; t < NT; ++t)
 #pragma unroll
           for (int r = 0; r < 4; ++r) {
             two_sum_acc(hi[t][r], lo[t][r], (float)acc[t][r]);
@@ -365,12 +374,12 @@ __global__ __launch_bounds__(kGPThreads) void gp_build_kernel(GPBuildArgs a) {
     T* out = reinterpret_cast<T*>(a.out) + (size_t)v * a.stride;
     const int f = lane & 15;
 #pragma unroll
-    for (int t = 0; t < kGPTiles; ++t)
+    for (int t = 0; t < NT; ++t)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int g = g0 + 16 * t + 4 * (lane >> 4) + r;
         const T val = COMP ? (T)(hi[t][r] + lo[t][r]) : (T)acc[t][r];
-        if (t < ntile && g < ns) {
+        if (g < ns) {
           if constexpr (KIND == 0) out[(size_t)g * 16 + f] = val;
           else if (f == 0) out[g] = val;
         }
@@ -393,6 +402,32 @@ __device__ inline void gp_block(const CT s[15], const CT dl[3], CT out[21]) {
   shift_frame<CT>(A, B, D, dl, out);
 }
 
+constexpr int kChunk = 3;                      // rows loaded together per lane
+constexpr int kKinvLds = 3240;                 // packed inverse held in LDS up to N_s = 80
+constexpr int kMaxRowsPerLane = kMaxNs / 8;    // trace rows per lane
+
+// Rows r0 .. r0 + kChunk - 1 (those below nrow) of axes c8 + 8 r of a voxel.
+template <typename FT>
+__device__ inline void load_rows(const FT* rec, int c8, int r0, int nrow, FT x[kChunk][16]) {
+#pragma unroll
+  for (int rr = 0; rr < kChunk; ++rr) {
+    if (r0 + rr < nrow) {
+      const FT* row = rec + (size_t)(c8 + 8 * (r0 + rr)) * 16;
+#pragma unroll
+      for (int e = 0; e < 16; e += 4) {
+        if constexpr (sizeof(FT) == 4) {
+          const float4 v4 = *reinterpret_cast<const float4*>(row + e);
+          x[rr][e] = v4.x; x[rr][e + 1] = v4.y; x[rr][e + 2] = v4.z; x[rr][e + 3] = v4.w;
+        } else {
+          const double2 v0 = *reinterpret_cast<const double2*>(row + e);
+          const double2 v1 = *reinterpret_cast<const double2*>(row + e + 2);
+          x[rr][e] = v0.x; x[rr][e + 1] = v0.y; x[rr][e + 2] = v1.x; x[rr][e + 3] = v1.y;
+        }
+      }
+    }
+  }
+}
+
 template <typename FT, int KIND>
 __global__ __launch_bounds__(kGPThreads) void gp_query_kernel(GPQueryArgs ga) {
   using CT = FT;
@@ -402,6 +437,9 @@ __global__ __launch_bounds__(kGPThreads) void gp_query_kernel(GPQueryArgs ga) {
   __shared__ CT s_w[kGPWaves][kMaxNs];
   __shared__ CT s_c[kGPWaves][8][22];
   __shared__ CT s_F[kGPWaves][64][22];
+  // packed lower triangle of the inverse, information fields only (the trace
+  // kernel keeps its occupancy instead)
+  __shared__ double s_kinv[KIND == 0 ? kKinvLds : 1];
 
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int grp = lane >> 3, c8 = lane & 7;
@@ -411,6 +449,16 @@ __global__ __launch_bounds__(kGPThreads) void gp_query_kernel(GPQueryArgs ga) {
   const int64_t gw = (int64_t)blockIdx.x * kGPWaves + wv;
   const int64_t nw = (int64_t)gridDim.x * kGPWaves;
 
+  const bool kinv_lds = KIND == 0 && ns * (ns + 1) / 2 <= kKinvLds;
+  if (kinv_lds) {
+    for (int i = threadIdx.x; i < ns * (ns + 1) / 2; i += kGPThreads) {
+      int r = (int)((sqrt(8.0 * i + 1.0) - 1.0) * 0.5);
+      while (r * (r + 1) / 2 > i) --r;
+      while ((r + 1) * (r + 2) / 2 <= i) ++r;
+      s_kinv[i] = ga.gp.kinv[(size_t)r * ns + (i - r * (r + 1) / 2)];
+    }
+  }
+  __syncthreads();  // the only workgroup barrier: before any wave can leave
   for (int64_t b = gw; b < nbatch; b += nw) {
     const int64_t qown = b * 64 + lane;
     const bool valid = qown < a.m;
@@ -419,41 +467,51 @@ __global__ __launch_bounds__(kGPThreads) void gp_query_kernel(GPQueryArgs ga) {
     wave_sync();
     for (int k = 0; k < 64; ++k) {
       const QSlot<CT> sl = s_q[wv][k];
+      const CornerC<CT> c = slot_corner(sl, a.g, grp);
+      // rows of this lane: axes g = c8 + 8 r of corner grp
+      const int nrow = c.active ? max(0, (ns - c8 + 7) / 8) : 0;
+      const FT* rec = field + c.vox * (size_t)ga.stride;
+      // first loads are issued before the GP weights, which they do not need
+      FT xr[kChunk][16];
+      FT xt[kMaxRowsPerLane];
+      if constexpr (KIND == 0) {
+        load_rows<FT>(rec, c8, 0, nrow, xr);
+      } else {
+#pragma unroll
+        for (int r = 0; r < kMaxRowsPerLane; ++r)
+          xt[r] = (r < nrow) ? rec[c8 + 8 * r] : FT(0);
+      }
       // GP weights of this pose: w = (K^s + noise I)^-1 K_z, FP64
       const double z[3] = {(double)sl.z[0], (double)sl.z[1], (double)sl.z[2]};
       for (int g = lane; g < ns; g += 64) s_kz[wv][g] = se_kernel(z, ga.gp.axes + 3 * g, ga.gp.inv_2l2);
       wave_sync();
       for (int g = lane; g < ns; g += 64) {
         double w = 0.0;
-        for (int h = 0; h < ns; ++h) w = fma(ga.gp.kinv[(size_t)h * ns + g], s_kz[wv][h], w);
+        if (kinv_lds) {
+          const int rg = g * (g + 1) / 2;
+          for (int h = 0; h <= g; ++h) w = fma(s_kinv[rg + h], s_kz[wv][h], w);
+          for (int h = g + 1; h < ns; ++h) w = fma(s_kinv[h * (h + 1) / 2 + g], s_kz[wv][h], w);
+        } else {
+#pragma unroll 8
+          for (int h = 0; h < ns; ++h) w = fma(ga.gp.kinv[(size_t)h * ns + g], s_kz[wv][h], w);
+        }
         s_w[wv][g] = (CT)w;
       }
       wave_sync();
-      const CornerC<CT> c = slot_corner(sl, a.g, grp);
       if constexpr (KIND == 0) {
         CT acc[15];
 #pragma unroll
         for (int e = 0; e < 15; ++e) acc[e] = 0;
-        if (c.active) {
-          const FT* rec = field + c.vox * (size_t)ga.stride;
-          for (int g = c8; g < ns; g += 8) {
-            const CT wg = s_w[wv][g];
-            const FT* row = rec + (size_t)g * 16;
-            FT x[16];
+        for (int r0 = 0; r0 < nrow; r0 += kChunk) {
 #pragma unroll
-            for (int e = 0; e < 16; e += 4) {
-              if constexpr (sizeof(FT) == 4) {
-                const float4 v4 = *reinterpret_cast<const float4*>(row + e);
-                x[e] = v4.x; x[e + 1] = v4.y; x[e + 2] = v4.z; x[e + 3] = v4.w;
-              } else {
-                const double2 v0 = *reinterpret_cast<const double2*>(row + e);
-                const double2 v1 = *reinterpret_cast<const double2*>(row + e + 2);
-                x[e] = v0.x; x[e + 1] = v0.y; x[e + 2] = v1.x; x[e + 3] = v1.y;
-              }
+          for (int rr = 0; rr < kChunk; ++rr) {
+            if (r0 + rr < nrow) {
+              const CT wg = s_w[wv][c8 + 8 * (r0 + rr)];
+#pragma unroll
+              for (int e = 0; e < 15; ++e) acc[e] = fma(wg, (CT)xr[rr][e], acc[e]);
             }
-#pragma unroll
-            for (int e = 0; e < 15; ++e) acc[e] = fma(wg, (CT)x[e], acc[e]);
           }
+          if (r0 + kChunk < nrow) load_rows<FT>(rec, c8, r0 + kChunk, nrow, xr);
         }
         sum8_arr<15>(acc);
         if (c8 == 0) {
@@ -471,19 +529,18 @@ __global__ __launch_bounds__(kGPThreads) void gp_query_kernel(GPQueryArgs ga) {
         }
       } else {
         CT acc = 0;
-        if (c.active) {
-          const FT* rec = field + c.vox * (size_t)ga.stride;
-          for (int g = c8; g < ns; g += 8) acc = fma(s_w[wv][g], (CT)rec[g], acc);
-        }
+#pragma unroll
+        for (int r = 0; r < kMaxRowsPerLane; ++r)
+          if (r < nrow) acc = fma(s_w[wv][c8 + 8 * r], (CT)xt[r], acc);
         acc = sum8(acc);
         if (c8 == 0) s_c[wv][grp][0] = c.active ? acc * c.w : CT(0);
       }
       wave_sync();
       if (lane < (KIND == 0 ? 21 : 1)) {
-        CT s = 0;
+        CT sacc = 0;
 #pragma unroll
-        for (int j = 0; j < 8; ++j) s += s_c[wv][j][lane];
-        s_F[wv][k][lane] = s;
+        for (int j = 0; j < 8; ++j) sacc += s_c[wv][j][lane];
+        s_F[wv][k][lane] = sacc;
       }
       wave_sync();
     }
@@ -578,25 +635,45 @@ hipError_t launch_gp_evidence(const GPDev& gp, const double* train_u, int32_t n_
   return hipGetLastError();
 }
 
+template <int PREC, int KIND>
+hipError_t launch_gp_build_tiles(const GPBuildArgs& a, dim3 grid, int pass0, int nt,
+                                 hipStream_t stream) {
+  dim3 block(kGPThreads);
+  switch (nt) {
+    case 1: hipLaunchKernelGGL((gp_build_kernel<PREC, KIND, 1>), grid, block, 0, stream, a, pass0); break;
+    case 2: hipLaunchKernelGGL((gp_build_kernel<PREC, KIND, 2>), grid, block, 0, stream, a, pass0); break;
+    case 3: hipLaunchKernelGGL((gp_build_kernel<PREC, KIND, 3>), grid, block, 0, stream, a, pass0); break;
+    case 4: hipLaunchKernelGGL((gp_build_kernel<PREC, KIND, 4>), grid, block, 0, stream, a, pass0); break;
+    default: hipLaunchKernelGGL((gp_build_kernel<PREC, KIND, kGPTiles>), grid, block, 0, stream, a, pass0); break;
+  }
+  return hipGetLastError();
+}
+
 hipError_t launch_gp_build(const GPBuildArgs& a, int prec, int kind, hipStream_t stream) {
   const int64_t nvox = (int64_t)a.g.nx * a.g.ny * a.g.nz;
-  const int passes = (a.gp.ns + 16 * kGPTiles - 1) / (16 * kGPTiles);
   const int64_t want = (nvox + kGPWaves - 1) / kGPWaves;
   const int64_t cap = resident_blocks(8);
-  dim3 grid((unsigned)(want < cap ? want : cap), (unsigned)passes);
-  dim3 block(kGPThreads);
-#define FIF_GP_LAUNCH(P, K) hipLaunchKernelGGL((gp_build_kernel<P, K>), grid, block, 0, stream, a)
-  if (kind == 0) {
-    if (prec == 0) FIF_GP_LAUNCH(0, 0);
-    else if (prec == 1) FIF_GP_LAUNCH(1, 0);
-    else FIF_GP_LAUNCH(2, 0);
-  } else {
-    if (prec == 0) FIF_GP_LAUNCH(0, 1);
-    else if (prec == 1) FIF_GP_LAUNCH(1, 1);
-    else FIF_GP_LAUNCH(2, 1);
+  const unsigned gx = (unsigned)(want < cap ? want : cap);
+  // passes of kGPTiles 16-axis tiles; the last one with the tiles it needs
+  const int per = 16 * kGPTiles;
+  const int full = a.gp.ns / per;
+  const int rest_tiles = (a.gp.ns % per + 15) / 16;
+  auto run = [&](dim3 grid, int pass0, int nt) -> hipError_t {
+    if (kind == 0) {
+      if (prec == 0) return launch_gp_build_tiles<0, 0>(a, grid, pass0, nt, stream);
+      if (prec == 1) return launch_gp_build_tiles<1, 0>(a, grid, pass0, nt, stream);
+      return launch_gp_build_tiles<2, 0>(a, grid, pass0, nt, stream);
+    }
+    if (prec == 0) return launch_gp_build_tiles<0, 1>(a, grid, pass0, nt, stream);
+    if (prec == 1) return launch_gp_build_tiles<1, 1>(a, grid, pass0, nt, stream);
+    return launch_gp_build_tiles<2, 1>(a, grid, pass0, nt, stream);
+  };
+  if (full > 0) {
+    hipError_t e = run(dim3(gx, (unsigned)full), 0, kGPTiles);
+    if (e != hipSuccess) return e;
   }
-#undef FIF_GP_LAUNCH
-  return hipGetLastError();
+  if (rest_tiles > 0) return run(dim3(gx, 1), full, rest_tiles);
+  return hipSuccess;
 }
 
 hipError_t launch_gp_query(const GPQueryArgs& a, int prec, int kind, hipStream_t stream) {
