@@ -76,20 +76,27 @@ def cpu_model():
     return platform.processor() or "unknown"
 
 
+# Sources that define the query kernel: its committed HBM counters stand only
+# while these are unchanged.
+QUERY_SOURCES = ("fif_query.hip", "fif_slot.h", "fif_device.h", "fif_metrics.h")
+
+
+def query_src_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for f in QUERY_SOURCES:
+        h.update(open(os.path.join(ROOT, "paper_2008_03324_amd", "csrc", f), "rb").read())
+    return h.hexdigest()[:16]
+
+
 def counter_traffic(kernel):
     """HBM bytes per launch from the committed rocprofv3 counters, or None when
-    the kernel sources changed since they were taken."""
-    import glob
-    import hashlib
+    the query kernel's sources changed since they were taken."""
     path = os.path.join(ROOT, "profiles", "counters.json")
     if not os.path.exists(path):
         return None
     rec = json.load(open(path))
-    h = hashlib.sha256()
-    for f in sorted(glob.glob(os.path.join(ROOT, "paper_2008_03324_amd", "csrc", "*"))):
-        if os.path.isfile(f):
-            h.update(open(f, "rb").read())
-    if h.hexdigest()[:16] != rec.get("src_hash"):
+    if query_src_hash() != rec.get("query_src_hash"):
         return None
     gb = rec.get("traffic_GB_per_launch", {}).get(kernel)
     return None if gb is None else gb * 1e9
@@ -230,10 +237,10 @@ def main():
         "build_tested_pairs_per_s": tested / (med["build"] / 1e3),
         "contributing_fraction": frac,
         "grad_poses_per_s": mg / (med["grad"] / 1e3),
-        "roofline": {"kernel": "query_info_kernel<float>", "bound": "hbm",
+        "roofline": {"kernel": "query_info_pipe_kernel", "bound": "hbm",
                      "achieved": q_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": q_gbs / HBM_PEAK_GBS,
-                     "traffic": counter_traffic("fif::query_info_kernel<float, false>"),
+                     "traffic": counter_traffic("fif::query_info_pipe_kernel"),
                      "algorithmic_bytes": q_bytes, "bytes_per_query": q_bytes / m},
         "roofline_build": {"kernel": "build_kernel<FP32_COMP>", "bound": "fp32 valu",
                            "achieved": b_tfs, "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
