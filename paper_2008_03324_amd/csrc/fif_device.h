@@ -501,7 +501,22 @@ __device__ inline double rcp_nr(double x) {
 
 #define FIF_A(i, j) a[su21((i), (j))]
 
-// Cyclic Jacobi on a symmetric 6x6 held as 21 values.  Sweeps until the
+// Round rd (0..4) of the round-robin schedule of the 15 pairs of 6 indices
+// (index 0 fixed, the others rotated): three disjoint pairs (P[k], Q[k]), P < Q.
+__device__ constexpr void round_robin6(int rd, int P[3], int Q[3]) {
+  int ring[5] = {1, 2, 3, 4, 5};
+  int r[5];
+  for (int i = 0; i < 5; ++i) r[i] = ring[(i + rd) % 5];
+  // pairs: (0, r0), (r1, r4), (r2, r3)
+  int a[3] = {0, r[1], r[2]}, b[3] = {r[0], r[4], r[3]};
+  for (int k = 0; k < 3; ++k) {
+    P[k] = a[k] < b[k] ? a[k] : b[k];
+    Q[k] = a[k] < b[k] ? b[k] : a[k];
+  }
+}
+
+// Jacobi on a symmetric 6x6 held as 21 values, the pairs of each sweep in
+// round-robin order (3 disjoint rotations per round).  Sweeps until the
 // off-diagonal Frobenius norm is below 1e-11 of the full norm (or 16 sweeps);
 // by Weyl's inequality every diagonal entry is then within that distance of an
 // eigenvalue, far inside the FP64 metric tolerance.
@@ -528,10 +543,19 @@ __device__ inline void jacobi6(double a[21], double V[36]) {
 #pragma unroll
       for (int j = i + 1; j < 6; ++j) off += 2.0 * FIF_A(i, j) * FIF_A(i, j);
     if (!(off > 1e-22 * fro)) break;
+    // Each sweep visits the 15 pairs in 5 rounds of 3 disjoint pairs (round-robin
+    // order).  Rotations on disjoint index pairs commute, so the three angles of
+    // a round are computed from the same matrix and applied one after another:
+    // three independent dependency chains instead of one.
 #pragma unroll
-    for (int p = 0; p < 6; ++p)
+    for (int rd = 0; rd < 5; ++rd) {
+      int P[3], Q[3];
+      round_robin6(rd, P, Q);
+      double cr[3], sr[3], tr[3], ar[3];
+      bool sk[3];
 #pragma unroll
-      for (int q = p + 1; q < 6; ++q) {
+      for (int k = 0; k < 3; ++k) {
+        const int p = P[k], q = Q[k];
         const double apq = FIF_A(p, q);
         const double app = FIF_A(p, p), aqq = FIF_A(q, q);
         const double d = aqq - app;
@@ -542,27 +566,37 @@ __device__ inline void jacobi6(double a[21], double V[36]) {
         double tt = 2.0 * apq * rcp_nr(fabs(d) + r);
         tt = (d < 0.0) ? -tt : tt;
         tt = skip ? 0.0 : tt;
-        const double c = rsq_nr(fma(tt, tt, 1.0));
-        const double s = tt * c;
+        cr[k] = rsq_nr(fma(tt, tt, 1.0));
+        sr[k] = tt * cr[k];
+        tr[k] = tt;
+        ar[k] = apq;
+        sk[k] = skip;
+      }
 #pragma unroll
-        for (int k = 0; k < 6; ++k) {
-          if (k == p || k == q) continue;
-          double akp = FIF_A(k, p), akq = FIF_A(k, q);
-          FIF_A(k, p) = c * akp - s * akq;
-          FIF_A(k, q) = s * akp + c * akq;
+      for (int k = 0; k < 3; ++k) {
+        const int p = P[k], q = Q[k];
+        const double c = cr[k], s = sr[k], tt = tr[k], apq = ar[k];
+        const double app = FIF_A(p, p), aqq = FIF_A(q, q);
+#pragma unroll
+        for (int m = 0; m < 6; ++m) {
+          if (m == p || m == q) continue;
+          double akp = FIF_A(m, p), akq = FIF_A(m, q);
+          FIF_A(m, p) = c * akp - s * akq;
+          FIF_A(m, q) = s * akp + c * akq;
         }
         FIF_A(p, p) = app - tt * apq;
         FIF_A(q, q) = aqq + tt * apq;
-        FIF_A(p, q) = skip ? apq : 0.0;
+        FIF_A(p, q) = sk[k] ? apq : 0.0;
         if (WANT_V) {
 #pragma unroll
-          for (int k = 0; k < 6; ++k) {
-            double vkp = V[k * 6 + p], vkq = V[k * 6 + q];
-            V[k * 6 + p] = c * vkp - s * vkq;
-            V[k * 6 + q] = s * vkp + c * vkq;
+          for (int m = 0; m < 6; ++m) {
+            double vkp = V[m * 6 + p], vkq = V[m * 6 + q];
+            V[m * 6 + p] = c * vkp - s * vkq;
+            V[m * 6 + q] = s * vkp + c * vkq;
           }
         }
       }
+    }
   }
 }
 
