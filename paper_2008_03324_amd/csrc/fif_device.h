@@ -505,7 +505,7 @@ __device__ inline double rcp_nr(double x) {
 // (index 0 fixed, the others rotated): three disjoint pairs (P[k], Q[k]), P < Q.
 __device__ constexpr void round_robin6(int rd, int P[3], int Q[3]) {
   int ring[5] = {1, 2, 3, 4, 5};
-  int r[5];
+  int r[5] = {0, 0, 0, 0, 0};
   for (int i = 0; i < 5; ++i) r[i] = ring[(i + rd) % 5];
   // pairs: (0, r0), (r1, r4), (r2, r3)
   int a[3] = {0, r[1], r[2]}, b[3] = {r[0], r[4], r[3]};

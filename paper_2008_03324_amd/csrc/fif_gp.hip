@@ -565,6 +565,82 @@ __global__ __launch_bounds__(kGPThreads) void gp_query_kernel(GPQueryArgs ga) {
   }
 }
 
+// Trace fields: one lane per pose.  The lane interpolates its pose's N_s
+// trace factors into an LDS column, then accumulates
+//   Tr = sum_g K_z[g] sum_h kinv[g][h] Tbar_h
+// with the inverse read at wave-uniform addresses (scalar loads, once per
+// wave instead of once per pose) and K_z formed per lane in FP64.
+template <typename FT>
+__global__ __launch_bounds__(256) void gp_query_trace_kernel(GPQueryArgs ga) {
+  using CT = FT;
+  extern __shared__ unsigned char s_dyn[];
+  CT* col = reinterpret_cast<CT*>(s_dyn);  // [ns][blockDim.x]
+  const QueryArgs& a = ga.q;
+  const int ns = ga.gp.ns;
+  const int tid = threadIdx.x, nt = blockDim.x;
+  const int64_t qi = (int64_t)blockIdx.x * nt + tid;
+  const bool valid = qi < a.m;
+  const int64_t ql = valid ? qi : a.m - 1;
+  const QSlot<CT> sl = make_slot<FT>(a, ql);
+  const FT* field = reinterpret_cast<const FT*>(a.field);
+  // interpolated factors: corner by corner, each lane streaming its corner's
+  // row (so a wave's lines stay in L1 while they are read), accumulated in
+  // the lane's LDS column
+  for (int h = 0; h < ns; ++h) col[(size_t)h * nt + tid] = CT(0);
+  const int n4 = (ns + 3) / 4;
+  for (int j = 0; j < 8; ++j) {
+    const CornerC<CT> c = slot_corner(sl, a.g, j);
+    if (!c.active) continue;
+    const FT* row = field + c.vox * (size_t)ga.stride;
+#pragma unroll 2
+    for (int h4 = 0; h4 < n4; ++h4) {
+      FT x[4];
+      if constexpr (sizeof(FT) == 4) {
+        const float4 v4 = *reinterpret_cast<const float4*>(row + 4 * h4);
+        x[0] = v4.x; x[1] = v4.y; x[2] = v4.z; x[3] = v4.w;
+      } else {
+        const double2 v0 = *reinterpret_cast<const double2*>(row + 4 * h4);
+        const double2 v1 = *reinterpret_cast<const double2*>(row + 4 * h4 + 2);
+        x[0] = v0.x; x[1] = v0.y; x[2] = v1.x; x[3] = v1.y;
+      }
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int h = 4 * h4 + e;
+        if (h < ns) {
+          CT* cp = col + (size_t)h * nt + tid;
+          *cp = fma(c.w, (CT)x[e], *cp);
+        }
+      }
+    }
+  }
+  // Tr = K_z^T (K^s + noise I)^-1 Tbar in FP64, kRows rows of the inverse at a
+  // time (each streamed along h; every Tbar_h read feeds kRows accumulators)
+  constexpr int kRows = 4;
+  const double z[3] = {(double)sl.z[0], (double)sl.z[1], (double)sl.z[2]};
+  double tr = 0.0;
+  for (int g0 = 0; g0 < ns; g0 += kRows) {
+    const double* kr[kRows];
+#pragma unroll
+    for (int k = 0; k < kRows; ++k)
+      kr[k] = ga.gp.kinv + (size_t)(g0 + k < ns ? g0 + k : g0) * ns;
+    double y[kRows];
+#pragma unroll
+    for (int k = 0; k < kRows; ++k) y[k] = 0.0;
+    for (int h = 0; h < ns; ++h) {
+      const double th = (double)col[(size_t)h * nt + tid];
+#pragma unroll
+      for (int k = 0; k < kRows; ++k) y[k] = fma(kr[k][h], th, y[k]);
+    }
+#pragma unroll
+    for (int k = 0; k < kRows; ++k)
+      if (g0 + k < ns) tr = fma(se_kernel(z, ga.gp.axes + 3 * (g0 + k), ga.gp.inv_2l2), y[k], tr);
+  }
+  if (valid) {
+    if (a.out) a.out[ql * a.ncols] = tr * a.vis.inv_s2;
+    if (a.flags) a.flags[ql] = (sl.bits & 8) ? FL_CLAMPED : 0;
+  }
+}
+
 // ---------------------------------------------------------------- export
 
 // One thread per (voxel, axis g): C_g = sum_h kinv[g][h] world(S_h) / sigma^2.
@@ -682,13 +758,18 @@ hipError_t launch_gp_query(const GPQueryArgs& a, int prec, int kind, hipStream_t
   const int64_t want = (nbatch + kGPWaves - 1) / kGPWaves;
   const int64_t cap = resident_blocks(8);
   dim3 grid((unsigned)(want < cap ? want : cap)), block(kGPThreads);
-  if (prec == 2) {
-    if (kind == 0) hipLaunchKernelGGL((gp_query_kernel<double, 0>), grid, block, 0, stream, a);
-    else hipLaunchKernelGGL((gp_query_kernel<double, 1>), grid, block, 0, stream, a);
-  } else {
-    if (kind == 0) hipLaunchKernelGGL((gp_query_kernel<float, 0>), grid, block, 0, stream, a);
-    else hipLaunchKernelGGL((gp_query_kernel<float, 1>), grid, block, 0, stream, a);
+  if (kind == 1) {
+    // one lane per pose; the LDS columns (N_s per lane) set the workgroup size
+    const size_t sb = prec == 2 ? 8 : 4;
+    const int nt = ((size_t)a.gp.ns * 256 * sb <= 80 * 1024) ? 256 : 64;
+    const size_t lds = (size_t)a.gp.ns * nt * sb;
+    dim3 tgrid((unsigned)((a.q.m + nt - 1) / nt)), tblock(nt);
+    if (prec == 2) hipLaunchKernelGGL((gp_query_trace_kernel<double>), tgrid, tblock, lds, stream, a);
+    else hipLaunchKernelGGL((gp_query_trace_kernel<float>), tgrid, tblock, lds, stream, a);
+    return hipGetLastError();
   }
+  if (prec == 2) hipLaunchKernelGGL((gp_query_kernel<double, 0>), grid, block, 0, stream, a);
+  else hipLaunchKernelGGL((gp_query_kernel<float, 0>), grid, block, 0, stream, a);
   return hipGetLastError();
 }
 
