@@ -121,3 +121,40 @@ def test_product_package_does_not_import_the_oracle():
                 text = open(os.path.join(dirpath, fn)).read()
                 assert "import oracle" not in text and "oracle/" not in text, fn
                 assert "fif_oracle" not in text, fn
+
+
+def test_gp_host_side_validation():
+    """GP entry points reject bad models and arguments before enqueuing anything."""
+    fif, L = _lib()
+    g = fif.Grid((0.0, 0.0, 0.0), 0.5, (4, 4, 4))
+    vis = fif.Vis()
+    gp = fif.CGP(30, 0, 15.0, 0.9, 1e-10, 4096, 8192)
+    assert L.fif_gp_field_bytes(ctypes.byref(g.c()), 30, fif.FP32_COMP, fif.KIND_INFO) == 64 * 30 * 16 * 4
+    assert L.fif_gp_field_bytes(ctypes.byref(g.c()), 30, fif.FP64, fif.KIND_TRACE) == 64 * 32 * 8
+    assert L.fif_gp_field_bytes(ctypes.byref(g.c()), 0, fif.FP64, fif.KIND_INFO) == 0
+    assert L.fif_gp_field_bytes(ctypes.byref(g.c()), 161, fif.FP64, fif.KIND_INFO) == 0
+    for bad in (fif.CGP(0, 0, 15.0, 0.9, 1e-10, 4096, 8192),      # no axes
+                fif.CGP(200, 0, 15.0, 0.9, 1e-10, 4096, 8192),    # too many axes
+                fif.CGP(30, 1, 15.0, 0.9, 1e-10, 4096, 8192),     # reserved
+                fif.CGP(30, 0, -1.0, 0.9, 1e-10, 4096, 8192),     # k_s
+                fif.CGP(30, 0, 15.0, 0.0, 1e-10, 4096, 8192),     # length
+                fif.CGP(30, 0, 15.0, 0.9, -1.0, 4096, 8192),      # noise
+                fif.CGP(30, 0, 15.0, 0.9, 1e-10, None, 8192),     # axes NULL
+                fif.CGP(30, 0, 15.0, 0.9, 1e-10, 4096, None)):    # kinv NULL
+        assert L.fif_gp_setup(ctypes.byref(bad), None) == -1
+    assert L.fif_gp_evidence(ctypes.byref(gp), 0.0, None, 0, None, 1, None, None) == -1  # fov
+    assert L.fif_gp_evidence(ctypes.byref(gp), 0.7, None, 10, None, 1, None, None) == -1  # NULL
+    assert L.fif_gp_evidence(ctypes.byref(gp), 0.7, None, 0, None, 0, None, None) == 0   # nothing
+    f = fif.CGPField(g.c(), vis.c(), gp, fif.FP32_COMP, fif.KIND_INFO, None)        # NULL data
+    assert L.fif_gp_build(None, 10, ctypes.byref(f), None, 0, None) == -1
+    f.data = 4096
+    assert L.fif_gp_build(None, 10, ctypes.byref(f), None, 0, None) == -1               # NULL landmarks
+    assert L.fif_gp_build(None, -1, ctypes.byref(f), None, 0, None) == -1
+    assert L.fif_gp_query(ctypes.byref(f), None, None, 5, 0, 0, None, None, None) == -1  # no metric
+    assert L.fif_gp_query(ctypes.byref(f), None, None, 5, 1, 2, None, None, None) == -1  # interp
+    assert L.fif_gp_query(ctypes.byref(f), None, None, 5, 1, 0, None, None, None) == -1  # NULL t
+    assert L.fif_gp_query(ctypes.byref(f), None, None, 0, 7, 0, None, None, None) == 0   # m = 0
+    ft = fif.CGPField(g.c(), vis.c(), gp, fif.FP32_COMP, fif.KIND_TRACE, 4096)
+    assert L.fif_gp_query(ctypes.byref(ft), None, None, 5, 2, 0, None, None, None) == -1
+    assert L.fif_gp_export(ctypes.byref(f), None, 3, None, None) == -1
+    assert L.fif_gp_export(ctypes.byref(f), None, 0, None, None) == 0
