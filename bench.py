@@ -89,6 +89,31 @@ def query_src_hash():
     return h.hexdigest()[:16]
 
 
+BUILD_SOURCES = ("fif_build.hip", "fif_device.h")
+PC_SOURCES = ("fif_pc.hip", "fif_device.h")
+
+
+def src_hash(files):
+    import hashlib
+    h = hashlib.sha256()
+    for f in files:
+        h.update(open(os.path.join(ROOT, "paper_2008_03324_amd", "csrc", f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def counter_flops(kernel, files):
+    """Hardware-counted FLOPs per launch (SQ_INSTS_VALU_FLOPS_FP32 x 64 lanes plus
+    MFMA ops) from the committed counters, or None when the kernel's sources
+    changed since they were taken."""
+    path = os.path.join(ROOT, "profiles", "counters.json")
+    if not os.path.exists(path):
+        return None
+    rec = json.load(open(path)).get("flops", {}).get(kernel)
+    if not rec or rec.get("src_hash") != src_hash(files):
+        return None
+    return rec
+
+
 def counter_traffic(kernel):
     """HBM bytes per launch from the committed rocprofv3 counters, or None when
     the query kernel's sources changed since they were taken."""
@@ -246,6 +271,12 @@ def main():
                            "achieved": b_tfs, "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
                            "frac": b_tfs / FP32_PEAK_TFLOPS},
     }
+    # hardware-counted FLOPs (rocprofv3 SQ_INSTS_VALU_FLOPS_FP32; issued
+    # instructions x 64 lanes, so lanes masked off in divergent branches count)
+    cb = counter_flops("fif::build_kernel<1, 0>", BUILD_SOURCES)
+    if cb:
+        t = cb["fp32"] / (med["build"] / 1e3) / 1e12
+        res["roofline_build"].update({"counter_achieved": t, "counter_frac": t / FP32_PEAK_TFLOPS})
     if "pc" in phases:
         pc_rate = m / (med["pc"] / 1e3)
         pc_flops = frac * pc_tested * PC_FLOPS_CONTRIB + (1 - frac) * pc_tested * PC_FLOPS_TESTED
@@ -255,6 +286,10 @@ def main():
                               "achieved": pc_flops / (med["pc"] / 1e3) / 1e12,
                               "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s"}
         res["roofline_pc"]["frac"] = res["roofline_pc"]["achieved"] / FP32_PEAK_TFLOPS
+        cp = counter_flops("fif::pc_kernel<1, false>", PC_SOURCES)
+        if cp:
+            t = cp["fp32"] / (med["pc"] / 1e3) / 1e12
+            res["roofline_pc"].update({"counter_achieved": t, "counter_frac": t / FP32_PEAK_TFLOPS})
 
     if not args.no_sweep:
         res["view_sweep"] = sweep_leg(fif, torch, scenes, g, field, dev)
