@@ -275,8 +275,9 @@ def main():
     # instructions x 64 lanes, so lanes masked off in divergent branches count)
     cb = counter_flops("fif::build_kernel<1, 0>", BUILD_SOURCES)
     if cb:
-        t = cb["fp32"] / (med["build"] / 1e3) / 1e12
-        res["roofline_build"].update({"counter_achieved": t, "counter_frac": t / FP32_PEAK_TFLOPS})
+        ctf = cb["fp32"] / (med["build"] / 1e3) / 1e12
+        res["roofline_build"].update({"counter_achieved": ctf,
+                                      "counter_frac": ctf / FP32_PEAK_TFLOPS})
     if "pc" in phases:
         pc_rate = m / (med["pc"] / 1e3)
         pc_flops = frac * pc_tested * PC_FLOPS_CONTRIB + (1 - frac) * pc_tested * PC_FLOPS_TESTED
@@ -288,8 +289,9 @@ def main():
         res["roofline_pc"]["frac"] = res["roofline_pc"]["achieved"] / FP32_PEAK_TFLOPS
         cp = counter_flops("fif::pc_kernel<1, false>", PC_SOURCES)
         if cp:
-            t = cp["fp32"] / (med["pc"] / 1e3) / 1e12
-            res["roofline_pc"].update({"counter_achieved": t, "counter_frac": t / FP32_PEAK_TFLOPS})
+            ctf = cp["fp32"] / (med["pc"] / 1e3) / 1e12
+            res["roofline_pc"].update({"counter_achieved": ctf,
+                                       "counter_frac": ctf / FP32_PEAK_TFLOPS})
 
     if not args.no_sweep:
         res["view_sweep"] = sweep_leg(fif, torch, scenes, g, field, dev)
