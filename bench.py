@@ -81,12 +81,17 @@ def cpu_model():
 QUERY_SOURCES = ("fif_query.hip", "fif_slot.h", "fif_device.h", "fif_metrics.h")
 
 
+def _code_only(text: str) -> bytes:
+    """Source text without comments and whitespace: edits to comments do not
+    invalidate the committed counters."""
+    import re
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    text = re.sub(r"//[^\n]*", "", text)
+    return re.sub(r"\s+", "", text).encode()
+
+
 def query_src_hash():
-    import hashlib
-    h = hashlib.sha256()
-    for f in QUERY_SOURCES:
-        h.update(open(os.path.join(ROOT, "paper_2008_03324_amd", "csrc", f), "rb").read())
-    return h.hexdigest()[:16]
+    return src_hash(QUERY_SOURCES)
 
 
 BUILD_SOURCES = ("fif_build.hip", "fif_device.h")
@@ -97,7 +102,7 @@ def src_hash(files):
     import hashlib
     h = hashlib.sha256()
     for f in files:
-        h.update(open(os.path.join(ROOT, "paper_2008_03324_amd", "csrc", f), "rb").read())
+        h.update(_code_only(open(os.path.join(ROOT, "paper_2008_03324_amd", "csrc", f)).read()))
     return h.hexdigest()[:16]
 
 

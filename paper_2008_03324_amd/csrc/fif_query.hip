@@ -3,14 +3,17 @@
 //
 // Information field, trilinear: a wave serves 64 queries.  Lanes are grouped
 // by 8; in pass `it` group g serves query 8g + it and lane j of the group
-// gathers trilinear corner j (a 272-B record for FP32 fields), contracts its
+// gathers trilinear corner j (a 264-B record for FP32 fields), contracts its
 // moments with the optical axis into the voxel's 6x6 block, moves it to the
 // query position (the blocks are taken about different voxel centres, so
 // each corner is shifted before the weighted sum), and the 8 partial sums
 // are reduced with cross-lane shuffles.  After 8 passes every lane holds the
 // FIM of its own query and evaluates the FP64 metrics, so no lane idles in the
 // eigen-solve.  The fused backward repeats the corner gathers with the metric
-// gradient broadcast to the group.
+// gradient broadcast to the group.  Forward queries on FP32 fields run in
+// query_info_pipe_kernel, the same arithmetic with persistent waves and the
+// gathers issued one corner step (and one batch) ahead.  Also here: the trace
+// field query, the optimal-view sweep and the export of the paper's blocks.
 #include "fif_kernels.h"
 #include "fif_metrics.h"
 #include "fif_slot.h"
