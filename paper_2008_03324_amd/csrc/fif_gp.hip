@@ -428,8 +428,11 @@ __device__ inline void load_rows(const FT* rec, int c8, int r0, int nrow, FT x[k
   }
 }
 
+// FP32 fields: two waves per SIMD (the register budget that keeps the gathers
+// of two waves in flight); FP64 fields take one.
 template <typename FT, int KIND>
-__global__ __launch_bounds__(kGPThreads) void gp_query_kernel(GPQueryArgs ga) {
+__global__ __launch_bounds__(kGPThreads)
+__attribute__((amdgpu_waves_per_eu(sizeof(FT) == 4 ? 2 : 1))) void gp_query_kernel(GPQueryArgs ga) {
   using CT = FT;
   const QueryArgs& a = ga.q;
   __shared__ QSlot<CT> s_q[kGPWaves][64];
@@ -481,21 +484,44 @@ __global__ __launch_bounds__(kGPThreads) void gp_query_kernel(GPQueryArgs ga) {
         for (int r = 0; r < kMaxRowsPerLane; ++r)
           xt[r] = (r < nrow) ? rec[c8 + 8 * r] : FT(0);
       }
-      // GP weights of this pose: w = (K^s + noise I)^-1 K_z, FP64
+      // GP weights of this pose: w = (K^s + noise I)^-1 K_z, FP64.  Lane l
+      // forms rows l, l + 64 and l + 128, each summed over h = 0 .. ns - 1 in
+      // order; every lane runs the same trip count, so the reads of the
+      // inverse pipeline instead of waiting one by one.
       const double z[3] = {(double)sl.z[0], (double)sl.z[1], (double)sl.z[2]};
       for (int g = lane; g < ns; g += 64) s_kz[wv][g] = se_kernel(z, ga.gp.axes + 3 * g, ga.gp.inv_2l2);
       wave_sync();
-      for (int g = lane; g < ns; g += 64) {
-        double w = 0.0;
-        if (kinv_lds) {
-          const int rg = g * (g + 1) / 2;
-          for (int h = 0; h <= g; ++h) w = fma(s_kinv[rg + h], s_kz[wv][h], w);
-          for (int h = g + 1; h < ns; ++h) w = fma(s_kinv[h * (h + 1) / 2 + g], s_kz[wv][h], w);
-        } else {
-#pragma unroll 8
-          for (int h = 0; h < ns; ++h) w = fma(ga.gp.kinv[(size_t)h * ns + g], s_kz[wv][h], w);
+      {
+        const int nr = (ns + 63) >> 6;  // rows per lane, 1 .. 3
+        double wr[3] = {0.0, 0.0, 0.0};
+        int gr[3], rs[3];
+#pragma unroll
+        for (int r = 0; r < 3; ++r) {
+          gr[r] = min(lane + 64 * r, ns - 1);  // lanes past the end repeat a row
+          rs[r] = gr[r] * (gr[r] + 1) / 2;
         }
-        s_w[wv][g] = (CT)w;
+        if (kinv_lds) {
+          int hs = 0;  // h (h + 1) / 2: start of packed row h
+#pragma unroll 1
+          for (int h = 0; h < ns; ++h) {
+            const double kzh = s_kz[wv][h];
+#pragma unroll
+            for (int r = 0; r < 3; ++r)
+              if (r < nr) wr[r] = fma(s_kinv[(h >= gr[r]) ? hs + gr[r] : rs[r] + h], kzh, wr[r]);
+            hs += h + 1;
+          }
+        } else {
+#pragma unroll 1
+          for (int h = 0; h < ns; ++h) {
+            const double kzh = s_kz[wv][h];
+#pragma unroll
+            for (int r = 0; r < 3; ++r)
+              if (r < nr) wr[r] = fma(ga.gp.kinv[(size_t)h * ns + gr[r]], kzh, wr[r]);
+          }
+        }
+#pragma unroll
+        for (int r = 0; r < 3; ++r)
+          if (lane + 64 * r < ns) s_w[wv][lane + 64 * r] = (CT)wr[r];
       }
       wave_sync();
       if constexpr (KIND == 0) {
