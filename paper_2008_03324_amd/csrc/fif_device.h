@@ -628,6 +628,68 @@ __device__ inline bool ldlt6(const double F[21], double L[36], double dinv[6], d
   return pd;
 }
 
+// Unit eigenvector of the smallest eigenvalue of a symmetric 6x6 (21 values)
+// by inverse iteration: LDL^T of F - sigma I with sigma just below that
+// eigenvalue (so the factorisation is of a positive definite matrix), then
+// three solves starting from (1, ..., 1).  Each solve shrinks the component
+// along eigenvector i relative to the wanted one by
+// (lambda_min - sigma) / (lambda_i - sigma).  The iterate is rescaled by its
+// largest component before it is normalised, so no sum of squares overflows.
+__device__ inline void lmin_vector6(const double F[21], double sigma, double v[6]) {
+  double L[36], d[6], dinv[6];
+#pragma unroll
+  for (int j = 0; j < 6; ++j) {
+    double s = F[u21(j, j)] - sigma;
+#pragma unroll
+    for (int k = 0; k < j; ++k) s -= L[j * 6 + k] * L[j * 6 + k] * d[k];
+    d[j] = s;
+    dinv[j] = 1.0 / s;
+#pragma unroll
+    for (int i = j + 1; i < 6; ++i) {
+      double r = F[u21(j, i)];
+#pragma unroll
+      for (int k = 0; k < j; ++k) r -= L[i * 6 + k] * L[j * 6 + k] * d[k];
+      L[i * 6 + j] = r * dinv[j];
+    }
+  }
+  double x[6] = {1.0, 1.0, 1.0, 1.0, 1.0, 1.0};
+#pragma unroll
+  for (int it = 0; it < 3; ++it) {
+    double y[6];
+#pragma unroll
+    for (int i = 0; i < 6; ++i) {  // L y = x
+      double s = x[i];
+#pragma unroll
+      for (int k = 0; k < i; ++k) s -= L[i * 6 + k] * y[k];
+      y[i] = s;
+    }
+#pragma unroll
+    for (int i = 0; i < 6; ++i) y[i] *= dinv[i];  // D z = y
+#pragma unroll
+    for (int i = 5; i >= 0; --i) {  // L^T x = z
+      double s = y[i];
+#pragma unroll
+      for (int k = i + 1; k < 6; ++k) s -= L[k * 6 + i] * x[k];
+      x[i] = s;
+    }
+    double mx = fabs(x[0]);
+#pragma unroll
+    for (int i = 1; i < 6; ++i) mx = fmax(mx, fabs(x[i]));
+    const double inv = 1.0 / mx;
+    double n2 = 0.0;
+#pragma unroll
+    for (int i = 0; i < 6; ++i) {
+      x[i] *= inv;
+      n2 = fma(x[i], x[i], n2);
+    }
+    const double rn = 1.0 / sqrt(n2);
+#pragma unroll
+    for (int i = 0; i < 6; ++i) x[i] *= rn;
+  }
+#pragma unroll
+  for (int i = 0; i < 6; ++i) v[i] = x[i];
+}
+
 // F^-1 (21) from the LDL^T factors.
 __device__ inline void ldlt6_inverse(const double L[36], const double dinv[6], double out[21]) {
   // X = L^-T D^-1 L^-1; compute W = L^-1 (unit lower), then X = W^T D^-1 W

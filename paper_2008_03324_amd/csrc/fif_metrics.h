@@ -36,8 +36,7 @@ __device__ inline void eval_metrics(const double F[21], uint32_t metrics, double
     double a[21];
 #pragma unroll
     for (int e = 0; e < 21; ++e) a[e] = F[e];
-    double V[GRAD ? 36 : 1];
-    jacobi6<GRAD>(a, V);
+    jacobi6<false>(a, nullptr);
     double ev[6];
 #pragma unroll
     for (int i = 0; i < 6; ++i) ev[i] = a[u21(i, i)];
@@ -57,15 +56,13 @@ __device__ inline void eval_metrics(const double F[21], uint32_t metrics, double
     if (row) row[col] = lmin;
     ++col;
     if (GRAD) {
+      // d lambda_min / dF = v v^T with v the unit eigenvector (undefined at a
+      // tie, which is flagged); v by inverse iteration with the shift
+      // 1e-10 max|lambda| below lambda_min, more than the Jacobi error of
+      // lambda_min (1e-11 |F|), so that F - sigma I stays positive definite
       double g = up[upc++];
       double v[6];
-#pragma unroll
-      for (int r = 0; r < 6; ++r) {
-        double s = V[r * 6 + 0];
-#pragma unroll
-        for (int c = 1; c < 6; ++c) s = (imin == c) ? V[r * 6 + c] : s;
-        v[r] = s;
-      }
+      lmin_vector6(F, lmin - fmax(1e-10 * amax, 1e-300), v);
 #pragma unroll
       for (int i = 0; i < 6; ++i)
 #pragma unroll

@@ -81,7 +81,7 @@ __global__ __launch_bounds__(kQThreads) void query_info_kernel(QueryArgs a) {
   CT Z[21];
 #pragma unroll
   for (int e = 0; e < 21; ++e) Z[e] = 0;
-  if constexpr (!GRAD && sizeof(FT) == 4) {
+  if constexpr (sizeof(FT) == 4) {
     FT recN[kMom];
     {
       const CornerC<CT> c0 = slot_corner(s_q[wbase + grp * 8], a.g, j);
@@ -163,6 +163,11 @@ __global__ __launch_bounds__(kQThreads) void query_info_kernel(QueryArgs a) {
   }
   __syncthreads();
   CT keep[6] = {0, 0, 0, 0, 0, 0};
+  FT recB[kMom];
+  if constexpr (sizeof(FT) == 4) {
+    const CornerC<CT> c0 = slot_corner(s_q[wbase + grp * 8], a.g, j);
+    load_record<FT>(field, nvox, c0.vox, c0.cell, j, recB);
+  }
   for (int it = 0; it < 8; ++it) {
     const int src = wbase + grp * 8 + it;
     const QSlot<CT> sl = s_q[src];
@@ -171,7 +176,17 @@ __global__ __launch_bounds__(kQThreads) void query_info_kernel(QueryArgs a) {
     for (int e = 0; e < 21; ++e) Gb[e] = s_g[GRAD ? src : 0][e];
     const CornerC<CT> c = slot_corner(sl, a.g, j);
     FT rec[kMom];
-    load_record<FT>(field, nvox, c.vox, c.cell, j, rec);
+    if constexpr (sizeof(FT) == 4) {
+      // FP32 records: the next query's record is loaded before this one is used
+#pragma unroll
+      for (int e = 0; e < kMom; ++e) rec[e] = recB[e];
+      if (it < 7) {
+        const CornerC<CT> cn = slot_corner(s_q[src + 1], a.g, j);
+        load_record<FT>(field, nvox, cn.vox, cn.cell, j, recB);
+      }
+    } else {
+      load_record<FT>(field, nvox, c.vox, c.cell, j, rec);
+    }
     CT Gp[21];
     shift21_adj<CT>(Gb, c.dl, Gp);
     CT val, gz[3];
