@@ -11,7 +11,9 @@ Differentiable Map for Perception-aware Planning", arXiv 2008.03324.
 """
 from __future__ import annotations
 
+import contextlib
 import ctypes
+import functools
 import math
 import os
 from dataclasses import dataclass
@@ -140,6 +142,19 @@ def _stream(stream=None):
     return ctypes.c_void_p(stream.cuda_stream)
 
 
+def _on_stream(fn):
+    """A call given `stream` runs with that stream current, so that every tensor
+    it allocates (outputs, temporaries, workspaces) belongs to the stream its
+    kernels are enqueued on: the caching allocator then does not hand that
+    memory to another stream while the kernels may still use it."""
+    @functools.wraps(fn)
+    def wrap(*args, stream=None, **kw):
+        ctx = torch.cuda.stream(stream) if stream is not None else contextlib.nullcontext()
+        with ctx:
+            return fn(*args, stream=stream, **kw)
+    return wrap
+
+
 def _ptr(t):
     return ctypes.c_void_p(t.data_ptr()) if t is not None else None
 
@@ -232,11 +247,13 @@ _WORKSPACE = {}
 
 
 def workspace(grid: Grid, n_landmarks: int, prec: int, device) -> torch.Tensor | None:
-    """Scratch for the spatially sorted build (cached per device, grown on demand)."""
+    """Scratch for the spatially sorted build: one buffer per (device, current
+    stream), grown on demand.  Builds enqueued on one stream run in order, so
+    they can share it; builds on different streams get different buffers."""
     nbytes = int(lib().fif_workspace_bytes(ctypes.byref(grid.c()), int(n_landmarks), prec))
     if nbytes == 0:
         return None
-    key = str(device)
+    key = (str(device), torch.cuda.current_stream(device).cuda_stream)
     ws = _WORKSPACE.get(key)
     if ws is None or ws.numel() < nbytes:
         ws = torch.empty(nbytes, dtype=torch.uint8, device=device)
@@ -244,6 +261,7 @@ def workspace(grid: Grid, n_landmarks: int, prec: int, device) -> torch.Tensor |
     return ws
 
 
+@_on_stream
 def build(landmarks: torch.Tensor, grid: Grid, vis: Vis, prec: int = FP32_COMP,
           kind: int = KIND_INFO, field: Field | None = None, sort: bool = True,
           stream=None) -> Field:
@@ -259,6 +277,7 @@ def build(landmarks: torch.Tensor, grid: Grid, vis: Vis, prec: int = FP32_COMP,
     return field
 
 
+@_on_stream
 def update(field: Field, landmarks: torch.Tensor, sign: int, stream=None) -> Field:
     lm = _dev(landmarks, torch.float64, "landmarks", 3)
     _check(lib().fif_update(_ptr(lm), lm.shape[0], int(sign), ctypes.byref(field.cstruct),
@@ -266,6 +285,7 @@ def update(field: Field, landmarks: torch.Tensor, sign: int, stream=None) -> Fie
     return field
 
 
+@_on_stream
 def query(field: Field, t: torch.Tensor, q: torch.Tensor, metrics: int = TRACE | LMIN | LOGDET,
           interp: int = TRILINEAR, out: torch.Tensor | None = None,
           flags: torch.Tensor | None = None, want_flags: bool = False, stream=None):
@@ -284,6 +304,7 @@ def query(field: Field, t: torch.Tensor, q: torch.Tensor, metrics: int = TRACE |
     return (out, flags) if want_flags else out
 
 
+@_on_stream
 def query_grad(field: Field, t: torch.Tensor, q: torch.Tensor, metrics: int,
                dL_dout: torch.Tensor, want_out: bool = False, stream=None):
     dt = field.pose_dtype
@@ -301,6 +322,7 @@ def query_grad(field: Field, t: torch.Tensor, q: torch.Tensor, metrics: int,
     return (gt, gphi, out) if want_out else (gt, gphi)
 
 
+@_on_stream
 def view_sweep(field: Field, t: torch.Tensor, dirs: torch.Tensor, metric: int = LOGDET,
                interp: int = TRILINEAR, want_values: bool = True, stream=None):
     """Metric of every candidate optical axis (dirs [n_dir, 3], float64) at every
@@ -318,6 +340,7 @@ def view_sweep(field: Field, t: torch.Tensor, dirs: torch.Tensor, metric: int = 
     return values, best
 
 
+@_on_stream
 def pc_query(landmarks: torch.Tensor, vis: Vis, t: torch.Tensor, q: torch.Tensor,
              metrics: int = TRACE | LMIN | LOGDET, prec: int = FP32_COMP, pinhole=None,
              out: torch.Tensor | None = None, stream=None):
@@ -337,6 +360,7 @@ def pc_query(landmarks: torch.Tensor, vis: Vis, t: torch.Tensor, q: torch.Tensor
     return out
 
 
+@_on_stream
 def export_blocks(field: Field, voxel_ids: torch.Tensor, stream=None) -> torch.Tensor:
     ids = _dev(voxel_ids, torch.int64, "voxel_ids")
     n = ids.numel()
@@ -367,11 +391,13 @@ class GPModel:
         return CGP(self.n_s, 0, self.k_s, float(self.length or 0.0), self.noise,
                    self.axes.data_ptr(), self.kinv.data_ptr())
 
+    @_on_stream
     def set_length(self, length: float, stream=None) -> "GPModel":
         self.length = float(length)
         _check(lib().fif_gp_setup(ctypes.byref(self.c()), _stream(stream)), "fif_gp_setup")
         return self
 
+    @_on_stream
     def evidence(self, half_fov: float, train_u: torch.Tensor, lengths: torch.Tensor,
                  stream=None) -> torch.Tensor:
         u = _dev(train_u, torch.float64, "train_u", 3)
@@ -429,6 +455,7 @@ class GPField:
         return self.buffer.numel()
 
 
+@_on_stream
 def gp_build(landmarks: torch.Tensor, grid: Grid, vis: Vis, model: GPModel,
              prec: int = FP32_COMP, kind: int = KIND_INFO, field: GPField | None = None,
              sort: bool = True, stream=None) -> GPField:
@@ -442,6 +469,7 @@ def gp_build(landmarks: torch.Tensor, grid: Grid, vis: Vis, model: GPModel,
     return field
 
 
+@_on_stream
 def gp_query(field: GPField, t: torch.Tensor, q: torch.Tensor,
              metrics: int = TRACE | LMIN | LOGDET, interp: int = TRILINEAR,
              out: torch.Tensor | None = None, want_flags: bool = False, stream=None):
@@ -460,6 +488,7 @@ def gp_query(field: GPField, t: torch.Tensor, q: torch.Tensor,
     return (out, flags) if want_flags else out
 
 
+@_on_stream
 def gp_export(field: GPField, voxel_ids: torch.Tensor, stream=None) -> torch.Tensor:
     ids = _dev(voxel_ids, torch.int64, "voxel_ids")
     n, ns = ids.numel(), field.model.n_s
