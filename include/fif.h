@@ -17,6 +17,12 @@
  *   fif_last_error() (thread-local) holds the HIP message.  Nothing throws
  *   across the ABI.  NaN inputs give NaN outputs, not errors.
  *
+ * Sizes
+ *   Pose counts, landmark counts and voxel-id counts may be up to 2^40, sweep
+ *   positions up to 2^31 - 1 (FIF_EINVAL beyond).  A call whose input is
+ *   longer than one dispatch can cover (2^30 work-items) is split into several
+ *   launches on the same stream; the results are the same as in one launch.
+ *
  * Conventions
  *   Pose T_wc = {R_wc, t}: t is the camera position in the world, R_wc = R(q)
  *   with q = (w, x, y, z) Hamilton (need not be unit: the library normalises).

@@ -270,6 +270,8 @@ fif_status pc_query(const double* landmarks, int64_t n_landmarks, const fif_vis*
   if (!vis_ok(vis)) return fail(FIF_EINVAL, "invalid visibility parameters%s");
   if (!prec_ok(prec)) return fail(FIF_EINVAL, "invalid precision%s");
   if (n_landmarks < 0 || m < 0) return fail(FIF_EINVAL, "negative size%s");
+  if (n_landmarks > ((int64_t)1 << 40) || m > ((int64_t)1 << 40))
+    return fail(FIF_EINVAL, "size too large%s");
   if (metrics == 0 || (metrics & ~15u)) return fail(FIF_EINVAL, "invalid metric mask%s");
   if (n_landmarks > 0 && !landmarks) return fail(FIF_EINVAL, "landmarks is NULL%s");
   if (cam && (!(cam->fx > 0) || !(cam->fy > 0) || cam->width < 1 || cam->height < 1))
@@ -305,6 +307,7 @@ fif_status fif_field_export(const fif_field* field, const int64_t* voxel_ids, in
   fif_status st = check_field(field);
   if (st != FIF_OK) return st;
   if (n < 0) return fail(FIF_EINVAL, "n < 0%s");
+  if (n > ((int64_t)1 << 40)) return fail(FIF_EINVAL, "n too large%s");
   if (n == 0) return FIF_OK;
   if (!voxel_ids || !blocks) return fail(FIF_EINVAL, "voxel_ids or blocks is NULL%s");
   fif::ExportArgs a;
@@ -458,7 +461,7 @@ fif_status fif_gp_export(const fif_gp_field* field, const int64_t* voxel_ids, in
   if (n == 0) return FIF_OK;
   if (!voxel_ids || !blocks) return fail(FIF_EINVAL, "voxel_ids or blocks is NULL%s");
   if (!aligned(voxel_ids, 8) || !aligned(blocks, 8)) return fail(FIF_EINVAL, "misaligned buffer%s");
-  if (n > ((int64_t)1 << 31) / FIF_GP_MAX_NS) return fail(FIF_EINVAL, "n too large%s");
+  if (n > ((int64_t)1 << 40)) return fail(FIF_EINVAL, "n too large%s");
   fif::GPExportArgs a;
   a.field = field->data;
   a.g = grid_dev(&field->grid);

@@ -789,10 +789,16 @@ hipError_t launch_gp_query(const GPQueryArgs& a, int prec, int kind, hipStream_t
     const size_t sb = prec == 2 ? 8 : 4;
     const int nt = ((size_t)a.gp.ns * 256 * sb <= 80 * 1024) ? 256 : 64;
     const size_t lds = (size_t)a.gp.ns * nt * sb;
-    dim3 tgrid((unsigned)((a.q.m + nt - 1) / nt)), tblock(nt);
-    if (prec == 2) hipLaunchKernelGGL((gp_query_trace_kernel<double>), tgrid, tblock, lds, stream, a);
-    else hipLaunchKernelGGL((gp_query_trace_kernel<float>), tgrid, tblock, lds, stream, a);
-    return hipGetLastError();
+    for (int64_t off = 0; off < a.q.m; off += kMaxLaunchItems) {
+      GPQueryArgs p = a;
+      p.q = query_part(a.q, off, std::min(kMaxLaunchItems, a.q.m - off), sb);
+      dim3 tgrid((unsigned)((p.q.m + nt - 1) / nt)), tblock(nt);
+      if (prec == 2) hipLaunchKernelGGL((gp_query_trace_kernel<double>), tgrid, tblock, lds, stream, p);
+      else hipLaunchKernelGGL((gp_query_trace_kernel<float>), tgrid, tblock, lds, stream, p);
+      const hipError_t e = hipGetLastError();
+      if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
   }
   if (prec == 2) hipLaunchKernelGGL((gp_query_kernel<double, 0>), grid, block, 0, stream, a);
   else hipLaunchKernelGGL((gp_query_kernel<float, 0>), grid, block, 0, stream, a);
@@ -800,17 +806,26 @@ hipError_t launch_gp_query(const GPQueryArgs& a, int prec, int kind, hipStream_t
 }
 
 hipError_t launch_gp_export(const GPExportArgs& a, int prec, int kind, hipStream_t stream) {
-  const int64_t total = a.n * a.gp.ns;
-  if (total <= 0) return hipSuccess;
-  dim3 grid((unsigned)((total + 127) / 128)), block(128);
-  if (prec == 2) {
-    if (kind == 0) hipLaunchKernelGGL((gp_export_kernel<double, 0>), grid, block, 0, stream, a);
-    else hipLaunchKernelGGL((gp_export_kernel<double, 1>), grid, block, 0, stream, a);
-  } else {
-    if (kind == 0) hipLaunchKernelGGL((gp_export_kernel<float, 0>), grid, block, 0, stream, a);
-    else hipLaunchKernelGGL((gp_export_kernel<float, 1>), grid, block, 0, stream, a);
+  if (a.n <= 0 || a.gp.ns <= 0) return hipSuccess;
+  const int64_t per = kMaxLaunchItems / a.gp.ns;  // voxel ids per launch
+  for (int64_t off = 0; off < a.n; off += per) {
+    GPExportArgs p = a;
+    p.n = std::min(per, a.n - off);
+    p.ids = a.ids + off;
+    p.out = a.out + (size_t)off * a.gp.ns * (kind == 0 ? 21 : 1);
+    const int64_t total = p.n * a.gp.ns;
+    dim3 grid((unsigned)((total + 127) / 128)), block(128);
+    if (prec == 2) {
+      if (kind == 0) hipLaunchKernelGGL((gp_export_kernel<double, 0>), grid, block, 0, stream, p);
+      else hipLaunchKernelGGL((gp_export_kernel<double, 1>), grid, block, 0, stream, p);
+    } else {
+      if (kind == 0) hipLaunchKernelGGL((gp_export_kernel<float, 0>), grid, block, 0, stream, p);
+      else hipLaunchKernelGGL((gp_export_kernel<float, 1>), grid, block, 0, stream, p);
+    }
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
   }
-  return hipGetLastError();
+  return hipSuccess;
 }
 
 }  // namespace fif

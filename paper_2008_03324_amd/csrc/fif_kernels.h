@@ -5,6 +5,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <algorithm>
+
 #include "fif_device.h"
 
 namespace fif {
@@ -126,6 +128,27 @@ struct GPExportArgs {
   int64_t n;
   double* out;
 };
+
+// Items (lanes) per launch of the kernels that give every pose, voxel id or
+// position its own lane(s): a dispatch holds its grid size in work-items as a
+// 32-bit number, so the launchers split longer inputs into launches of at
+// most this many work-items, each on a slice of the arrays.
+constexpr int64_t kMaxLaunchItems = int64_t(1) << 30;
+
+// Poses [off, off + n) of a query: the pose, output, flag and gradient arrays
+// advanced by off rows (sb = bytes of one pose scalar).
+inline QueryArgs query_part(const QueryArgs& a, int64_t off, int64_t n, size_t sb) {
+  QueryArgs p = a;
+  p.t = static_cast<const char*>(a.t) + (size_t)off * 3 * sb;
+  p.q = static_cast<const char*>(a.q) + (size_t)off * 4 * sb;
+  p.m = n;
+  if (a.out) p.out = a.out + (size_t)off * a.ncols;
+  if (a.flags) p.flags = a.flags + off;
+  if (a.dL_dout) p.dL_dout = a.dL_dout + (size_t)off * a.ncols;
+  if (a.dL_dt) p.dL_dt = static_cast<char*>(a.dL_dt) + (size_t)off * 3 * sb;
+  if (a.dL_dphi) p.dL_dphi = static_cast<char*>(a.dL_dphi) + (size_t)off * 3 * sb;
+  return p;
+}
 
 hipError_t launch_build(const BuildArgs& a, int prec, int kind, hipStream_t stream);
 hipError_t launch_gp_setup(const GPDev& gp, double* kinv, hipStream_t stream);

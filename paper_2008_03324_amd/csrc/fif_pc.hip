@@ -152,19 +152,29 @@ __global__ __launch_bounds__(kPcThreads) void pc_kernel(PcArgs a) {
 
 hipError_t launch_pc(const PcArgs& a, int prec, hipStream_t stream) {
   if (a.m <= 0) return hipSuccess;
-  dim3 grid((unsigned)((a.m + kPcThreads - 1) / kPcThreads)), block(kPcThreads);
-#define FIF_PC(P, E) hipLaunchKernelGGL((pc_kernel<P, E>), grid, block, 0, stream, a)
-  if (a.exact) {
-    if (prec == 0) FIF_PC(0, true);
-    else if (prec == 1) FIF_PC(1, true);
-    else FIF_PC(2, true);
-  } else {
-    if (prec == 0) FIF_PC(0, false);
-    else if (prec == 1) FIF_PC(1, false);
-    else FIF_PC(2, false);
-  }
+  const size_t sb = prec == 2 ? 8 : 4;
+  for (int64_t off = 0; off < a.m; off += kMaxLaunchItems) {
+    PcArgs p = a;
+    p.m = std::min(kMaxLaunchItems, a.m - off);
+    p.t = static_cast<const char*>(a.t) + (size_t)off * 3 * sb;
+    p.q = static_cast<const char*>(a.q) + (size_t)off * 4 * sb;
+    p.out = a.out + (size_t)off * a.ncols;
+    dim3 grid((unsigned)((p.m + kPcThreads - 1) / kPcThreads)), block(kPcThreads);
+#define FIF_PC(P, E) hipLaunchKernelGGL((pc_kernel<P, E>), grid, block, 0, stream, p)
+    if (a.exact) {
+      if (prec == 0) FIF_PC(0, true);
+      else if (prec == 1) FIF_PC(1, true);
+      else FIF_PC(2, true);
+    } else {
+      if (prec == 0) FIF_PC(0, false);
+      else if (prec == 1) FIF_PC(1, false);
+      else FIF_PC(2, false);
+    }
 #undef FIF_PC
-  return hipGetLastError();
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 
 }  // namespace fif

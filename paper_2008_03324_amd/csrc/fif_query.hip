@@ -547,10 +547,21 @@ __global__ __launch_bounds__(kSweepThreads) void view_sweep_kernel(SweepArgs a) 
 
 hipError_t launch_sweep(const SweepArgs& a, int prec, hipStream_t stream) {
   if (a.n_pos <= 0) return hipSuccess;
-  dim3 grid((unsigned)a.n_pos), block(kSweepThreads);
-  if (prec == 2) hipLaunchKernelGGL((view_sweep_kernel<double>), grid, block, 0, stream, a);
-  else hipLaunchKernelGGL((view_sweep_kernel<float>), grid, block, 0, stream, a);
-  return hipGetLastError();
+  const int64_t per = kMaxLaunchItems / kSweepThreads;  // positions per launch
+  const size_t sb = prec == 2 ? 8 : 4;
+  for (int64_t off = 0; off < a.n_pos; off += per) {
+    SweepArgs p = a;
+    p.n_pos = std::min(per, a.n_pos - off);
+    p.t = static_cast<const char*>(a.t) + (size_t)off * 3 * sb;
+    if (a.values) p.values = a.values + (size_t)off * a.n_dir;
+    if (a.best) p.best = a.best + off;
+    dim3 grid((unsigned)p.n_pos), block(kSweepThreads);
+    if (prec == 2) hipLaunchKernelGGL((view_sweep_kernel<double>), grid, block, 0, stream, p);
+    else hipLaunchKernelGGL((view_sweep_kernel<float>), grid, block, 0, stream, p);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 
 template <typename FT>
@@ -582,42 +593,54 @@ static int64_t pipe_blocks() {
 hipError_t launch_query(const QueryArgs& a, int prec, int kind, bool grad, hipStream_t stream) {
   if (a.m <= 0) return hipSuccess;
   const bool dbl = (prec == 2);
-  if (kind == 0) {
-    dim3 grid((unsigned)((a.m + kQThreads - 1) / kQThreads));
-    if (grad) {
-      if (dbl) hipLaunchKernelGGL((query_info_kernel<double, true>), grid, dim3(kQThreads), 0, stream, a);
-      else hipLaunchKernelGGL((query_info_kernel<float, true>), grid, dim3(kQThreads), 0, stream, a);
-    } else {
-      if (dbl) {
-        hipLaunchKernelGGL((query_info_kernel<double, false>), grid, dim3(kQThreads), 0, stream, a);
-      } else {
-        const int64_t nbatch = (a.m + 63) / 64;
-        const int64_t want = (nbatch + kPipeWaves - 1) / kPipeWaves;
-        const int64_t cap = pipe_blocks();
-        dim3 pgrid((unsigned)(want < cap ? want : cap));
-        hipLaunchKernelGGL(query_info_pipe_kernel, pgrid, dim3(kQThreads), 0, stream, a, nbatch);
-      }
-    }
-  } else {
-    dim3 grid((unsigned)((a.m + kQThreads - 1) / kQThreads));
-    if (dbl) hipLaunchKernelGGL((query_trace_kernel<double>), grid, dim3(kQThreads), 0, stream, a);
-    else hipLaunchKernelGGL((query_trace_kernel<float>), grid, dim3(kQThreads), 0, stream, a);
+  if (kind == 0 && !grad && !dbl) {  // persistent: any m in one launch
+    const int64_t nbatch = (a.m + 63) / 64;
+    const int64_t want = (nbatch + kPipeWaves - 1) / kPipeWaves;
+    const int64_t cap = pipe_blocks();
+    dim3 pgrid((unsigned)(want < cap ? want : cap));
+    hipLaunchKernelGGL(query_info_pipe_kernel, pgrid, dim3(kQThreads), 0, stream, a, nbatch);
+    return hipGetLastError();
   }
-  return hipGetLastError();
+  for (int64_t off = 0; off < a.m; off += kMaxLaunchItems) {
+    const QueryArgs p = query_part(a, off, std::min(kMaxLaunchItems, a.m - off), dbl ? 8 : 4);
+    dim3 grid((unsigned)((p.m + kQThreads - 1) / kQThreads));
+    if (kind == 0) {
+      if (grad) {
+        if (dbl) hipLaunchKernelGGL((query_info_kernel<double, true>), grid, dim3(kQThreads), 0, stream, p);
+        else hipLaunchKernelGGL((query_info_kernel<float, true>), grid, dim3(kQThreads), 0, stream, p);
+      } else {
+        hipLaunchKernelGGL((query_info_kernel<double, false>), grid, dim3(kQThreads), 0, stream, p);
+      }
+    } else {
+      if (dbl) hipLaunchKernelGGL((query_trace_kernel<double>), grid, dim3(kQThreads), 0, stream, p);
+      else hipLaunchKernelGGL((query_trace_kernel<float>), grid, dim3(kQThreads), 0, stream, p);
+    }
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 
 hipError_t launch_export(const ExportArgs& a, int prec, int kind, hipStream_t stream) {
   if (a.n <= 0) return hipSuccess;
-  dim3 grid((unsigned)((a.n + 127) / 128)), block(128);
   const bool dbl = (prec == 2);
-  if (kind == 0) {
-    if (dbl) hipLaunchKernelGGL((export_info_kernel<double>), grid, block, 0, stream, a);
-    else hipLaunchKernelGGL((export_info_kernel<float>), grid, block, 0, stream, a);
-  } else {
-    if (dbl) hipLaunchKernelGGL((export_trace_kernel<double>), grid, block, 0, stream, a);
-    else hipLaunchKernelGGL((export_trace_kernel<float>), grid, block, 0, stream, a);
+  for (int64_t off = 0; off < a.n; off += kMaxLaunchItems) {
+    ExportArgs p = a;
+    p.n = std::min(kMaxLaunchItems, a.n - off);
+    p.ids = a.ids + off;
+    p.out = a.out + (size_t)off * (kind == 0 ? 210 : 10);
+    dim3 grid((unsigned)((p.n + 127) / 128)), block(128);
+    if (kind == 0) {
+      if (dbl) hipLaunchKernelGGL((export_info_kernel<double>), grid, block, 0, stream, p);
+      else hipLaunchKernelGGL((export_info_kernel<float>), grid, block, 0, stream, p);
+    } else {
+      if (dbl) hipLaunchKernelGGL((export_trace_kernel<double>), grid, block, 0, stream, p);
+      else hipLaunchKernelGGL((export_trace_kernel<float>), grid, block, 0, stream, p);
+    }
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
   }
-  return hipGetLastError();
+  return hipSuccess;
 }
 
 }  // namespace fif
