@@ -22,6 +22,9 @@
  *   positions up to 2^31 - 1 (FIF_EINVAL beyond).  A call whose input is
  *   longer than one dispatch can cover (2^30 work-items) is split into several
  *   launches on the same stream; the results are the same as in one launch.
+ *   fif_build and fif_update take one launch per call and return
+ *   FIF_EUNSUPPORTED for grids with nx > 134,217,720, ny > 524,280 or
+ *   nz > 262,140.
  *
  * Conventions
  *   Pose T_wc = {R_wc, t}: t is the camera position in the world, R_wc = R(q)

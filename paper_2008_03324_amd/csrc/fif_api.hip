@@ -159,7 +159,10 @@ static fif_status build_common(const double* landmarks, int64_t n_landmarks, fif
   if (n_landmarks > 0 && !landmarks) return fail(FIF_EINVAL, "landmarks is NULL%s");
   if (landmarks && !aligned(landmarks, 8)) return fail(FIF_EINVAL, "landmarks must be 8-byte aligned%s");
   if (n_landmarks > ((int64_t)1 << 40)) return fail(FIF_EINVAL, "too many landmarks%s");
-  if ((field->grid.ny + 7) / 8 > 65535 || (field->grid.nz + 3) / 4 > 65535)
+  // one workgroup of 256 lanes per 8x8x4 tile; a dispatch holds fewer than
+  // 2^32 work-items along x and 2^16 workgroups along y and z
+  if ((int64_t)((field->grid.nx + 7) / 8) * 256 >= ((int64_t)1 << 32) ||
+      (field->grid.ny + 7) / 8 > 65535 || (field->grid.nz + 3) / 4 > 65535)
     return fail(FIF_EUNSUPPORTED, "grid too large for one build launch%s");
   fif::BuildArgs a;
   a.lm = landmarks;

@@ -103,6 +103,12 @@ def test_host_side_validation_returns_einval():
     gb.reserved = 1
     fb = fif.CField(gb, vis.c(), fif.FP64, fif.KIND_INFO, 4096)
     assert L.fif_query(ctypes.byref(fb), None, None, 1, 1, 0, None, None, None) == -1
+    # grids one build launch cannot cover: unsupported, refused before any launch
+    for shape in ((1 << 28, 1, 1), (1, 600_000, 1), (1, 1, 300_000)):
+        fw = fif.CField(fif.Grid((0.0, 0.0, 0.0), 0.5, shape).c(), vis.c(), fif.FP32_COMP,
+                        fif.KIND_INFO, 4096)
+        assert L.fif_build(None, 0, ctypes.byref(fw), None, 0, None) == -4, shape
+        assert L.fif_update(None, 5, 1, ctypes.byref(fw), None) == -1  # NULL landmarks
 
 
 def test_binding_fails_loudly_without_library(tmp_path, monkeypatch):
