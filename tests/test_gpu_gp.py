@@ -234,3 +234,55 @@ def test_gp_edge_cases(fif, model30, tiny30):
         fif.gp_query(ft, _cuda(tiny30["t"][:4]), _cuda(tiny30["q"][:4]), fif.LMIN)
     with pytest.raises(ValueError):
         fif.GPField(grid, vis, fif.GPModel(_cuda(scenes.sphere_axes(200)), KS, None), fif.FP64)
+
+
+@pytest.mark.parametrize("ns", [150, 160])
+def test_gp_large_ns_matches_oracle(fif, ns):
+    """N_s past 80 (the inverse read from global memory in the information query,
+    the trace query's 64-lane workgroups, two build passes), up to the maximum
+    N_s = 160: FP64 factors and queries, and an FP32-compensated field.  The
+    lengths are near the ML-II ones, where cond(K^s + noise I) is about 4.5e5;
+    the FP64 bar of 1e-9 allows the weight product's cancellation at that
+    conditioning (at N_s = 160 and l = 0.45, cond 1e6, both sides differ from
+    exact by ~1e-9)."""
+    print(f"case: GP tiny scene N_s={ns}", flush=True)
+    lm, g, v = scenes.tiny_scene(n_landmarks=400)
+    Z = scenes.sphere_axes(ns)
+    length = {150: 0.45, 160: 0.43}[ns]
+    A = oracle.gp_inverse(Z, length, NOISE)
+    model = fif.GPModel(_cuda(Z), KS, length, NOISE)
+    grid, vis = _gv(fif, g, v)
+    rng = np.random.default_rng(191 + ns)
+    ids = np.sort(rng.choice(grid.n_voxels, 64, replace=False))
+    CI = oracle.gp_build(lm, g.origin, g.h, g.shape, v.sigma, Z, KS, v.half_fov, A)
+    CT = oracle.gp_build(lm, g.origin, g.h, g.shape, v.sigma, Z, KS, v.half_fov, A, trace=True)
+    fi = fif.gp_build(_cuda(lm), grid, vis, model, prec=fif.FP64)
+    ft = fif.gp_build(_cuda(lm), grid, vis, model, prec=fif.FP64, kind=fif.KIND_TRACE)
+    idt = torch.from_numpy(ids).cuda()
+    assert _block_err(fif.gp_export(fi, idt).cpu().numpy(), upper21(CI[ids])).max() <= 1e-9
+    assert _block_err(fif.gp_export(ft, idt).cpu().numpy(), CT[ids]).max() <= 1e-9
+    t, q = scenes.tiny_poses(g, 192, seed=2300 + ns)
+    ofi = oracle.GPField(CI, g.origin, g.h, g.shape, Z, length)
+    oft = oracle.GPField(CT, g.origin, g.h, g.shape, Z, length, trace=True)
+    for interp in (0, 1):
+        out = fif.gp_query(fi, _cuda(t), _cuda(q), M7 | 8, interp=interp).cpu().numpy()
+        ref, _ = oracle.gp_query(ofi, t, q, M7 | 8, interp)
+        err = metric_errors(out[:, :3], ref[:, :3], ref[:, 3:])
+        print(ns, interp, {k: float(np.nanmax(e)) for k, e in err.items()})
+        assert err["trace_rel"].max() <= 1e-9
+        assert err["lmin_weyl"].max() <= 1e-9
+        assert np.nanmax(err["logdet_abs"]) <= 1e-7
+        tr = fif.gp_query(ft, _cuda(t), _cuda(q), fif.TRACE, interp=interp).cpu().numpy()
+        refT, _ = oracle.gp_query(oft, t, q, 1, interp)
+        assert (np.abs(tr[:, 0] - refT[:, 0]) / np.abs(refT[:, 0])).max() <= 1e-9
+    # FP32 compensated field against the oracle at the FP32-rounded poses
+    f32 = fif.gp_build(_cuda(lm), grid, vis, model, prec=fif.FP32_COMP)
+    t32, q32 = t.astype(np.float32), q.astype(np.float32)
+    out = fif.gp_query(f32, _cuda(t32, torch.float32), _cuda(q32, torch.float32), M7).cpu().numpy()
+    ref, _, F = oracle.gp_query(ofi, t32.astype(np.float64), q32.astype(np.float64), M7, 0,
+                                want_fim=True)
+    err = metric_errors(out, ref, upper21(F))
+    print(ns, "FP32_COMP", {k: float(np.nanmax(e)) for k, e in err.items()})
+    assert err["trace_rel"].max() <= 1e-3
+    assert err["lmin_weyl"].max() <= 1e-3
+    assert np.nanmax(err["logdet_abs"]) <= 1e-3
