@@ -107,6 +107,37 @@ def test_point_cloud_sampled_vs_oracle(fif, bld):
     assert e_fim(out[:, 3:], ref[:, 3:]).max() <= 1e-4
 
 
+def test_exact_point_cloud_sampled_vs_oracle(fif, bld):
+    """Pinhole visibility (600 x 600 px, f = 300) at the building scale: FP64
+    and FP32-compensated sums against the oracle on sampled poses.  A landmark
+    within the margin of an image border may fall on either side in the other
+    precision; those poses are left out (the oracle reports the margin), and so
+    are poses whose camera sees no landmark (F = 0 exactly on both sides)."""
+    print("case: building scene, exact point cloud", flush=True)
+    rng = np.random.default_rng(29)
+    pick = rng.choice(bld["t"].shape[0], 96, replace=False)
+    t64 = bld["t"][pick].astype(np.float64)
+    q64 = bld["q"][pick].astype(np.float64)
+    v = bld["v"]
+    ref, margin = oracle.pc_query(bld["lm"], v.half_fov, v.v_alpha, v.sigma, v.r_min, v.r_max,
+                                  t64, q64, M7 | 8, pinhole=scenes.PINHOLE, want_margin=True)
+    for prec, dt, tol, edge in ((fif.FP64, torch.float64, 1e-9, 1e-6),
+                                (fif.FP32_COMP, torch.float32, 1e-4, 1e-2)):
+        out = fif.pc_query(bld["lm_d"], bld["vis"], torch.from_numpy(t64).to("cuda", dt),
+                           torch.from_numpy(q64).to("cuda", dt), M7 | 8, prec=prec,
+                           pinhole=scenes.PINHOLE).cpu().numpy()
+        # a camera that sees no landmark has F = 0 on both sides
+        seen = np.abs(ref[:, 3:]).max(axis=1) > 0
+        assert np.all(out[~seen, 3:] == 0)
+        ok = (margin > edge) & seen
+        print(prec, "poses kept", int(ok.sum()), "of", len(ok), "blind", int((~seen).sum()))
+        assert ok.sum() >= 24
+        err = e_fim(out[ok, 3:], ref[ok, 3:])
+        print(prec, "exact pc e_FIM max", err.max())
+        assert err.max() <= tol
+        assert metric_errors(out[ok, :3], ref[ok, :3], ref[ok, 3:])["trace_rel"].max() <= tol
+
+
 def test_nearest_queries_sampled(fif, bld):
     rng = np.random.default_rng(24)
     pick = rng.choice(bld["t"].shape[0], 256, replace=False)
