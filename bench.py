@@ -57,6 +57,8 @@ def parse():
     ap.add_argument("--no-serve", action="store_true", help="skip the serving leg")
     ap.add_argument("--no-sweep", action="store_true", help="skip the optimal-view sweep leg")
     ap.add_argument("--no-gp", action="store_true", help="skip the GP visibility leg")
+    ap.add_argument("--no-precision", action="store_true",
+                    help="skip the precision sweep (1M landmarks, three field precisions)")
     ap.add_argument("--serve-seconds", type=float, default=2.0,
                     help="length of each Poisson stream of the serving leg")
     return ap.parse_args()
@@ -304,6 +306,9 @@ def main():
     if not args.no_gp:
         res["gp"] = gp_leg(fif, torch, scenes, lm_d, grid, vis, t_d, q_d, contrib, dev)
 
+    if not args.no_precision:
+        res["precision_sweep"] = precision_leg(fif, torch, scenes, t_d, q_d, dev)
+
     if not args.no_serve:
         res["serving"] = serve_leg(args, fif, torch)
         res["p99_ms_at_60pct_load"] = res["serving"]["rates"][1]["batched"]["p99_ms"]
@@ -366,6 +371,65 @@ def gp_leg(fif, torch, scenes, lm_d, grid, vis, t_d, q_d, contrib, dev, ns=70, m
             "query_poses": m, "query_info_ms": q_info, "query_trace_ms": q_tr,
             "query_info_per_s": m / (q_info / 1e3), "query_bytes_per_pose": qbytes,
             "query_info_gbs": gbs, "query_info_hbm_frac": gbs / HBM_PEAK_GBS}
+
+
+def precision_leg(fif, torch, scenes, t_d, q_d, dev, n_landmarks=1_000_000, n_ids=4096,
+                  m=100_000, reps=2):
+    """Precision sweep: the building scene at 1M landmarks built as FP64, FP32
+    compensated and FP32 naive fields.  Per variant: build time and contributing
+    pairs/s; for the FP32 variants, their error against the FP64 build (itself
+    held to the oracle by the tests): per-voxel block error |dC|_F / |C|_F on
+    sampled voxels, and metric errors on the first 100k building poses."""
+    lm, g, v = scenes.building_scene(n_landmarks=n_landmarks)
+    grid = fif.Grid(g.origin, g.h, g.shape)
+    vis = fif.Vis(v.half_fov, v.v_alpha, v.sigma, v.r_min, v.r_max)
+    lm_d = torch.tensor(lm, dtype=torch.float64, device=dev)
+    frac = contributing_fraction(torch, lm_d, grid, v.r_max)
+    contrib = frac * grid.n_voxels * n_landmarks
+    gen = torch.Generator(device="cpu").manual_seed(11)
+    ids = torch.randint(0, grid.n_voxels, (n_ids,), generator=gen).to(dev)
+    res = {"landmarks": n_landmarks, "contributing_fraction": frac, "variants": {}}
+    blocks, outs = {}, {}
+    for name, prec in (("FP64", fif.FP64), ("FP32_COMP", fif.FP32_COMP),
+                       ("FP32_NAIVE", fif.FP32_NAIVE)):
+        f = fif.Field(grid, vis, prec, device=dev)
+        fif.build(lm_d, grid, vis, field=f)
+        torch.cuda.synchronize()
+        ms = []
+        for _ in range(reps):
+            a = torch.cuda.Event(enable_timing=True)
+            b = torch.cuda.Event(enable_timing=True)
+            a.record()
+            fif.build(lm_d, grid, vis, field=f)
+            b.record()
+            torch.cuda.synchronize()
+            ms.append(a.elapsed_time(b))
+        med = float(np.median(ms))
+        pdt = f.pose_dtype
+        blocks[name] = fif.export_blocks(f, ids).cpu().numpy()
+        outs[name] = fif.query(f, t_d[:m].to(pdt).contiguous(), q_d[:m].to(pdt).contiguous(),
+                               fif.TRACE | fif.LMIN | fif.LOGDET).cpu().numpy()
+        del f
+        torch.cuda.empty_cache()
+        res["variants"][name] = {"build_ms": med, "pairs_per_s": contrib / (med / 1e3)}
+    w = np.where(np.triu_indices(6)[0] == np.triu_indices(6)[1], 1.0, 2.0)
+    ref, oref = blocks["FP64"], outs["FP64"]
+    nref = np.sqrt((ref ** 2 * w).sum(axis=(1, 2)))
+    for name in ("FP32_COMP", "FP32_NAIVE"):
+        e = np.sqrt(((blocks[name] - ref) ** 2 * w).sum(axis=(1, 2))) / np.maximum(nref, 1e-300)
+        o = outs[name]
+        tr = np.abs(o[:, 0] - oref[:, 0]) / np.abs(oref[:, 0])
+        lm_rel = np.abs(o[:, 1] - oref[:, 1]) / np.abs(oref[:, 1])
+        ld = np.abs(o[:, 2] - oref[:, 2])
+        res["variants"][name].update({
+            "block_err_max": float(e.max()), "block_err_median": float(np.median(e)),
+            "trace_rel_max": float(np.nanmax(tr)), "lmin_rel_median": float(np.nanmedian(lm_rel)),
+            "lmin_rel_max": float(np.nanmax(lm_rel)), "logdet_abs_max": float(np.nanmax(ld))})
+    log("precision sweep (1M landmarks): " + "; ".join(
+        f"{k} {d['build_ms']:.0f} ms {d['pairs_per_s']:.3g} pairs/s"
+        + (f", block err max {d['block_err_max']:.2e}" if "block_err_max" in d else "")
+        for k, d in res["variants"].items()))
+    return res
 
 
 def sweep_leg(fif, torch, scenes, g, field, dev, n_pos=200, n_axes=4096, reps=5):

@@ -149,6 +149,15 @@ __global__ __launch_bounds__(kBuildThreads) void build_kernel(BuildArgs a) {
   const double tz = a.g.oz + (double)iz * a.g.h;
   const float fx = (float)tx, fy = (float)ty, fz = (float)tz;
   const T vx = (T)tx, vy = (T)ty, vz = (T)tz;
+  // Compensated FP32 fields: a landmark closer to the voxel centre than 1 % of
+  // the centre's distance from the origin (or 1 cm) takes its offset d from
+  // the FP64 coordinates.  The difference of the FP32-rounded coordinates is
+  // off by up to ~6e-8 |t_v| in absolute terms, a large relative error in d
+  // when the landmark is that close -- and such a landmark dominates the
+  // voxel's 1/n^2 sums.  Rare, so a divergent branch, and only in landmark
+  // batches whose box comes that near the tile.  (The naive FP32 sums carry
+  // larger rounding errors of their own and skip the test.)
+  const float near2 = 1e-4f * (fx * fx + fy * fy + fz * fz) + 1e-4f;
 
   T acc[NACC];
   float hi[COMP ? NACC : 1], lo[COMP ? NACC : 1];
@@ -161,15 +170,26 @@ __global__ __launch_bounds__(kBuildThreads) void build_kernel(BuildArgs a) {
 
   // workgroup tile bounds (voxel centres, FP32 like the range test)
   float tlo[3], thi[3];
+  float near2_tile = 0.f;  // largest near2 over the tile's voxel centres
   if (a.lm_sorted) {
     const int x0 = blockIdx.x * 8, y0 = blockIdx.y * 8, z0 = blockIdx.z * 4;
     const int x1 = min(x0 + 7, a.g.nx - 1), y1 = min(y0 + 7, a.g.ny - 1), z1 = min(z0 + 3, a.g.nz - 1);
     tlo[0] = (float)(a.g.ox + x0 * a.g.h); thi[0] = (float)(a.g.ox + x1 * a.g.h);
     tlo[1] = (float)(a.g.oy + y0 * a.g.h); thi[1] = (float)(a.g.oy + y1 * a.g.h);
     tlo[2] = (float)(a.g.oz + z0 * a.g.h); thi[2] = (float)(a.g.oz + z1 * a.g.h);
+    float m2 = 0.f;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      const float e = fmaxf(fabsf(tlo[c]), fabsf(thi[c]));
+      m2 = fmaf(e, e, m2);
+    }
+    near2_tile = 1.0001f * (1e-4f * m2 + 1e-4f);
   }
   for (int64_t base = 0; base < a.L; base += kBatch) {
     const int nb = (int)((a.L - base) < kBatch ? (a.L - base) : kBatch);
+    // whether a landmark of this batch can be near a voxel centre of the tile
+    // (workgroup-uniform; without the sorted batches' boxes: always)
+    bool batch_near = true;
     if (a.lm_sorted) {
       // skip a batch whose box is out of range of the whole tile (workgroup-uniform)
       const float* bb = a.batch_box + 8 * (base / kBatch);
@@ -180,6 +200,7 @@ __global__ __launch_bounds__(kBuildThreads) void build_kernel(BuildArgs a) {
         d2 = fmaf(gap, gap, d2);
       }
       if (d2 > a.skip2) continue;
+      batch_near = d2 <= near2_tile;
     }
     __syncthreads();
     if (tid < nb) {
@@ -197,7 +218,10 @@ __global__ __launch_bounds__(kBuildThreads) void build_kernel(BuildArgs a) {
       s_lm[tid] = v;
     }
     __syncthreads();
-    // landmarks in groups of 4: the LDS reads of a group are issued together
+    // landmarks in groups of 4: the LDS reads of a group are issued together;
+    // the loop is instantiated with and without the near-landmark test
+    auto pairs = [&](auto near_test) __attribute__((always_inline)) {
+    constexpr bool NEAR_TEST = decltype(near_test)::value;
     for (int i0 = 0; i0 < nb; i0 += 4) {
       L4 pg[4];
 #pragma unroll
@@ -214,6 +238,20 @@ __global__ __launch_bounds__(kBuildThreads) void build_kernel(BuildArgs a) {
           T nn = (PREC == 2)
                      ? (T)fma((double)dz, (double)dz, fma((double)dy, (double)dy, (double)dx * dx))
                      : (T)n2;
+          if constexpr (COMP && NEAR_TEST) {
+            if (n2 < near2) {
+              const int64_t li = base + i0 + k;
+              double qx, qy, qz;
+              if (a.lm_sorted) {
+                const double4 p4 = a.lm_sorted[li];
+                qx = p4.x; qy = p4.y; qz = p4.z;
+              } else {
+                qx = a.lm[3 * li]; qy = a.lm[3 * li + 1]; qz = a.lm[3 * li + 2];
+              }
+              dx = (T)(qx - tx); dy = (T)(qy - ty); dz = (T)(qz - tz);
+              nn = __fmaf_rn(dz, dz, __fmaf_rn(dy, dy, dx * dx));
+            }
+          }
           T rn = inv_sqrt<T>(nn);
           if constexpr (KIND == 0)
             info_pair<T>(acc, dx, dy, dz, rn);
@@ -221,6 +259,13 @@ __global__ __launch_bounds__(kBuildThreads) void build_kernel(BuildArgs a) {
             trace_pair<T>(acc, dx, dy, dz, rn, p.x, p.y, p.z, p.w);
         }
       }
+    }
+    };
+    if constexpr (COMP) {
+      if (batch_near) pairs(std::true_type{});
+      else pairs(std::false_type{});
+    } else {
+      pairs(std::false_type{});
     }
     if (COMP) {
 #pragma unroll

@@ -46,6 +46,12 @@ __global__ __launch_bounds__(kPcThreads) void pc_kernel(PcArgs a) {
   const T zx = R[2], zy = R[5], zz = R[8];
   const float ftx = (float)t[0], fty = (float)t[1], ftz = (float)t[2];
   const T tx = (T)t[0], ty = (T)t[1], tz = (T)t[2];
+  // Compensated FP32 sums: a landmark closer to the camera than 1 % of the
+  // camera's distance from the origin (or 1 cm) takes its offset from the
+  // FP64 coordinates, as in the compensated field build (the FP32-rounded
+  // landmark is off by up to ~6e-8 |p| in absolute terms).  Rare, so a
+  // divergent branch.
+  const float near2 = 1e-4f * (ftx * ftx + fty * fty + ftz * ftz) + 1e-4f;
   const T k2 = (T)a.vis.k2, k1 = (T)a.vis.k1, k0 = (T)a.vis.k0;
   const T fx = (T)a.fx, fy = (T)a.fy, cx = (T)a.cx, cy = (T)a.cy;
   const T W = (T)a.width, H = (T)a.height;
@@ -98,6 +104,13 @@ __global__ __launch_bounds__(kPcThreads) void pc_kernel(PcArgs a) {
         T dx = p.x - tx, dy = p.y - ty, dz = p.z - tz;
         T nn = (PREC == 2) ? (T)fma((double)dz, (double)dz, fma((double)dy, (double)dy, (double)dx * dx))
                            : (T)__fmaf_rn((float)dz, (float)dz, __fmaf_rn((float)dy, (float)dy, (float)dx * (float)dx));
+        if constexpr (COMP) {
+          if ((float)nn < near2) {
+            const double* lp = a.lm + 3 * (base + s0 + i);
+            dx = (T)(lp[0] - t[0]); dy = (T)(lp[1] - t[1]); dz = (T)(lp[2] - t[2]);
+            nn = __fmaf_rn((float)dz, (float)dz, __fmaf_rn((float)dy, (float)dy, (float)dx * (float)dx));
+          }
+        }
         T rn = (PREC == 2) ? (T)(1.0 / sqrt((double)nn)) : (T)rsqrtf((float)nn);
         T ux = dx * rn, uy = dy * rn, uz = dz * rn;
         T w = T(1);

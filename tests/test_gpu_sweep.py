@@ -32,5 +32,9 @@ def test_precision_sweep_1M_landmarks():
     print({p: (float(e.max()), float(np.median(e))) for p, e in errs.items()})
     assert errs[fif.FP64].max() <= 1e-10
     assert errs[fif.FP32_COMP].max() <= 1e-3
+    # the compensated build takes the offsets of landmarks very close to a voxel
+    # centre from their FP64 coordinates: its worst voxel stays near FP32
+    # rounding (measured 1.1e-6) instead of ~1e-4
+    assert errs[fif.FP32_COMP].max() <= 1e-5
     assert errs[fif.FP32_NAIVE].max() <= 1e-3
     assert np.median(errs[fif.FP32_COMP]) <= np.median(errs[fif.FP32_NAIVE])
