@@ -375,7 +375,7 @@ __global__ __launch_bounds__(kBatch) void gather_box_kernel(const double* lm, in
   for (int c = 0; c < 3; ++c) { s_min[c][threadIdx.x] = mn[c]; s_max[c][threadIdx.x] = mx[c]; }
   __syncthreads();
   for (int stride = kBatch / 2; stride > 0; stride >>= 1) {
-    if (threadIdx.x < stride) {
+    if ((int)threadIdx.x < stride) {
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
         s_min[c][threadIdx.x] = fminf(s_min[c][threadIdx.x], s_min[c][threadIdx.x + stride]);

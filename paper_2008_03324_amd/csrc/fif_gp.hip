@@ -67,10 +67,6 @@ __device__ inline f64x4 mma16(double a, double b, f64x4 c, double* s) {
 }
 
 // Sigmoid visibility (eq:sigmoid_vis_func).
-__device__ inline float sigmoid_vis(float c, float ks, float cos_a) {
-  const float x = ks * (c - cos_a);
-  return __builtin_amdgcn_rcpf(1.0f + __builtin_amdgcn_exp2f(-1.4426950408889634f * x));
-}
 __device__ inline double sigmoid_vis(double c, double ks, double cos_a) {
   return 1.0 / (1.0 + exp(-ks * (c - cos_a)));
 }
@@ -271,7 +267,6 @@ __global__ __launch_bounds__(kGPThreads) void gp_build_kernel(GPBuildArgs a, int
     const double tx = a.g.ox + (double)ix * a.g.h, ty = a.g.oy + (double)iy * a.g.h,
                  tz = a.g.oz + (double)iz * a.g.h;
     const float fx = (float)tx, fy = (float)ty, fz = (float)tz;
-    const T vx = (T)tx, vy = (T)ty, vz = (T)tz;
     A4 acc[NT];
     float hi[COMP ? NT : 1][4], lo[COMP ? NT : 1][4];
 #pragma unroll
@@ -317,10 +312,16 @@ __global__ __launch_bounds__(kGPThreads) void gp_build_kernel(GPBuildArgs a, int
           const float n2 = __fmaf_rn(ddz, ddz, __fmaf_rn(ddy, ddy, ddx * ddx));
           in = (n2 >= a.lo2) && (n2 <= a.hi2);
           if (in) {
-            const T dx = (T)px - vx, dy = (T)py - vy, dz = (T)pz - vz;
+            // the offset from the FP64 coordinates: the FP32-rounded ones are
+            // off by up to ~6e-8 |p| in absolute terms, a large relative error
+            // for a landmark close to the voxel centre (once per listed
+            // landmark, so it costs nothing next to the N_s sigmoids)
+            const T dx = (T)(px - tx), dy = (T)(py - ty), dz = (T)(pz - tz);
             const T nn = (PREC == 2) ? (T)fma((double)dz, (double)dz,
                                               fma((double)dy, (double)dy, (double)dx * dx))
-                                     : (T)n2;
+                                     : (T)__fmaf_rn((float)dz, (float)dz,
+                                                    __fmaf_rn((float)dy, (float)dy,
+                                                              (float)dx * (float)dx));
             const T rn = (PREC == 2) ? (T)(1.0 / sqrt((double)nn)) : (T)rsqrtf((float)nn);
             rec.x = dx * rn; rec.y = dy * rn; rec.z = dz * rn;
             if constexpr (KIND == 0) {
