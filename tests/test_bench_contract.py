@@ -1,0 +1,53 @@
+"""bench.py on the CPU: more than one GPU is refused with a message, and the
+committed rocprofv3 counters are used only while the kernels' sources (their
+code, not their comments) are the ones they were taken from."""
+import json
+import os
+import subprocess
+import sys
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+sys.path.insert(0, ROOT)
+
+import bench  # noqa: E402
+
+
+def test_more_than_one_gpu_is_refused():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2
+    line = json.loads(r.stdout.strip().splitlines()[-1])
+    assert "one GPU" in line["error"]
+
+
+def test_source_hash_ignores_comments_and_whitespace():
+    code = "int f(int a) {\n  return a + 1;  // one more\n}\n"
+    same = "/* header */ int f(int a) { return a + 1; }\n"
+    other = "int f(int a) { return a + 2; }"
+    assert bench._code_only(code) == bench._code_only(same)
+    assert bench._code_only(code) != bench._code_only(other)
+
+
+def test_counters_follow_the_source_hash(tmp_path, monkeypatch):
+    prof = tmp_path / "profiles"
+    prof.mkdir()
+    rec = {"query_src_hash": bench.query_src_hash(),
+           "traffic_GB_per_launch": {"fif::query_info_pipe_kernel": 22.4},
+           "flops": {"fif::build_kernel<1, 0>": {"fp32": 1e13, "src_hash":
+                                                 bench.src_hash(bench.BUILD_SOURCES)}}}
+    (prof / "counters.json").write_text(json.dumps(rec))
+    real_join = os.path.join
+
+    def join(*parts):  # point only the counters file at the temporary copy
+        if len(parts) == 3 and parts[1] == "profiles" and parts[2] == "counters.json":
+            return str(prof / "counters.json")
+        return real_join(*parts)
+
+    monkeypatch.setattr(bench.os.path, "join", join)
+    assert bench.counter_traffic("fif::query_info_pipe_kernel") == 22.4e9
+    assert bench.counter_flops("fif::build_kernel<1, 0>", bench.BUILD_SOURCES)["fp32"] == 1e13
+    rec["query_src_hash"] = "0" * 16
+    rec["flops"]["fif::build_kernel<1, 0>"]["src_hash"] = "0" * 16
+    (prof / "counters.json").write_text(json.dumps(rec))
+    assert bench.counter_traffic("fif::query_info_pipe_kernel") is None
+    assert bench.counter_flops("fif::build_kernel<1, 0>", bench.BUILD_SOURCES) is None
