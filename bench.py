@@ -32,8 +32,9 @@ FP32_PEAK_TFLOPS = 157.3
 RECORD_BYTES_USED = 66 * 4          # moment scalars read per corner (FP32 field)
 POSE_BYTES = 7 * 4                  # t (3) + q (4), float32
 OUT_BYTES_3 = 3 * 8                 # three FP64 metrics
-# FP32 flops of one build pair: 35 monomial products, 25 adds,
-# 41 FMAs (2 flops), 3 (u) + 1 (rn^2) products, d and n^2 (8), 1 rsqrt
+# FP32 flops of one contributing build pair in the moment form: 35 monomial
+# products, 25 adds, 41 FMAs (2 flops), 3 (u) + 1 (rn^2) products, d and n^2
+# (8), 1 rsqrt
 BUILD_FLOPS_CONTRIB = 151
 BUILD_FLOPS_TESTED = 10             # d (3), n^2 (5), two compares
 PC_FLOPS_CONTRIB = 45
@@ -152,8 +153,9 @@ def contributing_fraction(torch, lm_d, grid, r_max, n_sample=32768, seed=7):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; --gpus above 1 is not "
-                                   "supported (see DESIGN.md for how the path would shard)"}))
+        print(json.dumps({"error": "bench.py runs on one GPU; --gpus above 1 is not supported "
+                                   "(the multi-GPU sharding of the build and the queries is "
+                                   "designed, not implemented)"}))
         sys.exit(2)
     import torch
 
