@@ -313,7 +313,9 @@ def main():
 
     if not args.no_serve:
         res["serving"] = serve_leg(args, fif, torch)
-        res["p99_ms_at_60pct_load"] = res["serving"]["rates"][1]["batched"]["p99_ms"]
+        # the library's serving loop (C++), at 60 % of its own saturation rate
+        res["p99_ms_at_60pct_load"] = res["serving"]["native"]["rates"][1]["p99_ms"]
+        res["p99_ms_at_60pct_load_python_loop"] = res["serving"]["rates"][1]["batched"]["p99_ms"]
 
     # ------------------------------------------------ accuracy + CPU baseline
     if not args.no_cpu:
@@ -460,7 +462,8 @@ def sweep_leg(fif, torch, scenes, g, field, dev, n_pos=200, n_axes=4096, reps=5)
 def serve_leg(args, fif, torch):
     """Four resident fields under Poisson streams at 30/60/90 % of the batched
     loop's saturation rate; continuous batching + hipGraphs versus one request
-    per launch (one stream, no graphs, no co-batching)."""
+    per launch (one stream, no graphs, no co-batching); then the same loop in
+    C++ (fif_serve_run) at 30/60/90 % of its own saturation rate."""
     import scenes
     from paper_2008_03324_amd import serve
     dev = torch.device("cuda:0")
@@ -517,9 +520,34 @@ def serve_leg(args, fif, torch):
             f"p99 {entry['batched']['p99_ms']:.2f} ms; one-per-launch p50 "
             f"{entry['one_per_launch']['p50_ms']:.2f} ms p99 {entry['one_per_launch']['p99_ms']:.2f} ms")
         rates.append(entry)
+    # the same loop in C++ (fif_serve_run): saturation, then Poisson streams at
+    # 30/60/90 % of its own saturation rate
+    native = serve.NativeServer(fields, n_streams=4, max_inflight=64, hbm_budget=2 << 30)
+    n_nat = 20_000
+    nat_reqs = make(scenes.request_stream(4, 1e9, n_nat, 262_144, 1024, seed=5001))
+    native.run(nat_reqs, realtime=False)
+    el = native.run(nat_reqs, realtime=False)
+    nat_rate = n_nat / el
+    nat_poses = sum(r.m for r in nat_reqs) / el
+    log(f"serving saturation, native loop: {nat_rate:.0f} req/s ({nat_poses / 1e6:.1f} M poses/s)")
+    nat_rates = []
+    for k, frac in enumerate((0.3, 0.6, 0.9)):
+        rate = frac * nat_rate
+        n = min(60_000, max(200, int(rate * args.serve_seconds)))
+        reqs = make(scenes.request_stream(4, rate, n, 262_144, 1024, seed=7000 + k))
+        el = native.run(reqs, realtime=True)
+        st = serve.latency_stats(reqs)
+        st.update({"load_fraction": frac, "rate_req_per_s": rate, "requests": n,
+                   "throughput_req_per_s": n / el,
+                   "throughput_poses_per_s": sum(r.m for r in reqs) / el})
+        log(f"serving {int(frac * 100)}%, native loop: p50 {st['p50_ms']:.2f} ms "
+            f"p99 {st['p99_ms']:.2f} ms at {n / el:.0f} req/s")
+        nat_rates.append(st)
     return {"fields": [list(f.grid.shape) for f in fields], "field_bytes": hbm,
             "saturation_req_per_s": sat_rate, "saturation_poses_per_s": sat_poses,
-            "one_per_launch_saturation_req_per_s": single_rate, "rates": rates}
+            "one_per_launch_saturation_req_per_s": single_rate, "rates": rates,
+            "native": {"saturation_req_per_s": nat_rate, "saturation_poses_per_s": nat_poses,
+                       "rates": nat_rates}}
 
 
 def cpu_leg(args, fif, torch, lm, g, v, t, q, out, pc_out, metrics):

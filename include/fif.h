@@ -278,6 +278,73 @@ fif_status fif_gp_query(const fif_gp_field* field, const void* t, const void* q,
 fif_status fif_gp_export(const fif_gp_field* field, const int64_t* voxel_ids, int64_t n,
                          double* blocks, void* stream);
 
+/* ------------------------------------------------------------------ serving
+ * Continuous batching over resident fields.  (Not a step of the paper's
+ * method: its planners re-evaluate pose FIMs many times across samples,
+ * iterations and sessions, Sec. I and Sec. VII, which is what a resident field
+ * serves.)  fif_serve_run serves a list of requests on the calling thread:
+ *   - a request is seen at its arrival time (realtime) or at once;
+ *   - requests are admitted in arrival order while fewer than max_inflight
+ *     are in flight and their buffers fit hbm_budget (FIF_SERVE_PLAN:
+ *     m x 24 B, FIF_SERVE_OPT: m x 96 B);
+ *   - admitted requests for the same field and kind are packed into one
+ *     launch (co_batch; up to max_batch poses and FIF_SERVE_MAX_PACK
+ *     requests): one kernel gathers their poses into a stream's batch
+ *     buffers, the query or query + gradient kernels run, one kernel scatters
+ *     the results to the requests' buffers;
+ *   - batches go round-robin over n_streams HIP streams created for the run
+ *     (default priority) and destroyed before it returns;
+ *   - a request is done when the event recorded after its batch is observed
+ *     complete.  admitted and done are written in seconds from the start of
+ *     the run; *elapsed is the run's length.
+ * Each request's results equal those of fif_query (metrics FIF_TRACE |
+ * FIF_LMIN | FIF_LOGDET, trilinear) or fif_query_grad (the same metrics,
+ * dL/dout = 1) on that request alone: a pose's arithmetic does not depend on
+ * the other poses of a launch.  The request buffers must be ready on the
+ * device before the call and stay allocated until it returns; the call
+ * returns after all work has completed.
+ * Errors: FIF_EINVAL (before anything is enqueued) for invalid fields,
+ * requests (field index, kind, m < 1, NULL or misaligned buffers, a request
+ * larger than hbm_budget or max_batch) or configuration; FIF_ENOMEM for a
+ * workspace smaller than fif_serve_workspace_bytes(cfg); FIF_EDEVICE for a
+ * HIP error during the run (the remaining requests keep done = NaN). */
+#define FIF_SERVE_PLAN 0
+#define FIF_SERVE_OPT 1
+#define FIF_SERVE_MAX_PACK 32
+#define FIF_SERVE_MAX_STREAMS 16
+
+typedef struct {
+  double arrival;  /* host: seconds from the start of the run */
+  int32_t field;   /* index into fields[] */
+  int32_t kind;    /* FIF_SERVE_PLAN | FIF_SERVE_OPT */
+  int64_t m;       /* poses, >= 1 */
+  const void* t;   /* device [m][3], float (FP32 fields) or double (FP64) */
+  const void* q;   /* device [m][4], (w, x, y, z) */
+  double* out;     /* device [m][3]: trace, lambda_min, log-det */
+  void* grad_t;    /* device [m][3] (FIF_SERVE_OPT; pose precision) */
+  void* grad_phi;  /* device [m][3] (FIF_SERVE_OPT; left so(3)) */
+  double admitted; /* written by fif_serve_run */
+  double done;     /* written by fif_serve_run */
+} fif_serve_request;
+
+typedef struct {
+  int32_t n_streams;    /* 1 .. FIF_SERVE_MAX_STREAMS */
+  int32_t max_inflight; /* requests in flight, >= 1 */
+  int64_t hbm_budget;   /* bytes of request buffers in flight, >= 1 */
+  int64_t max_batch;    /* poses per launch, 1 .. 2^24 */
+  int32_t co_batch;     /* nonzero: pack requests of one field and kind */
+  int32_t realtime;     /* nonzero: a request is not seen before its arrival */
+} fif_serve_config;
+
+/* Bytes of the device workspace of fif_serve_run (per stream: the batch's
+ * poses, outputs, upstream ones and gradients for max_batch poses); 0 for an
+ * invalid configuration. */
+size_t fif_serve_workspace_bytes(const fif_serve_config* cfg);
+
+fif_status fif_serve_run(const fif_field* fields, int32_t n_fields, fif_serve_request* reqs,
+                         int64_t n_req, const fif_serve_config* cfg, void* workspace,
+                         size_t workspace_bytes, double* elapsed);
+
 /* Static string for a status code. */
 const char* fif_status_string(fif_status status);
 

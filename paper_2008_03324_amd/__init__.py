@@ -71,6 +71,20 @@ class CGPField(ctypes.Structure):
                 ("kind", ctypes.c_int32), ("data", ctypes.c_void_p)]
 
 
+class CServeRequest(ctypes.Structure):
+    _fields_ = [("arrival", ctypes.c_double), ("field", ctypes.c_int32), ("kind", ctypes.c_int32),
+                ("m", ctypes.c_int64), ("t", ctypes.c_void_p), ("q", ctypes.c_void_p),
+                ("out", ctypes.c_void_p), ("grad_t", ctypes.c_void_p),
+                ("grad_phi", ctypes.c_void_p), ("admitted", ctypes.c_double),
+                ("done", ctypes.c_double)]
+
+
+class CServeConfig(ctypes.Structure):
+    _fields_ = [("n_streams", ctypes.c_int32), ("max_inflight", ctypes.c_int32),
+                ("hbm_budget", ctypes.c_int64), ("max_batch", ctypes.c_int64),
+                ("co_batch", ctypes.c_int32), ("realtime", ctypes.c_int32)]
+
+
 EXPORTS = {
     "fif_field_bytes": (ctypes.c_size_t, [ctypes.POINTER(CGrid), ctypes.c_int32, ctypes.c_int32]),
     "fif_workspace_bytes": (ctypes.c_size_t, [ctypes.POINTER(CGrid), ctypes.c_int64, ctypes.c_int32]),
@@ -108,6 +122,11 @@ EXPORTS = {
                                       ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
     "fif_gp_export": (ctypes.c_int32, [ctypes.POINTER(CGPField), ctypes.c_void_p, ctypes.c_int64,
                                        ctypes.c_void_p, ctypes.c_void_p]),
+    "fif_serve_workspace_bytes": (ctypes.c_size_t, [ctypes.POINTER(CServeConfig)]),
+    "fif_serve_run": (ctypes.c_int32, [ctypes.POINTER(CField), ctypes.c_int32,
+                                       ctypes.POINTER(CServeRequest), ctypes.c_int64,
+                                       ctypes.POINTER(CServeConfig), ctypes.c_void_p,
+                                       ctypes.c_size_t, ctypes.POINTER(ctypes.c_double)]),
     "fif_status_string": (ctypes.c_char_p, [ctypes.c_int32]),
     "fif_last_error": (ctypes.c_char_p, []),
 }

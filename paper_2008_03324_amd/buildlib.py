@@ -10,7 +10,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libfif.so")
-SOURCES = ["fif_api.hip", "fif_build.hip", "fif_query.hip", "fif_pc.hip", "fif_gp.hip"]
+SOURCES = ["fif_api.hip", "fif_build.hip", "fif_query.hip", "fif_pc.hip", "fif_gp.hip",
+           "fif_serve.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

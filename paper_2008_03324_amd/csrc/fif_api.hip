@@ -492,3 +492,13 @@ const char* fif_status_string(fif_status s) {
 const char* fif_last_error(void) { return g_last_error.c_str(); }
 
 }  // extern "C"
+
+namespace fif {
+// The thread's fif_last_error() text, set by parts of the library outside
+// this file (the serving loop).
+void set_last_error(const std::string& msg) { g_last_error = msg; }
+}  // namespace fif
+
+extern "C" {
+
+}  // extern "C"

@@ -6,6 +6,7 @@
 #include <stdint.h>
 
 #include <algorithm>
+#include <string>
 
 #include "fif_device.h"
 
@@ -149,6 +150,9 @@ inline QueryArgs query_part(const QueryArgs& a, int64_t off, int64_t n, size_t s
   if (a.dL_dphi) p.dL_dphi = static_cast<char*>(a.dL_dphi) + (size_t)off * 3 * sb;
   return p;
 }
+
+// Sets the calling thread's fif_last_error() text.
+void set_last_error(const std::string& msg);
 
 hipError_t launch_build(const BuildArgs& a, int prec, int kind, hipStream_t stream);
 hipError_t launch_gp_setup(const GPDev& gp, double* kinv, hipStream_t stream);

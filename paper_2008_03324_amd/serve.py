@@ -25,7 +25,10 @@ from collections import deque
 
 import torch
 
-from . import (FP64, LMIN, LOGDET, TRACE, Field, query, query_grad)
+import ctypes
+
+from . import (FP64, LMIN, LOGDET, TRACE, CField, CServeConfig, CServeRequest, Field, _check,
+               lib, query, query_grad)
 
 METRICS = TRACE | LMIN | LOGDET
 
@@ -271,6 +274,54 @@ class Server:
                 time.sleep(idle_sleep)
         torch.cuda.synchronize()
         return now()
+
+
+class NativeServer:
+    """The same loop in libfif (fif_serve_run): admission, packing of requests
+    of one field and kind into a launch (one gather kernel, the query or query
+    + gradient kernels, one scatter kernel), round-robin over HIP streams and
+    completion by events all run in C++ on the calling thread; Python only
+    marshals the request list before and reads the times after."""
+
+    def __init__(self, fields: list[Field], n_streams: int = 4, max_inflight: int = 32,
+                 hbm_budget: int = 4 << 30, max_batch: int = 65536, co_batch: bool = True):
+        self.fields = fields
+        self.cfg = CServeConfig(n_streams, max_inflight, hbm_budget, max_batch, int(co_batch), 1)
+        nbytes = int(lib().fif_serve_workspace_bytes(ctypes.byref(self.cfg)))
+        if nbytes == 0:
+            raise ValueError("invalid serving configuration")
+        dev = fields[0].buffer.device
+        self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=dev)
+        self.cfields = (CField * len(fields))(*[f.cstruct for f in fields])
+
+    def run(self, requests: list[Request], realtime: bool = True) -> float:
+        """Serve the requests; fills out / grad_t / grad_phi, admitted, done and
+        status of each; returns the run's length in seconds."""
+        n = len(requests)
+        arr = (CServeRequest * n)()
+        for i, r in enumerate(requests):
+            f = self.fields[r.field]
+            dt = f.pose_dtype
+            if r.t.dtype != dt or r.q.dtype != dt or not (r.t.is_contiguous() and r.q.is_contiguous()):
+                raise TypeError(f"request {r.rid}: t and q must be contiguous {dt}")
+            r.out = torch.empty((r.m, 3), dtype=torch.float64, device=r.t.device)
+            opt = r.kind == "opt"
+            if opt:
+                r.grad_t = torch.empty((r.m, 3), dtype=dt, device=r.t.device)
+                r.grad_phi = torch.empty((r.m, 3), dtype=dt, device=r.t.device)
+            arr[i] = CServeRequest(r.arrival, r.field, 1 if opt else 0, r.m, r.t.data_ptr(),
+                                   r.q.data_ptr(), r.out.data_ptr(),
+                                   r.grad_t.data_ptr() if opt else None,
+                                   r.grad_phi.data_ptr() if opt else None, 0.0, 0.0)
+        self.cfg.realtime = int(realtime)
+        torch.cuda.synchronize()  # request inputs and outputs allocated and ready
+        elapsed = ctypes.c_double(0.0)
+        _check(lib().fif_serve_run(self.cfields, len(self.fields), arr, n, ctypes.byref(self.cfg),
+                                   ctypes.c_void_p(self.workspace.data_ptr()),
+                                   self.workspace.numel(), ctypes.byref(elapsed)), "fif_serve_run")
+        for i, r in enumerate(requests):
+            r.admitted, r.done, r.status = arr[i].admitted, arr[i].done, "done"
+        return elapsed.value
 
 
 def latency_stats(requests: list[Request]) -> dict:

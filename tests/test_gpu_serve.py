@@ -81,3 +81,64 @@ def test_admission_by_budget(setup):
     tiny = serve.Server(fields, n_streams=1, use_graphs=False, hbm_budget=big - 1)
     with pytest.raises(serve.AdmissionError):
         tiny.run(_make(serve, pools, specs), realtime=False)
+
+
+@pytest.mark.parametrize("mode", ["packed", "packed_tight", "one_per_launch"])
+def test_native_results_identical_alone_and_in_mix(setup, mode):
+    """fif_serve_run (the loop in C++): every request's results equal the
+    direct query / gradient call on it alone, whatever was packed with it."""
+    fif, serve, fields, pools, specs = setup
+    reqs = _make(serve, pools, specs)
+    biggest = max(r.m for r in reqs)
+    kw = {"packed": dict(n_streams=3, co_batch=True, max_batch=16384),
+          "packed_tight": dict(n_streams=2, co_batch=True, max_batch=biggest, max_inflight=6),
+          "one_per_launch": dict(n_streams=1, co_batch=False, max_inflight=1,
+                                 max_batch=biggest)}[mode]
+    print(f"case: native serving loop, {mode}", flush=True)
+    srv = serve.NativeServer(fields, **kw)
+    elapsed = srv.run(reqs, realtime=True)
+    assert elapsed > 0
+    for r in reqs:
+        assert r.arrival <= r.admitted + 1e-9 and r.admitted <= r.done, (mode, r.rid)
+        out, gt, gphi = _alone(fif, fields, r)
+        assert torch.equal(r.out, out), (mode, r.rid)
+        if r.kind == "opt":
+            assert torch.equal(r.grad_t, gt) and torch.equal(r.grad_phi, gphi), (mode, r.rid)
+    st = serve.latency_stats(reqs)
+    assert st["n"] == len(reqs) and st["p99_ms"] >= st["p50_ms"] >= 0
+
+
+def test_native_admission_and_errors(setup):
+    import ctypes
+    fif, serve, fields, pools, specs = setup
+    reqs = _make(serve, pools, specs)
+    big = max(r.bytes_needed() for r in reqs)
+    srv = serve.NativeServer(fields, n_streams=2, hbm_budget=big)
+    srv.run(reqs, realtime=False)
+    assert all(r.done == r.done for r in reqs)  # not NaN
+    # a request larger than the budget is refused before anything runs
+    tiny = serve.NativeServer(fields, n_streams=1, hbm_budget=big - 1)
+    with pytest.raises(fif.FifError, match="HBM budget"):
+        tiny.run(_make(serve, pools, specs), realtime=False)
+    with pytest.raises(ValueError):
+        serve.NativeServer(fields, n_streams=0)
+    # a workspace smaller than fif_serve_workspace_bytes() is refused
+    cfg = fif.CServeConfig(1, 4, 1 << 30, 1024, 1, 0)
+    need = fif.lib().fif_serve_workspace_bytes(ctypes.byref(cfg))
+    ws = torch.empty(need, dtype=torch.uint8, device="cuda")
+    one = (fif.CServeRequest * 1)()
+    r0 = reqs[0]
+    r0.out = torch.empty((r0.m, 3), dtype=torch.float64, device="cuda")
+    one[0] = fif.CServeRequest(0.0, r0.field, 0, r0.m, r0.t.data_ptr(), r0.q.data_ptr(),
+                               r0.out.data_ptr(), None, None, 0.0, 0.0)
+    cf = (fif.CField * len(fields))(*[f.cstruct for f in fields])
+    el = ctypes.c_double()
+    L = fif.lib()
+    assert L.fif_serve_run(cf, len(fields), one, 1, ctypes.byref(cfg),
+                           ctypes.c_void_p(ws.data_ptr()), need - 1, ctypes.byref(el)) == -2
+    bad = fif.CServeRequest(0.0, 7, 0, r0.m, r0.t.data_ptr(), r0.q.data_ptr(),
+                            r0.out.data_ptr(), None, None, 0.0, 0.0)
+    one[0] = bad
+    assert L.fif_serve_run(cf, len(fields), one, 1, ctypes.byref(cfg),
+                           ctypes.c_void_p(ws.data_ptr()), need, ctypes.byref(el)) == -1
+    assert b"field index" in L.fif_last_error()
