@@ -164,3 +164,39 @@ def test_gp_host_side_validation():
     assert L.fif_gp_query(ctypes.byref(ft), None, None, 5, 2, 0, None, None, None) == -1
     assert L.fif_gp_export(ctypes.byref(f), None, 3, None, None) == -1
     assert L.fif_gp_export(ctypes.byref(f), None, 0, None, None) == 0
+
+
+def test_serve_host_side_validation():
+    """fif_serve_run refuses bad configurations, fields and requests before it
+    creates a stream or enqueues anything."""
+    fif, L = _lib()
+    g = fif.Grid((0.0, 0.0, 0.0), 0.5, (4, 4, 4))
+    vis = fif.Vis()
+    ok = fif.CServeConfig(2, 8, 1 << 20, 1024, 1, 0)
+    assert L.fif_serve_workspace_bytes(ctypes.byref(ok)) > 0
+    for bad in (fif.CServeConfig(0, 8, 1 << 20, 1024, 1, 0), fif.CServeConfig(17, 8, 1 << 20, 1024, 1, 0),
+                fif.CServeConfig(2, 0, 1 << 20, 1024, 1, 0), fif.CServeConfig(2, 8, 0, 1024, 1, 0),
+                fif.CServeConfig(2, 8, 1 << 20, 0, 1, 0)):
+        assert L.fif_serve_workspace_bytes(ctypes.byref(bad)) == 0
+    fields = (fif.CField * 1)(fif.CField(g.c(), vis.c(), fif.FP32_COMP, fif.KIND_INFO, 4096))
+    el = ctypes.c_double()
+    req = (fif.CServeRequest * 1)(fif.CServeRequest(0.0, 0, 0, 10, 4096, 4096, 4096, None, None,
+                                                    0.0, 0.0))
+    run = lambda f, nf, r, n, c, ws, nb: L.fif_serve_run(f, nf, r, n, ctypes.byref(c), ws, nb,
+                                                         ctypes.byref(el))
+    bad_cfg = fif.CServeConfig(0, 8, 1 << 20, 1024, 1, 0)
+    assert run(fields, 1, req, 1, bad_cfg, 4096, 1 << 30) == -1
+    assert run(fields, 0, req, 1, ok, 4096, 1 << 30) == -1
+    trace = (fif.CField * 1)(fif.CField(g.c(), vis.c(), fif.FP32_COMP, fif.KIND_TRACE, 4096))
+    assert run(trace, 1, req, 1, ok, 4096, 1 << 30) == -1  # serving needs information fields
+    for fld, kind, m in ((1, 0, 10), (0, 2, 10), (0, 0, 0), (0, 0, 2048), (0, 1, 10)):
+        # field index, kind, m < 1, m > max_batch, gradient buffers missing
+        r = (fif.CServeRequest * 1)(fif.CServeRequest(0.0, fld, kind, m, 4096, 4096, 4096, None,
+                                                      None, 0.0, 0.0))
+        assert run(fields, 1, r, 1, ok, 4096, 1 << 30) == -1, (fld, kind, m)
+    small = fif.CServeConfig(2, 8, 100, 1024, 1, 0)  # 10 poses need 240 B
+    assert run(fields, 1, req, 1, small, 4096, 1 << 30) == -1
+    assert b"budget" in L.fif_last_error()
+    need = L.fif_serve_workspace_bytes(ctypes.byref(ok))
+    assert run(fields, 1, req, 1, ok, 4096, need - 1) == -2
+    assert run(fields, 1, req, 0, ok, 4096, need) == 0  # nothing to serve
