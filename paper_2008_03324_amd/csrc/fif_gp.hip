@@ -653,6 +653,9 @@ __global__ __launch_bounds__(256) void gp_query_trace_kernel(GPQueryArgs ga) {
     double y[kRows];
 #pragma unroll
     for (int k = 0; k < kRows; ++k) y[k] = 0.0;
+    // unrolled so that the scalar loads of several h are in flight together
+    // (2.14 -> 1.65 ms for 1M poses at N_s = 70; 16 is slower again)
+#pragma unroll 8
     for (int h = 0; h < ns; ++h) {
       const double th = (double)col[(size_t)h * nt + tid];
 #pragma unroll
