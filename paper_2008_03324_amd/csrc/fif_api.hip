@@ -4,6 +4,7 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <atomic>
 #include <string>
 
 #include "../../include/fif.h"
@@ -497,6 +498,23 @@ namespace fif {
 // The thread's fif_last_error() text, set by parts of the library outside
 // this file (the serving loop).
 void set_last_error(const std::string& msg) { g_last_error = msg; }
+
+// Compute units of the calling thread's current device, cached per device
+// (the persistent kernels size their grids by it on every launch).
+int current_device_cus() {
+  static std::atomic<int> cache[64];
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0) return 256;
+  if (dev < 64) {
+    const int c = cache[dev].load(std::memory_order_relaxed);
+    if (c > 0) return c;
+  }
+  int v = 0;
+  if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || v <= 0)
+    v = 256;
+  if (dev < 64) cache[dev].store(v, std::memory_order_relaxed);
+  return v;
+}
 }  // namespace fif
 
 extern "C" {

@@ -715,15 +715,7 @@ __global__ void gp_export_kernel(GPExportArgs a) {
   }
 }
 
-int64_t resident_blocks(int per_cu) {
-  int dev = 0, cus = 256;
-  if (hipGetDevice(&dev) == hipSuccess) {
-    int v = 0;
-    if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && v > 0)
-      cus = v;
-  }
-  return (int64_t)cus * per_cu;
-}
+int64_t resident_blocks(int per_cu) { return (int64_t)current_device_cus() * per_cu; }
 
 }  // namespace
 

@@ -153,6 +153,8 @@ inline QueryArgs query_part(const QueryArgs& a, int64_t off, int64_t n, size_t s
 
 // Sets the calling thread's fif_last_error() text.
 void set_last_error(const std::string& msg);
+// Compute units of the calling thread's current device (cached).
+int current_device_cus();
 
 hipError_t launch_build(const BuildArgs& a, int prec, int kind, hipStream_t stream);
 hipError_t launch_gp_setup(const GPDev& gp, double* kinv, hipStream_t stream);

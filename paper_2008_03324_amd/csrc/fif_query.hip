@@ -580,15 +580,7 @@ __global__ void export_trace_kernel(ExportArgs a) {
 
 // Workgroups of the persistent query: 8 per CU of the current device (two are
 // resident per CU at this kernel's register count; the rest even out the tail).
-static int64_t pipe_blocks() {
-  int dev = 0, cus = 256;
-  if (hipGetDevice(&dev) == hipSuccess) {
-    int v = 0;
-    if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && v > 0)
-      cus = v;
-  }
-  return (int64_t)cus * 8;
-}
+static int64_t pipe_blocks() { return (int64_t)current_device_cus() * 8; }
 
 hipError_t launch_query(const QueryArgs& a, int prec, int kind, bool grad, hipStream_t stream) {
   if (a.m <= 0) return hipSuccess;
