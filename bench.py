@@ -596,6 +596,45 @@ def cpu_leg(args, fif, torch, lm, g, v, t, q, out, pc_out, metrics):
                 "logdet_abs_max": float(np.nanmax(np.abs(a[:, 2] - b[:, 2])))}
 
     pairs = ids.size * lm.shape[0]
+
+    # the same oracle on one core (a smaller sample: 128 poses), and the tiny
+    # workload (2,000 landmarks, 20x20x6 voxels, full build + 1,000 queries)
+    # on one core and on all of them
+    import scenes
+    one = {}
+    oracle.set_num_threads(1)
+    try:
+        n1 = 128
+        ids1 = oracle.corner_voxels(g.origin, g.h, g.shape, ts[:n1])
+        c0 = time.perf_counter()
+        C1 = oracle.build(lm, g.origin, g.h, g.shape, v.sigma, v.r_min, v.r_max, voxel_ids=ids1)
+        b1 = time.perf_counter() - c0
+        f1 = oracle.Field(C1, g.origin, g.h, g.shape, voxel_ids=ids1)
+        c0 = time.perf_counter()
+        oracle.query(f1, v.half_fov, v.v_alpha, ts[:n1], qs[:n1], metrics)
+        q1 = time.perf_counter() - c0
+        one = {"poses": n1, "corner_voxels": int(ids1.size),
+               "build_pairs_per_s": ids1.size * lm.shape[0] / b1, "queries_per_s": n1 / q1,
+               "seconds": b1 + q1}
+        tlm, tg, tv = scenes.tiny_scene()
+        tt, tq = scenes.tiny_poses(tg)
+        tiny = {}
+        for label, nth in (("1_core", 1), ("all_cores", nthreads)):
+            oracle.set_num_threads(nth)
+            c0 = time.perf_counter()
+            Ct = oracle.build(tlm, tg.origin, tg.h, tg.shape, tv.sigma, tv.r_min, tv.r_max)
+            tb = time.perf_counter() - c0
+            ft = oracle.Field(Ct, tg.origin, tg.h, tg.shape)
+            c0 = time.perf_counter()
+            oracle.query(ft, tv.half_fov, tv.v_alpha, tt, tq, metrics)
+            tqs = time.perf_counter() - c0
+            tiny[label] = {"threads": nth, "build_s": tb, "queries_per_s": tt.shape[0] / tqs,
+                           "build_pairs_per_s": tg.n_voxels * tlm.shape[0] / tb}
+    finally:
+        oracle.set_num_threads(nthreads)
+    log(f"oracle on 1 core: {one['build_pairs_per_s']:.3g} pairs/s, {one['queries_per_s']:.0f} "
+        f"queries/s; tiny workload build {tiny['1_core']['build_s']:.2f} s (1 core), "
+        f"{tiny['all_cores']['build_s']:.2f} s ({nthreads} threads)")
     return {
         "rel_err_field_vs_oracle": errs(gpu, ref, lmax),
         "rel_err_pc_vs_oracle": errs(gpu_pc, ref_pc, lmax[:n_pc]),
@@ -608,6 +647,8 @@ def cpu_leg(args, fif, torch, lm, g, v, t, q, out, pc_out, metrics):
                       f"({pc_s:.1f} s)",
             "build_pairs_per_s": pairs / build_s,
             "pc_queries_per_s": n_pc / pc_s,
+            "one_core": one,
+            "tiny_workload": tiny,
             "cpu_seconds": build_s + q_s * reps + pc_s,
             # the paper's own CPU numbers (Table I; C++, hardware not stated; 1,000
             # landmarks, ~16k voxels, 200 poses): context only, other scene and machine

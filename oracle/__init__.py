@@ -458,3 +458,8 @@ def num_threads() -> int:
     f = lib().oracle_num_threads
     f.restype = ctypes.c_int
     return int(f())
+
+
+def set_num_threads(n: int) -> None:
+    """Threads of the oracle's OpenMP loops from here on."""
+    lib().oracle_set_num_threads(ctypes.c_int(int(n)))

@@ -992,3 +992,12 @@ int oracle_num_threads(void) {
   return 1;
 #endif
 }
+
+/* Threads of the OpenMP loops from here on (timing on one core or all). */
+void oracle_set_num_threads(int n) {
+#ifdef _OPENMP
+  if (n > 0) omp_set_num_threads(n);
+#else
+  (void)n;
+#endif
+}
