@@ -71,6 +71,10 @@ __global__ __launch_bounds__(kQThreads) void query_info_kernel(QueryArgs a) {
   const size_t nvox = (size_t)a.g.nx * a.g.ny * a.g.nz;
   const CT k2 = (CT)a.vis.k2, k1 = (CT)a.vis.k1, k0 = (CT)a.vis.k0;
 
+  // gradient kernel: the forward and backward corner passes (gathers) run at
+  // a raised wave priority, the FP64 metric step in between at the normal one
+  // (0.21 -> 0.19 ms for 262k trajectory poses)
+  if (GRAD) __builtin_amdgcn_s_setprio(1);
   s_q[tid] = make_slot<FT>(a, ql);
   __syncthreads();
 
@@ -132,6 +136,7 @@ __global__ __launch_bounds__(kQThreads) void query_info_kernel(QueryArgs a) {
     }
   }
 
+  if (GRAD) __builtin_amdgcn_s_setprio(0);
   const QSlot<CT> own = s_q[tid];
   double td[3] = {(double)own.t[0], (double)own.t[1], (double)own.t[2]};
   double Zd[21], F[21];
@@ -155,6 +160,7 @@ __global__ __launch_bounds__(kQThreads) void query_info_kernel(QueryArgs a) {
   if (!GRAD) return;
 
   // ------------------------------------------------------------ backward
+  __builtin_amdgcn_s_setprio(1);
   {
     double Gt[21];
     shift21_adj<double>(G, td, Gt);
