@@ -429,6 +429,39 @@ __device__ inline void load_rows(const FT* rec, int c8, int r0, int nrow, FT x[k
   }
 }
 
+// Rows gr[0 .. NR-1] of w = (K^s + noise I)^-1 K_z for one pose: each row
+// summed over h = 0 .. ns - 1 in ascending order.  NR is a template argument so
+// that the reads of all rows for one h are issued together.
+template <int NR>
+__device__ inline void gp_wrows(const GPDev& gp, const double* kz, const double* kinv_lds,
+                                bool in_lds, int lane, double wr[3]) {
+  const int ns = gp.ns;
+  int gr[NR], rs[NR];
+#pragma unroll
+  for (int r = 0; r < NR; ++r) {
+    gr[r] = min(lane + 64 * r, ns - 1);  // lanes past the end repeat a row
+    rs[r] = gr[r] * (gr[r] + 1) / 2;
+  }
+  if (in_lds) {
+    int hs = 0;  // h (h + 1) / 2: start of packed row h
+#pragma unroll 2
+    for (int h = 0; h < ns; ++h) {
+      const double kzh = kz[h];
+#pragma unroll
+      for (int r = 0; r < NR; ++r)
+        wr[r] = fma(kinv_lds[(h >= gr[r]) ? hs + gr[r] : rs[r] + h], kzh, wr[r]);
+      hs += h + 1;
+    }
+  } else {
+#pragma unroll 2
+    for (int h = 0; h < ns; ++h) {
+      const double kzh = kz[h];
+#pragma unroll
+      for (int r = 0; r < NR; ++r) wr[r] = fma(gp.kinv[(size_t)h * ns + gr[r]], kzh, wr[r]);
+    }
+  }
+}
+
 // FP32 fields: two waves per SIMD (the register budget that keeps the gathers
 // of two waves in flight); FP64 fields take one.
 template <typename FT, int KIND>
@@ -486,40 +519,19 @@ __attribute__((amdgpu_waves_per_eu(sizeof(FT) == 4 ? 2 : 1))) void gp_query_kern
           xt[r] = (r < nrow) ? rec[c8 + 8 * r] : FT(0);
       }
       // GP weights of this pose: w = (K^s + noise I)^-1 K_z, FP64.  Lane l
-      // forms rows l, l + 64 and l + 128, each summed over h = 0 .. ns - 1 in
-      // order; every lane runs the same trip count, so the reads of the
-      // inverse pipeline instead of waiting one by one.
+      // forms rows l, l + 64 and l + 128 (as many as N_s needs), each summed
+      // over h = 0 .. ns - 1 in order; every lane runs the same trip count and
+      // the reads for all of its rows (and two values of h) are in flight
+      // together instead of waiting one by one.
       const double z[3] = {(double)sl.z[0], (double)sl.z[1], (double)sl.z[2]};
       for (int g = lane; g < ns; g += 64) s_kz[wv][g] = se_kernel(z, ga.gp.axes + 3 * g, ga.gp.inv_2l2);
       wave_sync();
       {
         const int nr = (ns + 63) >> 6;  // rows per lane, 1 .. 3
         double wr[3] = {0.0, 0.0, 0.0};
-        int gr[3], rs[3];
-#pragma unroll
-        for (int r = 0; r < 3; ++r) {
-          gr[r] = min(lane + 64 * r, ns - 1);  // lanes past the end repeat a row
-          rs[r] = gr[r] * (gr[r] + 1) / 2;
-        }
-        if (kinv_lds) {
-          int hs = 0;  // h (h + 1) / 2: start of packed row h
-#pragma unroll 1
-          for (int h = 0; h < ns; ++h) {
-            const double kzh = s_kz[wv][h];
-#pragma unroll
-            for (int r = 0; r < 3; ++r)
-              if (r < nr) wr[r] = fma(s_kinv[(h >= gr[r]) ? hs + gr[r] : rs[r] + h], kzh, wr[r]);
-            hs += h + 1;
-          }
-        } else {
-#pragma unroll 1
-          for (int h = 0; h < ns; ++h) {
-            const double kzh = s_kz[wv][h];
-#pragma unroll
-            for (int r = 0; r < 3; ++r)
-              if (r < nr) wr[r] = fma(ga.gp.kinv[(size_t)h * ns + gr[r]], kzh, wr[r]);
-          }
-        }
+        if (nr == 1) gp_wrows<1>(ga.gp, s_kz[wv], s_kinv, kinv_lds, lane, wr);
+        else if (nr == 2) gp_wrows<2>(ga.gp, s_kz[wv], s_kinv, kinv_lds, lane, wr);
+        else gp_wrows<3>(ga.gp, s_kz[wv], s_kinv, kinv_lds, lane, wr);
 #pragma unroll
         for (int r = 0; r < 3; ++r)
           if (lane + 64 * r < ns) s_w[wv][lane + 64 * r] = (CT)wr[r];
