@@ -477,6 +477,9 @@ __attribute__((amdgpu_waves_per_eu(sizeof(FT) == 4 ? 2 : 1))) void gp_query_kern
   // packed lower triangle of the inverse, information fields only (the trace
   // kernel keeps its occupancy instead)
   __shared__ double s_kinv[KIND == 0 ? kKinvLds : 1];
+  // sample axes: read from LDS so that the GP weights never wait on the
+  // vector-memory counter behind the row gathers already in flight
+  __shared__ double s_axes[3 * kMaxNs];
 
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int grp = lane >> 3, c8 = lane & 7;
@@ -495,6 +498,7 @@ __attribute__((amdgpu_waves_per_eu(sizeof(FT) == 4 ? 2 : 1))) void gp_query_kern
       s_kinv[i] = ga.gp.kinv[(size_t)r * ns + (i - r * (r + 1) / 2)];
     }
   }
+  for (int i = threadIdx.x; i < 3 * ns; i += kGPThreads) s_axes[i] = ga.gp.axes[i];
   __syncthreads();  // the only workgroup barrier: before any wave can leave
   for (int64_t b = gw; b < nbatch; b += nw) {
     const int64_t qown = b * 64 + lane;
@@ -524,7 +528,7 @@ __attribute__((amdgpu_waves_per_eu(sizeof(FT) == 4 ? 2 : 1))) void gp_query_kern
       // the reads for all of its rows (and two values of h) are in flight
       // together instead of waiting one by one.
       const double z[3] = {(double)sl.z[0], (double)sl.z[1], (double)sl.z[2]};
-      for (int g = lane; g < ns; g += 64) s_kz[wv][g] = se_kernel(z, ga.gp.axes + 3 * g, ga.gp.inv_2l2);
+      for (int g = lane; g < ns; g += 64) s_kz[wv][g] = se_kernel(z, s_axes + 3 * g, ga.gp.inv_2l2);
       wave_sync();
       {
         const int nr = (ns + 63) >> 6;  // rows per lane, 1 .. 3
@@ -622,34 +626,50 @@ __global__ __launch_bounds__(256) void gp_query_trace_kernel(GPQueryArgs ga) {
   const int64_t ql = valid ? qi : a.m - 1;
   const QSlot<CT> sl = make_slot<FT>(a, ql);
   const FT* field = reinterpret_cast<const FT*>(a.field);
-  // interpolated factors: corner by corner, each lane streaming its corner's
-  // row (so a wave's lines stay in L1 while they are read), accumulated in
-  // the lane's LDS column
-  for (int h = 0; h < ns; ++h) col[(size_t)h * nt + tid] = CT(0);
-  const int n4 = (ns + 3) / 4;
+  // interpolated factors, kH at a time: the rows of all 8 corners for those
+  // factors are requested together (many gathers in flight per lane), summed
+  // in registers corner by corner, and written once to the lane's LDS column.
+  // A corner that nearest mode leaves out reads corner 0's row with weight 0.
+  constexpr int kH = sizeof(FT) == 4 ? 24 : 8;
+  size_t cvox[8];
+  CT cw[8];
+#pragma unroll
   for (int j = 0; j < 8; ++j) {
     const CornerC<CT> c = slot_corner(sl, a.g, j);
-    if (!c.active) continue;
-    const FT* row = field + c.vox * (size_t)ga.stride;
-#pragma unroll 2
-    for (int h4 = 0; h4 < n4; ++h4) {
-      FT x[4];
-      if constexpr (sizeof(FT) == 4) {
-        const float4 v4 = *reinterpret_cast<const float4*>(row + 4 * h4);
-        x[0] = v4.x; x[1] = v4.y; x[2] = v4.z; x[3] = v4.w;
-      } else {
-        const double2 v0 = *reinterpret_cast<const double2*>(row + 4 * h4);
-        const double2 v1 = *reinterpret_cast<const double2*>(row + 4 * h4 + 2);
-        x[0] = v0.x; x[1] = v0.y; x[2] = v1.x; x[3] = v1.y;
-      }
+    cvox[j] = c.vox;
+    cw[j] = c.active ? c.w : CT(0);
+  }
 #pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        const int h = 4 * h4 + e;
-        if (h < ns) {
-          CT* cp = col + (size_t)h * nt + tid;
-          *cp = fma(c.w, (CT)x[e], *cp);
+  for (int j = 1; j < 8; ++j)
+    if (cw[j] == CT(0)) cvox[j] = cvox[0];
+  for (int h0 = 0; h0 < ns; h0 += kH) {
+    FT x[8][kH];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const FT* row = field + cvox[j] * (size_t)ga.stride + h0;
+#pragma unroll
+      for (int q = 0; q < kH / 4; ++q) {
+        if (h0 + 4 * q < ns) {
+          if constexpr (sizeof(FT) == 4) {
+            const float4 v4 = *reinterpret_cast<const float4*>(row + 4 * q);
+            x[j][4 * q] = v4.x; x[j][4 * q + 1] = v4.y; x[j][4 * q + 2] = v4.z; x[j][4 * q + 3] = v4.w;
+          } else {
+            const double2 v0 = *reinterpret_cast<const double2*>(row + 4 * q);
+            const double2 v1 = *reinterpret_cast<const double2*>(row + 4 * q + 2);
+            x[j][4 * q] = v0.x; x[j][4 * q + 1] = v0.y; x[j][4 * q + 2] = v1.x; x[j][4 * q + 3] = v1.y;
+          }
+        } else {
+#pragma unroll
+          for (int e = 0; e < 4; ++e) x[j][4 * q + e] = FT(0);
         }
       }
+    }
+#pragma unroll
+    for (int e = 0; e < kH; ++e) {
+      CT acc = CT(0);
+#pragma unroll
+      for (int j = 0; j < 8; ++j) acc = fma(cw[j], (CT)x[j][e], acc);
+      if (h0 + e < ns) col[(size_t)(h0 + e) * nt + tid] = acc;
     }
   }
   // Tr = K_z^T (K^s + noise I)^-1 Tbar in FP64, kRows rows of the inverse at a
