@@ -405,7 +405,6 @@ __device__ inline void gp_block(const CT s[15], const CT dl[3], CT out[21]) {
 
 constexpr int kChunk = 3;                      // rows loaded together per lane
 constexpr int kKinvLds = 3240;                 // packed inverse held in LDS up to N_s = 80
-constexpr int kMaxRowsPerLane = kMaxNs / 8;    // trace rows per lane
 
 // Rows r0 .. r0 + kChunk - 1 (those below nrow) of axes c8 + 8 r of a voxel.
 template <typename FT>
@@ -462,11 +461,13 @@ __device__ inline void gp_wrows(const GPDev& gp, const double* kz, const double*
   }
 }
 
+// Information fields (KIND 0; trace fields have their own kernel below).
 // FP32 fields: two waves per SIMD (the register budget that keeps the gathers
 // of two waves in flight); FP64 fields take one.
 template <typename FT, int KIND>
 __global__ __launch_bounds__(kGPThreads)
 __attribute__((amdgpu_waves_per_eu(sizeof(FT) == 4 ? 2 : 1))) void gp_query_kernel(GPQueryArgs ga) {
+  static_assert(KIND == 0, "trace fields use gp_query_trace_kernel");
   using CT = FT;
   const QueryArgs& a = ga.q;
   __shared__ QSlot<CT> s_q[kGPWaves][64];
@@ -474,9 +475,7 @@ __attribute__((amdgpu_waves_per_eu(sizeof(FT) == 4 ? 2 : 1))) void gp_query_kern
   __shared__ CT s_w[kGPWaves][kMaxNs];
   __shared__ CT s_c[kGPWaves][8][22];
   __shared__ CT s_F[kGPWaves][64][22];
-  // packed lower triangle of the inverse, information fields only (the trace
-  // kernel keeps its occupancy instead)
-  __shared__ double s_kinv[KIND == 0 ? kKinvLds : 1];
+  __shared__ double s_kinv[kKinvLds];  // packed lower triangle of the inverse
   // sample axes: read from LDS so that the GP weights never wait on the
   // vector-memory counter behind the row gathers already in flight
   __shared__ double s_axes[3 * kMaxNs];
@@ -489,7 +488,7 @@ __attribute__((amdgpu_waves_per_eu(sizeof(FT) == 4 ? 2 : 1))) void gp_query_kern
   const int64_t gw = (int64_t)blockIdx.x * kGPWaves + wv;
   const int64_t nw = (int64_t)gridDim.x * kGPWaves;
 
-  const bool kinv_lds = KIND == 0 && ns * (ns + 1) / 2 <= kKinvLds;
+  const bool kinv_lds = ns * (ns + 1) / 2 <= kKinvLds;
   if (kinv_lds) {
     for (int i = threadIdx.x; i < ns * (ns + 1) / 2; i += kGPThreads) {
       int r = (int)((sqrt(8.0 * i + 1.0) - 1.0) * 0.5);
@@ -514,14 +513,7 @@ __attribute__((amdgpu_waves_per_eu(sizeof(FT) == 4 ? 2 : 1))) void gp_query_kern
       const FT* rec = field + c.vox * (size_t)ga.stride;
       // first loads are issued before the GP weights, which they do not need
       FT xr[kChunk][16];
-      FT xt[kMaxRowsPerLane];
-      if constexpr (KIND == 0) {
-        load_rows<FT>(rec, c8, 0, nrow, xr);
-      } else {
-#pragma unroll
-        for (int r = 0; r < kMaxRowsPerLane; ++r)
-          xt[r] = (r < nrow) ? rec[c8 + 8 * r] : FT(0);
-      }
+      load_rows<FT>(rec, c8, 0, nrow, xr);
       // GP weights of this pose: w = (K^s + noise I)^-1 K_z, FP64.  Lane l
       // forms rows l, l + 64 and l + 128 (as many as N_s needs), each summed
       // over h = 0 .. ns - 1 in order; every lane runs the same trip count and
@@ -541,7 +533,7 @@ __attribute__((amdgpu_waves_per_eu(sizeof(FT) == 4 ? 2 : 1))) void gp_query_kern
           if (lane + 64 * r < ns) s_w[wv][lane + 64 * r] = (CT)wr[r];
       }
       wave_sync();
-      if constexpr (KIND == 0) {
+      {
         CT acc[15];
 #pragma unroll
         for (int e = 0; e < 15; ++e) acc[e] = 0;
@@ -570,16 +562,9 @@ __attribute__((amdgpu_waves_per_eu(sizeof(FT) == 4 ? 2 : 1))) void gp_query_kern
 #pragma unroll
           for (int e = 0; e < 21; ++e) s_c[wv][grp][e] = Y[e];
         }
-      } else {
-        CT acc = 0;
-#pragma unroll
-        for (int r = 0; r < kMaxRowsPerLane; ++r)
-          if (r < nrow) acc = fma(s_w[wv][c8 + 8 * r], (CT)xt[r], acc);
-        acc = sum8(acc);
-        if (c8 == 0) s_c[wv][grp][0] = c.active ? acc * c.w : CT(0);
       }
       wave_sync();
-      if (lane < (KIND == 0 ? 21 : 1)) {
+      if (lane < 21) {
         CT sacc = 0;
 #pragma unroll
         for (int j = 0; j < 8; ++j) sacc += s_c[wv][j][lane];
@@ -590,19 +575,15 @@ __attribute__((amdgpu_waves_per_eu(sizeof(FT) == 4 ? 2 : 1))) void gp_query_kern
     // metrics of this lane's own pose
     const QSlot<CT> own = s_q[wv][lane];
     uint8_t flag = (own.bits & 8) ? FL_CLAMPED : 0;
-    if constexpr (KIND == 0) {
-      double td[3] = {(double)own.t[0], (double)own.t[1], (double)own.t[2]};
-      double Zd[21], F[21];
+    double td[3] = {(double)own.t[0], (double)own.t[1], (double)own.t[2]};
+    double Zd[21], F[21];
 #pragma unroll
-      for (int e = 0; e < 21; ++e) Zd[e] = (double)s_F[wv][lane][e];
-      shift21<double>(Zd, td, F);
+    for (int e = 0; e < 21; ++e) Zd[e] = (double)s_F[wv][lane][e];
+    shift21<double>(Zd, td, F);
 #pragma unroll
-      for (int e = 0; e < 21; ++e) F[e] *= a.vis.inv_s2;
-      double* row = (valid && a.out) ? a.out + ql * a.ncols : nullptr;
-      eval_metrics<false>(F, a.metrics, row, &flag, nullptr, nullptr, a.flags != nullptr);
-    } else {
-      if (valid && a.out) a.out[ql * a.ncols] = (double)s_F[wv][lane][0] * a.vis.inv_s2;
-    }
+    for (int e = 0; e < 21; ++e) F[e] *= a.vis.inv_s2;
+    double* row = (valid && a.out) ? a.out + ql * a.ncols : nullptr;
+    eval_metrics<false>(F, a.metrics, row, &flag, nullptr, nullptr, a.flags != nullptr);
     if (valid && a.flags) a.flags[ql] = flag;
     wave_sync();  // s_q and s_F are rewritten by the next batch
   }

@@ -314,11 +314,15 @@ class NativeServer:
                                    r.grad_t.data_ptr() if opt else None,
                                    r.grad_phi.data_ptr() if opt else None, 0.0, 0.0)
         self.cfg.realtime = int(realtime)
-        torch.cuda.synchronize()  # request inputs and outputs allocated and ready
         elapsed = ctypes.c_double(0.0)
-        _check(lib().fif_serve_run(self.cfields, len(self.fields), arr, n, ctypes.byref(self.cfg),
-                                   ctypes.c_void_p(self.workspace.data_ptr()),
-                                   self.workspace.numel(), ctypes.byref(elapsed)), "fif_serve_run")
+        # the loop creates its streams on the current device: the fields' one
+        with torch.cuda.device(self.workspace.device):
+            torch.cuda.synchronize()  # request inputs and outputs allocated and ready
+            _check(lib().fif_serve_run(self.cfields, len(self.fields), arr, n,
+                                       ctypes.byref(self.cfg),
+                                       ctypes.c_void_p(self.workspace.data_ptr()),
+                                       self.workspace.numel(), ctypes.byref(elapsed)),
+                   "fif_serve_run")
         for i, r in enumerate(requests):
             r.admitted, r.done, r.status = arr[i].admitted, arr[i].done, "done"
         return elapsed.value

@@ -164,16 +164,21 @@ def test_gp_fp32_fields_within_bar(fif, model30, tiny30):
         assert et.max() <= 1e-3
 
 
-def test_gp_trace_field_equals_information_trace(fif, model30, tiny30):
-    print("case: GP trace field vs information field trace", flush=True)
+@pytest.mark.parametrize("interp", [0, 1])
+def test_gp_trace_field_equals_information_trace(fif, model30, tiny30, interp):
+    print(f"case: GP trace field vs information field trace and oracle, interp={interp}", flush=True)
     grid, vis = _gv(fif, tiny30["g"], tiny30["v"])
     lm = _cuda(tiny30["lm"])
     fi = fif.gp_build(lm, grid, vis, model30["model"], prec=fif.FP64)
     ft = fif.gp_build(lm, grid, vis, model30["model"], prec=fif.FP64, kind=fif.KIND_TRACE)
     t, q = _cuda(tiny30["t"]), _cuda(tiny30["q"])
-    a = fif.gp_query(fi, t, q, fif.TRACE).cpu().numpy()
-    b = fif.gp_query(ft, t, q, fif.TRACE).cpu().numpy()
+    a = fif.gp_query(fi, t, q, fif.TRACE, interp=interp).cpu().numpy()
+    b, flags = fif.gp_query(ft, t, q, fif.TRACE, interp=interp, want_flags=True)
+    b = b.cpu().numpy()
     assert np.abs(a - b).max() <= 1e-10 * np.abs(a).max()
+    ref, rflags = oracle.gp_query(tiny30["ft"], tiny30["t"], tiny30["q"], 1, interp)
+    assert (np.abs(b[:, 0] - ref[:, 0]) / np.abs(ref[:, 0])).max() <= 1e-9
+    assert np.array_equal(flags.cpu().numpy() & 1, rflags & 1)
 
 
 def test_gp_building_scene_ns70_sampled(fif):
