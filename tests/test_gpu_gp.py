@@ -241,19 +241,20 @@ def test_gp_edge_cases(fif, model30, tiny30):
         fif.GPField(grid, vis, fif.GPModel(_cuda(scenes.sphere_axes(200)), KS, None), fif.FP64)
 
 
-@pytest.mark.parametrize("ns", [150, 160])
+@pytest.mark.parametrize("ns", [100, 150, 160])
 def test_gp_large_ns_matches_oracle(fif, ns):
     """N_s past 80 (the inverse read from global memory in the information query,
-    the trace query's 64-lane workgroups, two build passes), up to the maximum
-    N_s = 160: FP64 factors and queries, and an FP32-compensated field.  The
-    lengths are near the ML-II ones, where cond(K^s + noise I) is about 4.5e5;
+    two rows of it per lane at N_s = 100 and three at 150 and 160; the trace
+    query's 64-lane workgroups; two build passes), up to the maximum N_s = 160:
+    FP64 factors and queries, and an FP32-compensated field.  The lengths are
+    near the ML-II ones, where cond(K^s + noise I) is about 4.5e5;
     the FP64 bar of 1e-9 allows the weight product's cancellation at that
     conditioning (at N_s = 160 and l = 0.45, cond 1e6, both sides differ from
     exact by ~1e-9)."""
     print(f"case: GP tiny scene N_s={ns}", flush=True)
     lm, g, v = scenes.tiny_scene(n_landmarks=400)
     Z = scenes.sphere_axes(ns)
-    length = {150: 0.45, 160: 0.43}[ns]
+    length = {100: 0.5, 150: 0.45, 160: 0.43}[ns]
     A = oracle.gp_inverse(Z, length, NOISE)
     model = fif.GPModel(_cuda(Z), KS, length, NOISE)
     grid, vis = _gv(fif, g, v)
