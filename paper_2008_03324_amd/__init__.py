@@ -280,6 +280,13 @@ def workspace(grid: Grid, n_landmarks: int, prec: int, device) -> torch.Tensor |
     return ws
 
 
+def release_workspaces() -> None:
+    """Drop the cached build workspaces (one per device and stream used so far).
+    The memory returns to torch's caching allocator, which reuses it in stream
+    order, so builds still in flight are not disturbed."""
+    _WORKSPACE.clear()
+
+
 @_on_stream
 def build(landmarks: torch.Tensor, grid: Grid, vis: Vis, prec: int = FP32_COMP,
           kind: int = KIND_INFO, field: Field | None = None, sort: bool = True,

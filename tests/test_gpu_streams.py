@@ -43,3 +43,13 @@ def test_side_streams_match_default_stream(fif):
     for i in range(2):
         assert torch.equal(fields[i].buffer, ref[i].buffer)
         assert torch.equal(outs[i].nan_to_num(7.0), ref_out[i].nan_to_num(7.0))
+    # dropping the cached workspaces while builds are in flight on the side
+    # streams does not disturb them, and later builds get fresh ones
+    for i, s in enumerate(streams):
+        fif.build(halves[i], grid, vis, field=fields[i], stream=s)
+    fif.release_workspaces()
+    again = fif.build(halves[0], grid, vis, prec=fif.FP32_COMP)
+    torch.cuda.synchronize()
+    for i in range(2):
+        assert torch.equal(fields[i].buffer, ref[i].buffer)
+    assert torch.equal(again.buffer, ref[0].buffer)
