@@ -302,7 +302,10 @@ fif_status fif_gp_export(const fif_gp_field* field, const int64_t* voxel_ids, in
  * dL/dout = 1) on that request alone: a pose's arithmetic does not depend on
  * the other poses of a launch.  The request buffers must be ready on the
  * device before the call and stay allocated until it returns; the call
- * returns after all work has completed.
+ * returns after all work has completed.  The run uses the current device
+ * (where the fields, requests and workspace must live); the workspace holds
+ * the streams' batch buffers for the whole call, so calls that overlap in time
+ * need workspaces of their own.
  * Errors: FIF_EINVAL (before anything is enqueued) for invalid fields,
  * requests (field index, kind, m < 1, NULL or misaligned buffers, a request
  * larger than hbm_budget or max_batch) or configuration; FIF_ENOMEM for a
