@@ -51,3 +51,22 @@ def test_counters_follow_the_source_hash(tmp_path, monkeypatch):
     (prof / "counters.json").write_text(json.dumps(rec))
     assert bench.counter_traffic("fif::query_info_pipe_kernel") is None
     assert bench.counter_flops("fif::build_kernel<1, 0>", bench.BUILD_SOURCES) is None
+
+
+def test_morton_key_of_the_sorted_leg():
+    """The sorted-order leg's key interleaves the cell's x, y, z bits (x lowest);
+    checked against a bit-by-bit interleave."""
+    import numpy as np
+    import torch
+
+    rng = np.random.default_rng(5)
+    cells = rng.integers(0, 1024, size=(500, 3))
+    t = torch.from_numpy(cells).to(torch.int64)
+    key = (bench._spread10(t[:, 0]) | (bench._spread10(t[:, 1]) << 1)
+           | (bench._spread10(t[:, 2]) << 2)).tolist()
+    for (i, j, k), got in zip(cells.tolist(), key):
+        want = 0
+        for b in range(10):
+            want |= ((i >> b) & 1) << (3 * b) | ((j >> b) & 1) << (3 * b + 1) \
+                | ((k >> b) & 1) << (3 * b + 2)
+        assert got == want
