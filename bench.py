@@ -32,6 +32,7 @@ FP32_PEAK_TFLOPS = 157.3
 RECORD_BYTES_USED = 66 * 4          # moment scalars read per corner (FP32 field)
 POSE_BYTES = 7 * 4                  # t (3) + q (4), float32
 OUT_BYTES_3 = 3 * 8                 # three FP64 metrics
+TRACE_RECORD_BYTES_USED = 10 * 4    # trace factors read per corner (FP32 trace field)
 # FP32 flops of one contributing build pair in the moment form: 35 monomial
 # products, 25 adds, 41 FMAs (2 flops), 3 (u) + 1 (rn^2) products, d and n^2
 # (8), 1 rsqrt
@@ -59,6 +60,8 @@ def parse():
     ap.add_argument("--no-sweep", action="store_true", help="skip the optimal-view sweep leg")
     ap.add_argument("--no-sorted", action="store_true",
                     help="skip the query on the same poses in Morton order")
+    ap.add_argument("--no-trace", action="store_true", help="skip the trace-field leg")
+    ap.add_argument("--no-update", action="store_true", help="skip the incremental-update leg")
     ap.add_argument("--no-gp", action="store_true", help="skip the GP visibility leg")
     ap.add_argument("--no-precision", action="store_true",
                     help="skip the precision sweep (1M landmarks, three field precisions)")
@@ -310,6 +313,12 @@ def main():
     if not args.no_sorted and "query" in phases:
         res["query_sorted"] = sorted_leg(fif, torch, g, field, t_d, q_d, metrics, out, dev)
 
+    if not args.no_trace and "query" in phases:
+        res["trace_field"] = trace_leg(fif, torch, lm_d, grid, vis, t_d, q_d, out, dev)
+
+    if not args.no_update:
+        res["update"] = update_leg(fif, torch, scenes, grid, vis, field, dev)
+
     if not args.no_gp:
         res["gp"] = gp_leg(fif, torch, scenes, lm_d, grid, vis, t_d, q_d, contrib, dev)
 
@@ -485,6 +494,74 @@ def sorted_leg(fif, torch, g, field, t_d, q_d, metrics, out_random, dev, reps=5)
     return {"order": "Morton (Z) order of the floor voxel", "ms": med,
             "queries_per_s": m / (med / 1e3), "timing": "back-to-back, median of 5",
             "bitwise_same_as_random_order": same}
+
+
+def _median_ms(torch, fn, reps):
+    fn()
+    torch.cuda.synchronize()
+    ms = []
+    for _ in range(reps):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        fn()
+        e1.record()
+        torch.cuda.synchronize()
+        ms.append(e0.elapsed_time(e1))
+    return float(np.median(ms))
+
+
+def trace_leg(fif, torch, lm_d, grid, vis, t_d, q_d, out_info, dev):
+    """Trace field (eq:general_trace_pif): 10 factors per voxel, built from the
+    same landmarks, and the trace of the same 10M poses from it.  Its answers
+    are compared with the trace column of the information field's query."""
+    ft = fif.Field(grid, vis, fif.FP32_COMP, fif.KIND_TRACE, device=dev)
+    b_ms = _median_ms(torch, lambda: fif.build(lm_d, grid, vis, field=ft), 3)
+    m = t_d.shape[0]
+    out = torch.empty((m, 1), dtype=torch.float64, device=dev)
+    q_ms = _median_ms(torch, lambda: fif.query(ft, t_d, q_d, fif.TRACE, out=out), 5)
+    ref = out_info[:, 0]
+    rel = ((out[:, 0] - ref).abs() / ref.abs().clamp_min(1e-300)).max().item()
+    qbytes = m * (8 * TRACE_RECORD_BYTES_USED + POSE_BYTES + 8)
+    gbs = qbytes / (q_ms / 1e3) / 1e9
+    log(f"trace field: build {b_ms:.1f} ms, 10M trace queries {q_ms:.3f} ms back-to-back "
+        f"({gbs:.0f} GB/s), max rel. diff from the information field's trace {rel:.2e}")
+    return {"build_ms": b_ms, "query_ms": q_ms, "queries_per_s": m / (q_ms / 1e3),
+            "timing": "back-to-back, median", "query_gbs": gbs,
+            "query_hbm_frac": gbs / HBM_PEAK_GBS, "bytes_per_query": qbytes / m,
+            "max_rel_diff_vs_information_trace": rel}
+
+
+def update_leg(fif, torch, scenes, grid, vis, field, dev, n=1000, reps=3):
+    """Incremental update (Sec. VI-A, online update): a newly seen piece of wall
+    (1,000 landmarks) added to a copy of the resident field and removed again;
+    times of both, and how far the field is from the original afterwards."""
+    f = fif.Field(grid, vis, field.prec, field.kind, device=dev)
+    f.buffer.copy_(field.buffer)
+    patch = torch.from_numpy(scenes.wall_patch(n)).to(dev)
+    add, rem = [], []
+    for _ in range(reps + 1):
+        for sign, lst in ((+1, add), (-1, rem)):
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record()
+            fif.update(f, patch, sign)
+            e1.record()
+            torch.cuda.synchronize()
+            lst.append(e0.elapsed_time(e1))
+    add_ms, rem_ms = float(np.median(add[1:])), float(np.median(rem[1:]))
+    rng = np.random.default_rng(8)
+    ids = torch.from_numpy(np.sort(rng.choice(grid.n_voxels, 4096, replace=False))).to(dev)
+    a = fif.export_blocks(f, ids).reshape(ids.numel(), -1)
+    b = fif.export_blocks(field, ids).reshape(ids.numel(), -1)
+    drift = ((a - b).abs().amax(dim=1) / b.abs().amax(dim=1).clamp_min(1e-300)).max().item()
+    pairs = grid.n_voxels * n
+    log(f"update: +{n} landmarks {add_ms:.2f} ms, -{n} {rem_ms:.2f} ms "
+        f"({pairs / (add_ms / 1e3):.2e} tested pairs/s); after {reps + 1} add/remove cycles "
+        f"blocks within {drift:.1e} of the original")
+    return {"landmarks": n, "add_ms": add_ms, "remove_ms": rem_ms,
+            "tested_pairs_per_s": pairs / (add_ms / 1e3), "cycles": reps + 1,
+            "max_rel_block_drift_after_cycles": drift}
 
 
 def sweep_leg(fif, torch, scenes, g, field, dev, n_pos=200, n_axes=4096, reps=5):

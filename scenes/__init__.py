@@ -130,6 +130,22 @@ def building_scene(n_landmarks: int = 100_000, seed: int = SEED_SCENE + 2,
     return lm, grid, Vis(r_max=r_max)
 
 
+def wall_patch(n: int = 1000, seed: int = SEED_SCENE + 8, centre=(3.0, -2.0, 0.0),
+               size: float = 2.0, noise: float = 0.05) -> np.ndarray:
+    """A newly observed piece of wall for incremental updates: n landmarks on a
+    vertical size x size square at `centre` with a random azimuth, offset along
+    its normal by N(0, noise^2)."""
+    rng = np.random.default_rng(seed)
+    az = rng.uniform(0.0, math.pi)
+    s = rng.uniform(-0.5, 0.5, n) * size
+    zz = rng.uniform(-0.5, 0.5, n) * size
+    off = rng.normal(0.0, noise, n)
+    c = np.asarray(centre, np.float64)
+    return np.stack([c[0] + s * math.cos(az) - off * math.sin(az),
+                     c[1] + s * math.sin(az) + off * math.cos(az),
+                     c[2] + zz], axis=1)
+
+
 def building_poses(grid: Grid, m: int, seed: int = SEED_POSES + 2, dtype=np.float32):
     rng = np.random.default_rng(seed)
     t = uniform_in_hull(rng, grid, m)
