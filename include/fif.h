@@ -138,10 +138,13 @@ fif_status fif_build(const double* landmarks, int64_t n_landmarks, fif_field* fi
 
 /* Incremental update (Sec. VI-A, "Offline Processing vs. Online Update"): add
  * (sign = +1) or remove (sign = -1) the contribution of the given landmarks to
- * every voxel whose centre has them in range.  Same landmark layout as
- * fif_build. */
+ * every voxel whose centre has them in range.  Same landmark layout and
+ * workspace as fif_build (fif_workspace_bytes() for n_landmarks): with a
+ * workspace the added landmarks are ordered spatially and voxel tiles out of
+ * range of a whole batch of them skip it; with NULL every voxel tests every
+ * added landmark.  Both give the same sums up to rounding order. */
 fif_status fif_update(const double* landmarks, int64_t n_landmarks, int32_t sign,
-                      fif_field* field, void* stream);
+                      fif_field* field, void* workspace, size_t workspace_bytes, void* stream);
 
 /* Batched pose query (Sec. VI-A, eq:fim_separation): F = V_I(R) C_I(t) with
  * C_I(t) interpolated from the voxel centres, reduced to the requested metrics

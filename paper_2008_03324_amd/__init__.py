@@ -91,7 +91,8 @@ EXPORTS = {
     "fif_build": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int64, ctypes.POINTER(CField),
                                    ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p]),
     "fif_update": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32,
-                                    ctypes.POINTER(CField), ctypes.c_void_p]),
+                                    ctypes.POINTER(CField), ctypes.c_void_p, ctypes.c_size_t,
+                                    ctypes.c_void_p]),
     "fif_query": (ctypes.c_int32, [ctypes.POINTER(CField), ctypes.c_void_p, ctypes.c_void_p,
                                    ctypes.c_int64, ctypes.c_uint32, ctypes.c_int32,
                                    ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
@@ -304,10 +305,16 @@ def build(landmarks: torch.Tensor, grid: Grid, vis: Vis, prec: int = FP32_COMP,
 
 
 @_on_stream
-def update(field: Field, landmarks: torch.Tensor, sign: int, stream=None) -> Field:
+def update(field: Field, landmarks: torch.Tensor, sign: int, sort: bool = True,
+           stream=None) -> Field:
+    """Add (sign +1) or remove (sign -1) landmarks.  With sort (the default) the
+    added landmarks are ordered spatially in a workspace so that voxel tiles out
+    of range of a whole batch of them skip it."""
     lm = _dev(landmarks, torch.float64, "landmarks", 3)
+    ws = workspace(field.grid, lm.shape[0], field.prec, lm.device) if sort else None
     _check(lib().fif_update(_ptr(lm), lm.shape[0], int(sign), ctypes.byref(field.cstruct),
-                            _stream(stream)), "fif_update")
+                            _ptr(ws), ws.numel() if ws is not None else 0, _stream(stream)),
+           "fif_update")
     return field
 
 

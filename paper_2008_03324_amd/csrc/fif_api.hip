@@ -195,13 +195,14 @@ fif_status fif_build(const double* landmarks, int64_t n_landmarks, fif_field* fi
 }
 
 fif_status fif_update(const double* landmarks, int64_t n_landmarks, int32_t sign,
-                      fif_field* field, void* stream) {
+                      fif_field* field, void* workspace, size_t workspace_bytes, void* stream) {
   if (sign != 1 && sign != -1) return fail(FIF_EINVAL, "sign must be +1 or -1%s");
   if (n_landmarks == 0) {
     fif_status st = check_field(field);
     return st;
   }
-  return build_common(landmarks, n_landmarks, field, 1, sign, nullptr, 0, stream, "fif_update");
+  return build_common(landmarks, n_landmarks, field, 1, sign, workspace, workspace_bytes, stream,
+                      "fif_update");
 }
 
 static int metric_cols(uint32_t metrics) {

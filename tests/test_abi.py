@@ -72,7 +72,7 @@ def test_host_side_validation_returns_einval():
     f.data = 4096
     assert L.fif_build(None, 10, ctypes.byref(f), None, 0, None) == -1  # NULL landmarks
     assert L.fif_build(None, -1, ctypes.byref(f), None, 0, None) == -1
-    assert L.fif_update(None, 1, 2, ctypes.byref(f), None) == -1  # bad sign
+    assert L.fif_update(None, 1, 2, ctypes.byref(f), None, 0, None) == -1  # bad sign
     assert L.fif_query(ctypes.byref(f), None, None, 5, 0, 0, None, None, None) == -1  # no metric
     assert L.fif_query(ctypes.byref(f), None, None, 5, 1, 3, None, None, None) == -1  # interp
     assert L.fif_query(ctypes.byref(f), None, None, 5, 1, 0, None, None, None) == -1  # NULL t
@@ -108,7 +108,7 @@ def test_host_side_validation_returns_einval():
         fw = fif.CField(fif.Grid((0.0, 0.0, 0.0), 0.5, shape).c(), vis.c(), fif.FP32_COMP,
                         fif.KIND_INFO, 4096)
         assert L.fif_build(None, 0, ctypes.byref(fw), None, 0, None) == -4, shape
-        assert L.fif_update(None, 5, 1, ctypes.byref(fw), None) == -1  # NULL landmarks
+        assert L.fif_update(None, 5, 1, ctypes.byref(fw), None, 0, None) == -1  # NULL landmarks
 
 
 def test_binding_fails_loudly_without_library(tmp_path, monkeypatch):

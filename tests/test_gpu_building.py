@@ -245,21 +245,24 @@ def test_trace_field_matches_information_field(fif, bld):
         assert np.abs(got[a] - CT).max() <= 1e-4 * np.abs(CT).max()
 
 
-def test_incremental_update_equals_rebuild(fif, bld):
-    """Sec. VI-A: adding then removing landmarks updates the factors additively."""
-    print("case: incremental update", flush=True)
+@pytest.mark.parametrize("sort", [True, False])
+def test_incremental_update_equals_rebuild(fif, bld, sort):
+    """Sec. VI-A: adding then removing landmarks updates the factors additively
+    (the added landmarks spatially sorted and batch-culled, or tested by every
+    voxel)."""
+    print(f"case: incremental update, sort={sort}", flush=True)
     lm = bld["lm"]
     lm_a = torch.from_numpy(np.ascontiguousarray(lm[:60_000])).cuda()
     lm_b = torch.from_numpy(np.ascontiguousarray(lm[60_000:])).cuda()
     f = fif.build(lm_a, bld["grid"], bld["vis"], prec=fif.FP64)
-    fif.update(f, lm_b, +1)
+    fif.update(f, lm_b, +1, sort=sort)
     full = fif.build(bld["lm_d"], bld["grid"], bld["vis"], prec=fif.FP64)
     rng = np.random.default_rng(27)
     ids = torch.from_numpy(np.sort(rng.choice(bld["grid"].n_voxels, 500, replace=False))).cuda()
     a = fif.export_blocks(f, ids).cpu().numpy()
     b = fif.export_blocks(full, ids).cpu().numpy()
     assert np.abs(a - b).max() <= 1e-9 * np.abs(b).max()
-    fif.update(f, lm_b, -1)
+    fif.update(f, lm_b, -1, sort=sort)
     part = fif.build(lm_a, bld["grid"], bld["vis"], prec=fif.FP64)
     a = fif.export_blocks(f, ids).cpu().numpy()
     c = fif.export_blocks(part, ids).cpu().numpy()
