@@ -557,10 +557,10 @@ def update_leg(fif, torch, scenes, grid, vis, field, dev, n=1000, reps=3):
     drift = ((a - b).abs().amax(dim=1) / b.abs().amax(dim=1).clamp_min(1e-300)).max().item()
     pairs = grid.n_voxels * n
     log(f"update: +{n} landmarks {add_ms:.2f} ms, -{n} {rem_ms:.2f} ms "
-        f"({pairs / (add_ms / 1e3):.2e} tested pairs/s); after {reps + 1} add/remove cycles "
-        f"blocks within {drift:.1e} of the original")
+        f"({pairs / (add_ms / 1e3):.2e} voxel-landmark pairs/s over the grid); after "
+        f"{reps + 1} add/remove cycles blocks within {drift:.1e} of the original")
     return {"landmarks": n, "add_ms": add_ms, "remove_ms": rem_ms,
-            "tested_pairs_per_s": pairs / (add_ms / 1e3), "cycles": reps + 1,
+            "grid_pairs_per_s": pairs / (add_ms / 1e3), "cycles": reps + 1,
             "max_rel_block_drift_after_cycles": drift}
 
 
