@@ -22,7 +22,8 @@
  *   positions up to 2^31 - 1 (FIF_EINVAL beyond).  A call whose input is
  *   longer than one dispatch can cover (2^30 work-items) is split into several
  *   launches on the same stream; the results are the same as in one launch.
- *   fif_build and fif_update take one launch per call and return
+ *   fif_build and fif_update cover the grid with one launch of the build
+ *   kernel (after the landmark sort when given a workspace) and return
  *   FIF_EUNSUPPORTED for grids with nx > 134,217,720, ny > 524,280 or
  *   nz > 262,140.
  *
@@ -118,8 +119,9 @@ typedef struct {
  * an invalid grid, precision or kind. */
 size_t fif_field_bytes(const fif_grid* grid, int32_t prec, int32_t kind);
 
-/* Bytes of the optional fif_build workspace (0 when n_landmarks <= 0 or the
- * grid/precision is invalid).  With it, fif_build first orders the landmarks
+/* Bytes of the optional fif_build / fif_update workspace for n_landmarks
+ * landmarks (0 when n_landmarks <= 0 or the grid/precision is invalid).  With
+ * it, fif_build first orders the landmarks
  * spatially (Morton keys, stable radix sort) and skips, per voxel tile, every
  * batch of landmarks whose bounding box is out of range; with a NULL workspace
  * every (voxel, landmark) pair is tested in input order.  Both orders give the
