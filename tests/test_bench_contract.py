@@ -70,3 +70,20 @@ def test_morton_key_of_the_sorted_leg():
             want |= ((i >> b) & 1) << (3 * b) | ((j >> b) & 1) << (3 * b + 1) \
                 | ((k >> b) & 1) << (3 * b + 2)
         assert got == want
+
+
+def test_committed_bench_line_has_the_contract_keys():
+    """The bench line kept under profiles/ carries every key of the JSON contract,
+    including the roofline and CPU-baseline objects."""
+    line = open(os.path.join(ROOT, "profiles", "bench_building_10M.json")).read()
+    d = json.loads(line.strip().splitlines()[-1])
+    for k in ("metric", "value", "unit", "n_gpus", "steps", "warmup", "ms_per_step",
+              "higher_is_better", "scaling", "vs_baseline", "dtype", "data", "config",
+              "roofline", "cpu_baseline"):
+        assert k in d, k
+    assert d["n_gpus"] == 1 and d["value"] > 0 and "workload" in d["config"]
+    r = d["roofline"]
+    assert r["bound"] in ("hbm", "mfma", "alu") and r["unit"] in ("GB/s", "TFLOP/s")
+    assert abs(r["frac"] - r["achieved"] / r["peak"]) < 1e-9 and "traffic" in r
+    c = d["cpu_baseline"]
+    assert c["kind"] == "oracle" and c["cores"] >= 1 and c["value"] > 0 and c["sample"]
