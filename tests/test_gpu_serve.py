@@ -142,3 +142,35 @@ def test_native_admission_and_errors(setup):
     assert L.fif_serve_run(cf, len(fields), one, 1, ctypes.byref(cfg),
                            ctypes.c_void_p(ws.data_ptr()), need, ctypes.byref(el)) == -1
     assert b"field index" in L.fif_last_error()
+
+
+def test_native_fp64_fields():
+    """fif_serve_run on FP64 fields: poses, gradients and results move as doubles
+    through the pack and unpack kernels; every request equals its direct call."""
+    import paper_2008_03324_amd as fif
+    from paper_2008_03324_amd import serve
+    print("case: native serving loop on two FP64 fields", flush=True)
+    fields, pools = [], []
+    for i, shape in enumerate(((20, 20, 10), (32, 24, 8))):
+        lm, g, v = scenes.building_scene(n_landmarks=3000, seed=81 + i, shape=shape, h=0.25,
+                                         r_max=6.0)
+        grid = fif.Grid(g.origin, g.h, g.shape)
+        vis = fif.Vis(v.half_fov, v.v_alpha, v.sigma, v.r_min, v.r_max)
+        fields.append(fif.build(torch.tensor(lm, device="cuda"), grid, vis, prec=fif.FP64))
+        pt, pq = scenes.building_poses(g, 4000, seed=84 + i, dtype=np.float64)
+        tt, tq = scenes.trajectories(g, 80, 64, seed=86 + i)
+        pools.append({"plan": (torch.from_numpy(pt).cuda(), torch.from_numpy(pq).cuda()),
+                      "opt": (torch.from_numpy(tt.reshape(-1, 3).astype(np.float64)).cuda(),
+                              torch.from_numpy(tq.reshape(-1, 4).astype(np.float64)).cuda())})
+    specs = scenes.request_stream(2, 2000.0, 40, 4000, 80, seed=88)
+    reqs = _make(serve, pools, specs)
+    assert {r.kind for r in reqs} == {"plan", "opt"}
+    srv = serve.NativeServer(fields, n_streams=2, co_batch=True, max_batch=8192, max_inflight=8)
+    assert srv.run(reqs, realtime=False) > 0
+    for r in reqs:
+        assert r.out.dtype == torch.float64 and r.t.dtype == torch.float64
+        out, gt, gphi = _alone(fif, fields, r)
+        assert torch.equal(r.out.nan_to_num(7.0), out.nan_to_num(7.0)), r.rid
+        if r.kind == "opt":
+            assert r.grad_t.dtype == torch.float64
+            assert torch.equal(r.grad_t, gt) and torch.equal(r.grad_phi, gphi), r.rid
