@@ -125,7 +125,9 @@ size_t fif_field_bytes(const fif_grid* grid, int32_t prec, int32_t kind);
  * spatially (Morton keys, stable radix sort) and skips, per voxel tile, every
  * batch of landmarks whose bounding box is out of range; with a NULL workspace
  * every (voxel, landmark) pair is tested in input order.  Both orders give the
- * same field up to rounding, each deterministic. */
+ * same field up to rounding, each deterministic.  The sort (rocPRIM radix sort)
+ * enqueues a hipMemsetAsync: keep calls given a workspace out of captured HIP
+ * graphs (pass NULL there). */
 size_t fif_workspace_bytes(const fif_grid* grid, int64_t n_landmarks, int32_t prec);
 
 /* Build a field (Sec. VI-A): for every voxel centre t_v,
