@@ -141,6 +141,24 @@ def trace_factor(landmarks, t, sigma, r_min=0.0, r_max=np.inf) -> np.ndarray:
     return out
 
 
+def trace_build(landmarks, origin, h, shape, sigma, r_min=0.0, r_max=np.inf,
+                voxel_ids=None) -> np.ndarray:
+    """Trace factors C_Tr of the listed voxels (all when voxel_ids is None): (n, 10)."""
+    lm = _f64(landmarks, 3)
+    g = _grid(origin, h, shape)
+    if voxel_ids is None:
+        n = int(np.prod(shape))
+        ids = None
+    else:
+        ids = np.ascontiguousarray(voxel_ids, dtype=np.int64)
+        n = ids.shape[0]
+    out = np.zeros((n, 10))
+    lib().oracle_trace_build(_p(lm), ctypes.c_int64(lm.shape[0]), ctypes.byref(g),
+                             ctypes.c_double(sigma), ctypes.c_double(r_min),
+                             ctypes.c_double(r_max), _p(ids), ctypes.c_int64(n), _p(out))
+    return out
+
+
 def build(landmarks, origin, h, shape, sigma, r_min=0.0, r_max=np.inf,
           voxel_ids=None) -> np.ndarray:
     """Factors of the listed voxels (all when voxel_ids is None): (n, 10, 6, 6)."""
@@ -220,6 +238,38 @@ def query(field: Field, alpha, v_alpha, t, q, metrics_mask, interp=0):
                             ctypes.c_int(interp), _p(out), _p(flags))
     if rc != 0:
         raise KeyError("oracle field is missing a voxel the query needs")
+    return out, flags
+
+
+class TraceField:
+    """A trace-factor field (eq:general_trace_pif) held by the oracle."""
+
+    def __init__(self, CT, origin, h, shape, voxel_ids=None):
+        self.C = np.ascontiguousarray(CT, dtype=np.float64).reshape(-1, 10)
+        self.origin, self.h, self.shape = tuple(origin), float(h), tuple(int(s) for s in shape)
+        if voxel_ids is not None:
+            order = np.argsort(voxel_ids, kind="stable")
+            self.ids = np.ascontiguousarray(np.asarray(voxel_ids, np.int64)[order])
+            self.C = np.ascontiguousarray(self.C[order])
+        else:
+            self.ids = None
+        self.grid = _grid(self.origin, self.h, self.shape)
+
+
+def trace_query(field: TraceField, alpha, v_alpha, t, q, interp=0):
+    """Trace of the FIM from a trace field: (traces [m], flags [m])."""
+    t = _f64(t, 3)
+    q = _f64(q, 4)
+    m = t.shape[0]
+    out = np.zeros(m)
+    flags = np.zeros(m, np.uint8)
+    n = field.ids.shape[0] if field.ids is not None else field.C.shape[0]
+    rc = lib().oracle_trace_query(_p(field.C), _p(field.ids), ctypes.c_int64(n),
+                                  ctypes.byref(field.grid), ctypes.c_double(alpha),
+                                  ctypes.c_double(v_alpha), _p(t), _p(q), ctypes.c_int64(m),
+                                  ctypes.c_int(interp), _p(out), _p(flags))
+    if rc != 0:
+        raise KeyError("oracle trace field is missing a voxel the query needs")
     return out, flags
 
 

@@ -411,16 +411,21 @@ static void contract(const double* C, const double vr[10], double F[36]) {
 /* Interpolated factor and FIM at one pose from a field given as a lookup:
  * either the whole field (field[v*360]) or, when field_ids != NULL, a sorted
  * table field_ids[n_field] of the voxels present. */
-static const double* field_at(const double* field, const int64_t* field_ids, int64_t n_field,
-                              int64_t v) {
-  if (!field_ids) return field + v * 360;
+static const double* row_at(const double* field, const int64_t* ids, int64_t n_field,
+                            int64_t per, int64_t v) {
+  if (!ids) return field + v * per;
   int64_t lo = 0, hi = n_field - 1;
   while (lo <= hi) {
     int64_t mid = (lo + hi) / 2;
-    if (field_ids[mid] == v) return field + mid * 360;
-    if (field_ids[mid] < v) lo = mid + 1; else hi = mid - 1;
+    if (ids[mid] == v) return field + mid * per;
+    if (ids[mid] < v) lo = mid + 1; else hi = mid - 1;
   }
   return NULL;
+}
+
+static const double* field_at(const double* field, const int64_t* field_ids, int64_t n_field,
+                              int64_t v) {
+  return row_at(field, field_ids, n_field, 360, v);
 }
 
 /* Query one pose: returns the clamp flag, fills F (6x6) and Cbar (10 blocks). */
@@ -493,6 +498,63 @@ int oracle_query_fim(const double* field, const int64_t* field_ids, int64_t n_fi
     if (query_one(field, field_ids, n_field, g, k, t + 3 * a, q + 4 * a, interp,
                   F_out + 36 * a, Cbar, vr, z) < 0)
       err = 1;
+  }
+  return err ? -1 : 0;
+}
+
+/* Trace factors of the listed voxels (all when voxel_ids == NULL), the trace
+ * field of eq:general_trace_pif: CT[n_vox][10]. */
+void oracle_trace_build(const double* lm, int64_t L, const orc_grid* g, double sigma,
+                        double r_min, double r_max, const int64_t* voxel_ids, int64_t n_vox,
+                        double* CT) {
+#pragma omp parallel for schedule(dynamic, 4)
+  for (int64_t a = 0; a < n_vox; ++a) {
+    int64_t v = voxel_ids ? voxel_ids[a] : a;
+    double t[3];
+    oracle_voxel_centre(g, v, t);
+    oracle_trace_factor(lm, L, t, sigma, r_min, r_max, CT + a * 10);
+  }
+}
+
+/* Trace-field query (eq:fim_trace_separation, eq:general_trace_pif): the
+ * trace factor is retrieved at t like the information factor (trilinear over
+ * the 8 voxel centres, or the nearest one; Sec. VI-A), then
+ *   Tr F = sum_k vr_k(z) CTbar_k.
+ * field: [n_field][10]; out[m]; flags[m] bit0 = clamped (may be NULL).
+ * Returns 0, or -1 if a needed voxel is absent. */
+int oracle_trace_query(const double* field, const int64_t* field_ids, int64_t n_field,
+                       const orc_grid* g, double alpha, double v_alpha, const double* t,
+                       const double* q, int64_t m, int interp, double* out, uint8_t* flags) {
+  double k[3];
+  oracle_quad_coeffs(alpha, v_alpha, k);
+  int err = 0;
+#pragma omp parallel for schedule(static)
+  for (int64_t a = 0; a < m; ++a) {
+    double R[9], z[3], vr[10], CT[10] = {0};
+    oracle_quat_to_R(q + 4 * a, R);
+    z[0] = R[2]; z[1] = R[5]; z[2] = R[8];
+    oracle_vr(k, z, vr);
+    int clamped, missing = 0;
+    if (interp == 1) {
+      int64_t id;
+      clamped = nearest(g, t + 3 * a, &id);
+      const double* C = row_at(field, field_ids, n_field, 10, id);
+      if (!C) missing = 1; else memcpy(CT, C, sizeof CT);
+    } else {
+      int64_t ids[8];
+      double w[8], dw[8][3];
+      clamped = trilinear(g, t + 3 * a, ids, w, dw);
+      for (int j = 0; j < 8; ++j) {
+        const double* C = row_at(field, field_ids, n_field, 10, ids[j]);
+        if (!C) { missing = 1; break; }
+        for (int e = 0; e < 10; ++e) CT[e] += w[j] * C[e];
+      }
+    }
+    if (missing) { err = 1; continue; }
+    double s = 0.0;
+    for (int e = 0; e < 10; ++e) s += vr[e] * CT[e];
+    out[a] = s;
+    if (flags) flags[a] = (uint8_t)(clamped ? 1 : 0);
   }
   return err ? -1 : 0;
 }
@@ -674,18 +736,6 @@ void oracle_gp_build(const double* lm, int64_t L, const orc_grid* g, double sigm
   }
 }
 
-static const double* gp_field_at(const double* field, const int64_t* ids, int64_t n_field,
-                                 int64_t per, int64_t v) {
-  if (!ids) return field + v * per;
-  int64_t lo = 0, hi = n_field - 1;
-  while (lo <= hi) {
-    int64_t mid = (lo + hi) / 2;
-    if (ids[mid] == v) return field + mid * per;
-    if (ids[mid] < v) lo = mid + 1; else hi = mid - 1;
-  }
-  return NULL;
-}
-
 /* GP field query (eq:fim_separation with vr = K_z): the factor is interpolated
  * at t (trilinear over the 8 voxel centres, or the nearest one), then
  *   F = sum_g vr_g(z) Cbar_g,   or for trace fields Tr = sum_g vr_g Cbar_Tr,g.
@@ -711,14 +761,14 @@ int oracle_gp_query(const double* field, const int64_t* ids, int64_t n_field, co
     if (interp == 1) {
       int64_t id;
       clamped = nearest(g, t + 3 * a, &id);
-      const double* C = gp_field_at(field, ids, n_field, per, id);
+      const double* C = row_at(field, ids, n_field, per, id);
       if (!C) missing = 1; else memcpy(Cbar, C, (size_t)per * sizeof(double));
     } else {
       int64_t vid[8];
       double w[8], dw[8][3];
       clamped = trilinear(g, t + 3 * a, vid, w, dw);
       for (int j = 0; j < 8 && !missing; ++j) {
-        const double* C = gp_field_at(field, ids, n_field, per, vid[j]);
+        const double* C = row_at(field, ids, n_field, per, vid[j]);
         if (!C) { missing = 1; break; }
         for (int64_t e = 0; e < per; ++e) Cbar[e] += w[j] * C[e];
       }
@@ -871,9 +921,12 @@ int oracle_query_grad(const double* field, const int64_t* field_ids, int64_t n_f
     int col = 0;
     for (uint32_t bit = 1; bit <= 4; bit <<= 1) {
       if (!(metrics & bit)) continue;
+      double up = dL_dout[a * ncols + col++];
+      /* a metric with zero weight is not part of L: its derivative (NaN for
+       * the log-det of a FIM that is not positive definite) does not enter */
+      if (up == 0.0) continue;
       double Gm[36];
       metric_grad(F, bit, Gm);
-      double up = dL_dout[a * ncols + col++];
       for (int e = 0; e < 36; ++e) G[e] += up * Gm[e];
     }
     int64_t ids[8];

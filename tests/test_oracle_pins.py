@@ -313,6 +313,107 @@ def test_interpolation_properties():
     np.testing.assert_allclose(Fs, np.repeat(Fs[:1], 10, 0), atol=1e-12)
 
 
+def _random_sym_field(rng, n):
+    C = rng.standard_normal((n, 10, 6, 6))
+    return C + C.transpose(0, 1, 3, 2)
+
+
+def test_nearest_rule_off_centre():
+    """Sec. VI-A retrieves a factor by nearest neighbour or by interpolation;
+    the nearest voxel is read as round-half-up per axis.  Off the voxel centres
+    (a grid spacing that is not a binary fraction, an origin off zero): 0.4 h
+    from a centre keeps that voxel, 0.6 h takes the neighbour, on every axis and
+    on several axes at once; on a grid where the midpoints are exact, +0.5 h
+    takes the upper voxel and -0.5 h keeps the centre's own."""
+    rng = np.random.default_rng(14)
+    k = oracle.quad_coeffs(ALPHA, 0.8)
+    q = scenes.haar_quaternions(rng, 1)
+    vr = oracle.vr(k, oracle.quat_to_R(q[0])[:, 2])
+
+    def check(origin, h, shape, cases):
+        n = int(np.prod(shape))
+        C = _random_sym_field(rng, n)
+        field = oracle.Field(C, origin, h, shape)
+        for ijk, s, want in cases:
+            t = np.asarray(origin) + (np.asarray(ijk) + np.asarray(s)) * h
+            v = want[0] + shape[0] * (want[1] + shape[1] * want[2])
+            F = oracle.query_fim(field, ALPHA, 0.8, t[None], q, interp=1)[0]
+            ref = np.einsum("k,kij->ij", vr, C[v])
+            assert np.abs(F - ref).max() <= 1e-13 * np.abs(ref).max(), (ijk, s, want)
+
+    origin, h, shape = (0.13, -0.71, 0.37), 0.3, (5, 4, 3)
+    cases = []
+    for ijk in ((2, 1, 1), (1, 2, 1), (3, 2, 1)):
+        for ax in range(3):
+            for s, di in ((-0.6, -1), (-0.4, 0), (0.4, 0), (0.6, 1)):
+                off = [0.0, 0.0, 0.0]
+                off[ax] = s
+                want = list(ijk)
+                want[ax] += di
+                cases.append((ijk, off, want))
+        cases.append((ijk, (0.4, -0.6, 0.6), (ijk[0], ijk[1] - 1, ijk[2] + 1)))
+        cases.append((ijk, (-0.45, 0.55, -0.3), (ijk[0], ijk[1] + 1, ijk[2])))
+    check(origin, h, shape, cases)
+    # exact midpoints: h and the origin are binary fractions
+    origin, h, shape = (0.25, -0.5, 1.0), 0.5, (4, 4, 3)
+    ties = []
+    for ax in range(3):
+        up_, down = [0.0] * 3, [0.0] * 3
+        up_[ax], down[ax] = 0.5, -0.5
+        want = [1, 1, 1]
+        want[ax] = 2
+        ties.append(((1, 1, 1), up_, want))
+        ties.append(((1, 1, 1), down, (1, 1, 1)))
+    ties.append(((1, 2, 0), (0.5, -0.5, 0.5), (2, 2, 1)))
+    check(origin, h, shape, ties)
+
+
+def test_hull_clamp_is_constant_extension():
+    """Reading of the grid boundary (the paper is silent): a position outside
+    the hull of voxel centres takes the value at its projection onto the hull
+    (constant extension), for interpolation and nearest retrieval, on a field
+    that is not constant.  On a field linear in the voxel index a linear
+    extrapolation would differ from the hull value; the oracle returns the
+    hull value."""
+    rng = np.random.default_rng(15)
+    origin, h, shape = (-0.4, 0.2, 0.05), 0.35, (4, 3, 3)
+    n = int(np.prod(shape))
+    C = _random_sym_field(rng, n)
+    field = oracle.Field(C, origin, h, shape)
+    lo = np.asarray(origin)
+    hi = lo + (np.asarray(shape) - 1) * h
+    t = rng.uniform(lo - 2 * h, hi + 2 * h, (400, 3))
+    out = ((t < lo) | (t > hi)).any(axis=1)
+    t = t[out]
+    assert t.shape[0] > 100
+    q = scenes.haar_quaternions(rng, t.shape[0])
+    tc = np.clip(t, lo, hi)
+    for interp in (0, 1):
+        F = oracle.query_fim(field, ALPHA, 0.8, t, q, interp=interp)
+        Fc = oracle.query_fim(field, ALPHA, 0.8, tc, q, interp=interp)
+        scale = np.abs(Fc).max(axis=(1, 2))
+        assert (np.abs(F - Fc).max(axis=(1, 2)) <= 1e-12 * scale).all(), interp
+        _, fl = oracle.query(field, ALPHA, 0.8, t, q, 1, interp)
+        assert (fl & 1).all()
+    # linear in the x index: C_v = A + i_x B.  Beyond the upper x face (y, z
+    # inside) the value is A + (nx - 1) B, not A + g_x B with g_x > nx - 1.
+    A, B = _random_sym_field(rng, 2)
+    ix = np.arange(n) % shape[0]
+    CL = A[None] + ix[:, None, None, None] * B[None]
+    fl_ = oracle.Field(CL, origin, h, shape)
+    k = oracle.quad_coeffs(ALPHA, 0.8)
+    for dx in (0.3 * h, 1.7 * h):
+        tt = np.array([[hi[0] + dx, lo[1] + 0.37 * h, lo[2] + 1.2 * h]])
+        qq = scenes.haar_quaternions(rng, 1)
+        vr = oracle.vr(k, oracle.quat_to_R(qq[0])[:, 2])
+        want = np.einsum("k,kij->ij", vr, A + (shape[0] - 1) * B)
+        extrap = np.einsum("k,kij->ij", vr, A + (shape[0] - 1 + dx / h) * B)
+        for interp in (0, 1):
+            F = oracle.query_fim(fl_, ALPHA, 0.8, tt, qq, interp=interp)[0]
+            assert np.abs(F - want).max() <= 1e-12 * np.abs(want).max()
+            assert np.abs(F - extrap).max() > 1e-3 * np.abs(want).max()
+
+
 def test_clamp_and_nearest_flags():
     origin, h, shape = (0.0, 0.0, 0.0), 1.0, (3, 3, 3)
     C = np.ones((27, 10, 6, 6))
@@ -369,6 +470,51 @@ def test_additivity_and_trace_factor():
         z = rng.standard_normal(3); z /= np.linalg.norm(z)
         vr = oracle.vr(k, z)
         assert vr @ CT == pytest.approx(np.trace(np.einsum("k,kij->ij", vr, C)), rel=1e-12)
+
+
+def test_trace_field_query_equals_information_trace():
+    """eq:general_trace_pif: the trace field gives the trace of the FIM that the
+    information field gives, for interpolated and nearest retrieval, inside
+    and outside the hull; the built trace factors are the traces of the built
+    information factors."""
+    lm, grid, vis = scenes.tiny_scene(n_landmarks=300)
+    rng = np.random.default_rng(16)
+    t, q = scenes.tiny_poses(grid, 64, seed=78)
+    t[:8] += rng.uniform(-2.0, 2.0, (8, 3))  # some outside the hull
+    ids = oracle.corner_voxels(grid.origin, grid.h, grid.shape, t)
+    C = oracle.build(lm, grid.origin, grid.h, grid.shape, vis.sigma, voxel_ids=ids)
+    CT = oracle.trace_build(lm, grid.origin, grid.h, grid.shape, vis.sigma, voxel_ids=ids)
+    np.testing.assert_allclose(CT, np.trace(C, axis1=2, axis2=3), rtol=1e-12)
+    f = oracle.Field(C, grid.origin, grid.h, grid.shape, voxel_ids=ids)
+    tf = oracle.TraceField(CT, grid.origin, grid.h, grid.shape, voxel_ids=ids)
+    for interp in (0, 1):
+        ref, rfl = oracle.query(f, vis.half_fov, vis.v_alpha, t, q, 1, interp)
+        tr, fl = oracle.trace_query(tf, vis.half_fov, vis.v_alpha, t, q, interp)
+        np.testing.assert_allclose(tr, ref[:, 0], rtol=1e-12)
+        np.testing.assert_array_equal(fl & 1, rfl & 1)
+
+
+def test_zero_weight_metric_leaves_gradient_finite():
+    """The gradient of L = sum_c w_c s_c: a metric with w_c = 0 is not part of
+    L.  With v_alpha = 0.5 some FIMs are indefinite (log-det NaN); weights
+    (1, 1, 0) on (trace, lmin, logdet) give the finite gradient of trace +
+    lmin, the same as asking for those two metrics alone, while a nonzero
+    log-det weight on such a pose gives NaN."""
+    lm, grid, vis = scenes.tiny_scene(n_landmarks=200)
+    C = oracle.build(lm, grid.origin, grid.h, grid.shape, vis.sigma)
+    field = oracle.Field(C, grid.origin, grid.h, grid.shape)
+    t, q = scenes.tiny_poses(grid, 48, seed=79)
+    out, fl = oracle.query(field, ALPHA, 0.5, t, q, 7)
+    npd = np.isnan(out[:, 2])
+    assert npd.any() and (~npd).any()
+    up3 = np.tile([1.0, 1.0, 0.0], (t.shape[0], 1))
+    gt, gphi = oracle.query_grad(field, ALPHA, 0.5, t, q, 7, up3)
+    gt2, gphi2 = oracle.query_grad(field, ALPHA, 0.5, t, q, 3, up3[:, :2])
+    assert np.isfinite(gt).all() and np.isfinite(gphi).all()
+    np.testing.assert_array_equal(gt, gt2)
+    np.testing.assert_array_equal(gphi, gphi2)
+    gt3, _ = oracle.query_grad(field, ALPHA, 0.5, t, q, 7, np.ones((t.shape[0], 3)))
+    assert np.isnan(gt3[npd]).all() and np.isfinite(gt3[~npd]).all()
 
 
 def test_psd_for_nonnegative_visibility_and_indefinite_for_v05():
