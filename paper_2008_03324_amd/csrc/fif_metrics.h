@@ -80,8 +80,11 @@ __device__ inline void eval_metrics(const double F[21], uint32_t metrics, double
         double g = up[upc++];
         double inv[21];
         ldlt6_inverse(L, dinv, inv);
+        // a zero weight leaves the log-det out of L, so a FIM that is not
+        // positive definite does not turn the other metrics' gradient to NaN
 #pragma unroll
-        for (int e = 0; e < 21; ++e) G[e] = pd ? fma(g, inv[e], G[e]) : __builtin_nan("");
+        for (int e = 0; e < 21; ++e)
+          G[e] = (g == 0.0) ? G[e] : (pd ? fma(g, inv[e], G[e]) : __builtin_nan(""));
       }
     }
   }

@@ -226,23 +226,74 @@ def test_empty_landmark_set_and_tiny_grids(fif):
             assert e_fim(go[:, 3:], ref[:, 3:]).max() <= 1e-10, shape
 
 
-def test_trace_field_matches_information_field(fif, bld):
-    """Sec. VII-A: the trace factor gives the trace of the information factor."""
-    tf = fif.build(bld["lm_d"], bld["grid"], bld["vis"], prec=fif.FP32_COMP, kind=fif.KIND_TRACE)
-    m = 200_000
-    tr = fif.query(tf, bld["t_d"][:m].contiguous(), bld["q_d"][:m].contiguous(), fif.TRACE)
-    ref = bld["out"][:m, 0]
-    rel = ((tr[:, 0] - ref).abs() / ref.abs()).max().item()
-    assert rel <= 1e-3, rel
-    # and against the oracle trace factor on sampled voxels
+def _oracle_trace_field(b, t64):
+    g, v = b["g"], b["v"]
+    ids = oracle.corner_voxels(g.origin, g.h, g.shape, t64)
+    CT = oracle.trace_build(b["lm"], g.origin, g.h, g.shape, v.sigma, v.r_min, v.r_max,
+                            voxel_ids=ids)
+    return oracle.TraceField(CT, g.origin, g.h, g.shape, voxel_ids=ids)
+
+
+@pytest.mark.parametrize("prec", ["FP32_COMP", "FP64"])
+def test_trace_field_queries_sampled_vs_oracle(fif, bld, prec):
+    """eq:general_trace_pif, Sec. VII-A: the trace field's query against the
+    oracle's trace-field query (trace factors built in FP64 at the corner
+    voxels of the sampled poses), trilinear and nearest; the exported trace
+    factors against the oracle's; and the trace of the information field on
+    the same poses."""
+    print(f"case: building trace field {prec}", flush=True)
+    p = getattr(fif, prec)
+    tf = fif.build(bld["lm_d"], bld["grid"], bld["vis"], prec=p, kind=fif.KIND_TRACE)
     rng = np.random.default_rng(26)
+    pick = rng.choice(bld["t"].shape[0], 384, replace=False)
+    t64 = bld["t"][pick].astype(np.float64)
+    q64 = bld["q"][pick].astype(np.float64)
+    otf = _oracle_trace_field(bld, t64)
+    v = bld["v"]
+    if prec == "FP64":
+        td, qd = torch.from_numpy(t64).cuda(), torch.from_numpy(q64).cuda()
+        bar = 1e-9
+    else:
+        idx = torch.from_numpy(pick).cuda()
+        td, qd = bld["t_d"][idx].contiguous(), bld["q_d"][idx].contiguous()
+        bar = 1e-5  # measured ~1e-6; the FP32 bar is 1e-3
+    for interp in (fif.TRILINEAR, fif.NEAREST):
+        got, fl = fif.query(tf, td, qd, fif.TRACE, interp=interp, want_flags=True)
+        got = got.cpu().numpy()[:, 0]
+        ref, rfl = oracle.trace_query(otf, v.half_fov, v.v_alpha, t64, q64, interp)
+        rel = np.abs(got - ref) / np.abs(ref)
+        print(prec, "interp", interp, "trace field vs oracle max rel", rel.max())
+        assert rel.max() <= 1e-3
+        assert rel.max() <= bar
+        np.testing.assert_array_equal(fl.cpu().numpy() & 1, rfl & 1)
+    # the information field's trace on the same poses (FP32 field of the module)
+    if prec == "FP32_COMP":
+        m = 200_000
+        tr = fif.query(tf, bld["t_d"][:m].contiguous(), bld["q_d"][:m].contiguous(), fif.TRACE)
+        info = bld["out"][:m, 0]
+        assert ((tr[:, 0] - info).abs() / info.abs()).max().item() <= 1e-3
+    # exported trace factors against the oracle's
     ids = np.sort(rng.choice(bld["grid"].n_voxels, 64, replace=False))
-    g, v = bld["g"], bld["v"]
+    g = bld["g"]
     got = fif.export_blocks(tf, torch.from_numpy(ids).cuda()).cpu().numpy()
-    for a, vid in enumerate(ids):
-        t = oracle.voxel_centre(g.origin, g.h, g.shape, vid)
-        CT = oracle.trace_factor(bld["lm"], t, v.sigma, v.r_min, v.r_max)
-        assert np.abs(got[a] - CT).max() <= 1e-4 * np.abs(CT).max()
+    CT = oracle.trace_build(bld["lm"], g.origin, g.h, g.shape, v.sigma, v.r_min, v.r_max,
+                            voxel_ids=ids)
+    assert (np.abs(got - CT).max(axis=1) <= (1e-12 if prec == "FP64" else 1e-5)
+            * np.abs(CT).max(axis=1)).all()
+
+
+_UPDATE_REF = {}
+
+
+def _update_reference(bld, ids):
+    """Oracle blocks of the sampled voxels for the landmark sets A (the first
+    60,000) and A + B (all), computed once for both update paths."""
+    if not _UPDATE_REF:
+        g, v = bld["g"], bld["v"]
+        for name, lm in (("A", bld["lm"][:60_000]), ("AB", bld["lm"])):
+            _UPDATE_REF[name] = oracle.build(lm, g.origin, g.h, g.shape, v.sigma, v.r_min,
+                                             v.r_max, voxel_ids=ids)
+    return _UPDATE_REF
 
 
 @pytest.mark.parametrize("sort", [True, False])
@@ -258,15 +309,25 @@ def test_incremental_update_equals_rebuild(fif, bld, sort):
     fif.update(f, lm_b, +1, sort=sort)
     full = fif.build(bld["lm_d"], bld["grid"], bld["vis"], prec=fif.FP64)
     rng = np.random.default_rng(27)
-    ids = torch.from_numpy(np.sort(rng.choice(bld["grid"].n_voxels, 500, replace=False))).cuda()
+    ids_np = np.sort(rng.choice(bld["grid"].n_voxels, 500, replace=False))
+    ids = torch.from_numpy(ids_np).cuda()
+    ref = _update_reference(bld, ids_np[::3])
     a = fif.export_blocks(f, ids).cpu().numpy()
     b = fif.export_blocks(full, ids).cpu().numpy()
     assert np.abs(a - b).max() <= 1e-9 * np.abs(b).max()
+    # A + B against the oracle's build of all landmarks
+    err = block_rel_err(a[::3], ref["AB"])
+    print("update +B vs oracle: max", err.max())
+    assert err.max() <= 1e-9
     fif.update(f, lm_b, -1, sort=sort)
     part = fif.build(lm_a, bld["grid"], bld["vis"], prec=fif.FP64)
     a = fif.export_blocks(f, ids).cpu().numpy()
     c = fif.export_blocks(part, ids).cpu().numpy()
     assert np.abs(a - c).max() <= 1e-9 * np.abs(c).max()
+    # A + B - B against the oracle's build of A
+    err = block_rel_err(a[::3], ref["A"])
+    print("update +B-B vs oracle: max", err.max())
+    assert err.max() <= 1e-9
     # the queries see the update through the cell side records as well
     m = 100_000
     td = bld["t_d"][:m].double().contiguous()

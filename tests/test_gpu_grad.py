@@ -61,7 +61,9 @@ def test_fp32_gradient_vs_oracle(fif, traj):
         scale = np.abs(b[ok]).max(axis=1, keepdims=True)
         rel = np.abs(a[ok] - b[ok]) / scale
         print("fp32 grad rel err max", rel.max(), "median", np.median(rel))
-        assert rel.max() <= 1e-2
+        assert rel.max() <= 1e-3
+        # measured 3e-5 at most: kept as a guard well inside the bar
+        assert rel.max() <= 2e-4
         assert np.median(rel) <= 1e-4
 
 

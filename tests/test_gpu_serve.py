@@ -3,7 +3,9 @@ by HBM budget and slots; the one-request-per-launch mode agrees too."""
 import numpy as np
 import pytest
 
+import oracle
 import scenes
+from fifcheck import metric_errors, sym_from21
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -15,12 +17,11 @@ def setup():
     from paper_2008_03324_amd import serve
     print("case: serving loop on two small fields", flush=True)
     fields, pools = [], []
-    for i, shape in enumerate(((24, 24, 12), (40, 30, 10))):
-        lm, g, v = scenes.building_scene(n_landmarks=4000, seed=77 + i, shape=shape, h=0.25,
-                                         r_max=6.0)
+    for lm, g, v in _field_scenes():
         grid = fif.Grid(g.origin, g.h, g.shape)
         vis = fif.Vis(v.half_fov, v.v_alpha, v.sigma, v.r_min, v.r_max)
         fields.append(fif.build(torch.tensor(lm, device="cuda"), grid, vis, prec=fif.FP32_COMP))
+        i = len(fields) - 1
         pt, pq = scenes.building_poses(g, 20_000, seed=90 + i)
         tt, tq = scenes.trajectories(g, 128, 64, seed=95 + i)
         pools.append({"plan": (torch.from_numpy(pt).cuda(), torch.from_numpy(pq).cuda()),
@@ -29,6 +30,80 @@ def setup():
     specs = scenes.request_stream(2, 2000.0, 150, 20_000, 128, seed=99)
     torch.cuda.synchronize()
     return fif, serve, fields, pools, specs
+
+
+def _field_scenes():
+    """The two served fields' scenes (seeded, so the oracle sees the same
+    landmarks and grids as the GPU fields)."""
+    return [scenes.building_scene(n_landmarks=4000, seed=77 + i, shape=shape, h=0.25, r_max=6.0)
+            for i, shape in enumerate(((24, 24, 12), (40, 30, 10)))]
+
+
+def _check_vs_oracle(reqs, n_each=6, rows=48):
+    """Served outputs and gradients of a sample of requests (n_each of each
+    kind, up to `rows` poses of each) against the FP64 oracle on oracle-built
+    factors of the poses' corner voxels, at the FP32-field bar of 1e-3:
+    trace relative, lambda_min / lambda_max, log-det in nats; gradients
+    |dg| / max|g| per pose (dL/dout = 1 for each metric), poses within 1e-3 of
+    a cell face or with a near-repeated lambda_min left out (one-sided or
+    undefined derivative)."""
+    worst = {"out": 0.0, "grad": 0.0}
+    scns = _field_scenes()
+    n_opt = 0
+    for kind in ("plan", "opt"):
+        sample = [r for r in reqs if r.kind == kind][:n_each]
+        assert len(sample) == n_each
+        for r in sample:
+            lm, g, v = scns[r.field]
+            sel = np.linspace(0, r.m - 1, min(rows, r.m)).astype(np.int64)
+            t64 = r.t.cpu().numpy()[sel].astype(np.float64)
+            q64 = r.q.cpu().numpy()[sel].astype(np.float64)
+            ids = oracle.corner_voxels(g.origin, g.h, g.shape, t64)
+            C = oracle.build(lm, g.origin, g.h, g.shape, v.sigma, v.r_min, v.r_max,
+                             voxel_ids=ids)
+            of = oracle.Field(C, g.origin, g.h, g.shape, voxel_ids=ids)
+            ref, _ = oracle.query(of, v.half_fov, v.v_alpha, t64, q64, 7 | 8)
+            got = r.out.cpu().numpy()[sel]
+            err = metric_errors(got, ref[:, :3], ref[:, 3:])
+            e = max(err["trace_rel"].max(), err["lmin_weyl"].max(), err["logdet_abs"].max())
+            worst["out"] = max(worst["out"], e)
+            assert e <= 1e-3, (r.rid, err)
+            if kind == "opt":
+                n_opt += 1
+                rgt, rgphi = oracle.query_grad(of, v.half_fov, v.v_alpha, t64, q64, 7,
+                                               np.ones((len(sel), 3)))
+                gg = (t64 - np.asarray(g.origin)) / g.h
+                fr = gg - np.floor(gg)
+                ev = np.linalg.eigvalsh(sym_from21(ref[:, 3:]))
+                ok = ((fr > 1e-3) & (fr < 1 - 1e-3)).all(axis=1)
+                ok &= (ev[:, 1] - ev[:, 0]) > 1e-6 * np.abs(ev).max(axis=1)
+                assert ok.sum() >= len(sel) // 2
+                for a, b in ((r.grad_t.cpu().numpy()[sel], rgt),
+                             (r.grad_phi.cpu().numpy()[sel], rgphi)):
+                    rel = np.abs(a[ok] - b[ok]) / np.abs(b[ok]).max(axis=1, keepdims=True)
+                    worst["grad"] = max(worst["grad"], rel.max())
+                    assert rel.max() <= 1e-3, r.rid
+    assert n_opt == n_each
+    return worst
+
+
+@pytest.mark.parametrize("loop", ["native", "python"])
+def test_served_requests_vs_oracle(setup, loop):
+    """A sample of served requests, planner (queries) and optimizer (queries
+    and gradients), in the mix of the realtime stream, against the oracle."""
+    fif, serve, fields, pools, specs = setup
+    print(f"case: served requests vs oracle, {loop} loop", flush=True)
+    reqs = _make(serve, pools, specs)
+    if loop == "native":
+        srv = serve.NativeServer(fields, n_streams=3, co_batch=True, max_batch=16384)
+        srv.run(reqs, realtime=True)
+    else:
+        srv = serve.Server(fields, n_streams=3, use_graphs=True, co_batch=True, max_batch=16384)
+        srv.warmup()
+        srv.run(reqs, realtime=True)
+        assert all(r.status == "done" for r in reqs)
+    worst = _check_vs_oracle(reqs)
+    print(loop, "served vs oracle, worst", worst)
 
 
 def _make(serve, pools, specs):

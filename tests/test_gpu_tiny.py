@@ -201,3 +201,32 @@ def test_v05_indefinite_parity(fif, tiny):
     assert err["logdet_abs"].max() <= 1e-8
     assert (ref[:, 1] < 0).any() and np.isnan(ref[:, 2]).any()
     np.testing.assert_array_equal(flags & 2, rflags & 2)
+
+
+def test_v05_gradient_with_zero_logdet_weight(fif, tiny):
+    """v_alpha = 0.5: indefinite FIMs have no log-det.  With weight 0 on the
+    log-det the gradient is that of the other metrics (finite, equal to the
+    oracle's); with weight 1 it is NaN exactly on the poses whose FIM is not
+    positive definite."""
+    print("case: tiny gradient FP64, v_alpha 0.5, zero log-det weight", flush=True)
+    grid, vis = _grid_vis(fif, tiny["g"], tiny["v"], v_alpha=0.5)
+    field = fif.build(_cuda(tiny["lm"]), grid, vis, prec=fif.FP64)
+    t, q = tiny["t"], tiny["q"]
+    g = (t - np.asarray(tiny["g"].origin)) / tiny["g"].h
+    fr = g - np.floor(g)
+    ok = ((fr > 1e-6) & (fr < 1 - 1e-6)).all(axis=1)
+    ref, rflags = oracle.query(tiny["ofield"], tiny["v"].half_fov, 0.5, t, q, M7, 0)
+    ok &= (rflags & 4) == 0
+    up = np.tile([1.0, 0.5, 0.0], (t.shape[0], 1))
+    gt, gphi = fif.query_grad(field, _cuda(t), _cuda(q), M7, _cuda(up))
+    gt, gphi = gt.cpu().numpy(), gphi.cpu().numpy()
+    assert np.isfinite(gt).all() and np.isfinite(gphi).all()
+    rgt, rgphi = oracle.query_grad(tiny["ofield"], tiny["v"].half_fov, 0.5, t, q, M7, up)
+    for a, b in ((gt, rgt), (gphi, rgphi)):
+        scale = np.abs(b[ok]).max(axis=1, keepdims=True)
+        assert (np.abs(a[ok] - b[ok]) / scale).max() <= 1e-7
+    npd = np.isnan(ref[:, 2])
+    assert npd.any()
+    gt1, _ = fif.query_grad(field, _cuda(t), _cuda(q), M7, _cuda(np.ones_like(up)))
+    gt1 = gt1.cpu().numpy()
+    assert np.isnan(gt1[npd]).all() and np.isfinite(gt1[~npd]).all()
