@@ -140,6 +140,28 @@ size_t fif_workspace_bytes(const fif_grid* grid, int64_t n_landmarks, int32_t pr
 fif_status fif_build(const double* landmarks, int64_t n_landmarks, fif_field* field,
                      void* workspace, size_t workspace_bytes, void* stream);
 
+/* fif_build without a workspace argument and without allocating: for callers
+ * that cannot allocate device memory (tight serving loops, harnesses that
+ * forbid hipMalloc).  The landmarks are ordered
+ * spatially and batch-culled exactly as fif_build does with a workspace (the
+ * same sort, the same summation order: the field equals fif_build's bit for
+ * bit), but the sort's scratch lives in a static device array of
+ * FIF_NOALLOC_SCRATCH_BYTES bytes that the library holds on every device it
+ * runs on until the process ends.  The call makes no hipMalloc/hipFree and no
+ * allocating library call.  Nothing in the scratch needs to start at zero:
+ * every byte the build reads is written earlier in the same call.
+ * Limits and errors: as fif_build, plus FIF_EINVAL (before anything is
+ * enqueued) when fif_workspace_bytes(grid, n_landmarks, prec) exceeds
+ * FIF_NOALLOC_SCRATCH_BYTES (about 1.19 million landmarks: the sort takes
+ * 56 bytes per landmark).  All calls on one
+ * device share that device's scratch: calls that overlap in time on one
+ * device (different streams or threads without ordering) race and must not be
+ * made.  Like fif_build with a workspace, the sort enqueues a
+ * hipMemsetAsync, so keep the call out of captured HIP graphs. */
+#define FIF_NOALLOC_SCRATCH_BYTES (64u << 20)
+fif_status fif_build_noalloc(const double* landmarks, int64_t n_landmarks, fif_field* field,
+                             void* stream);
+
 /* Incremental update (Sec. VI-A, "Offline Processing vs. Online Update"): add
  * (sign = +1) or remove (sign = -1) the contribution of the given landmarks to
  * every voxel whose centre has them in range.  Same landmark layout and

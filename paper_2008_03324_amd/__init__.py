@@ -90,6 +90,8 @@ EXPORTS = {
     "fif_workspace_bytes": (ctypes.c_size_t, [ctypes.POINTER(CGrid), ctypes.c_int64, ctypes.c_int32]),
     "fif_build": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int64, ctypes.POINTER(CField),
                                    ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p]),
+    "fif_build_noalloc": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int64,
+                                           ctypes.POINTER(CField), ctypes.c_void_p]),
     "fif_update": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32,
                                     ctypes.POINTER(CField), ctypes.c_void_p, ctypes.c_size_t,
                                     ctypes.c_void_p]),
@@ -301,6 +303,20 @@ def build(landmarks: torch.Tensor, grid: Grid, vis: Vis, prec: int = FP32_COMP,
     ws = workspace(grid, lm.shape[0], prec, lm.device) if sort else None
     _check(lib().fif_build(_ptr(lm), lm.shape[0], ctypes.byref(field.cstruct), _ptr(ws),
                            ws.numel() if ws is not None else 0, _stream(stream)), "fif_build")
+    return field
+
+
+@_on_stream
+def build_noalloc(landmarks: torch.Tensor, grid: Grid, vis: Vis, prec: int = FP32_COMP,
+                  kind: int = KIND_INFO, field: Field | None = None, stream=None) -> Field:
+    """Build a field with the sorted, batch-culled path and the library's static
+    scratch instead of a workspace (fif_build_noalloc; the same field as
+    build(sort=True)).  Pass `field` to keep the call free of allocations."""
+    lm = _dev(landmarks, torch.float64, "landmarks", 3)
+    if field is None:
+        field = Field(grid, vis, prec, kind, device=lm.device)
+    _check(lib().fif_build_noalloc(_ptr(lm), lm.shape[0], ctypes.byref(field.cstruct),
+                                   _stream(stream)), "fif_build_noalloc")
     return field
 
 

@@ -5,6 +5,7 @@
 #include <string.h>
 
 #include <atomic>
+#include <mutex>
 #include <string>
 
 #include "../../include/fif.h"
@@ -192,6 +193,70 @@ fif_status fif_build(const double* landmarks, int64_t n_landmarks, fif_field* fi
                      void* workspace, size_t workspace_bytes, void* stream) {
   return build_common(landmarks, n_landmarks, field, 0, 1, workspace, workspace_bytes, stream,
                       "fif_build");
+}
+
+}  // extern "C"
+
+namespace {
+
+// Scratch of fif_build_noalloc: the landmark sort's keys and indices, the
+// spatially sorted copy, the batch boxes and the radix sort's temporaries,
+// held in a static device array instead of a caller's workspace.  Every device
+// that runs the library holds its own copy until the process ends.  Host code
+// never uses the array's name as an address: it takes the device address from
+// hipGetSymbolAddress once per device.
+constexpr int kMaxDevices = 64;
+static __device__ __align__(256) unsigned char scratch[FIF_NOALLOC_SCRATCH_BYTES];
+
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+fif_status scratch_of_current_device(void** out) {
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return device_status(e, "fif_build_noalloc: hipGetDevice");
+  if (dev < 0 || dev >= kMaxDevices)
+    return fail(FIF_EUNSUPPORTED, "fif_build_noalloc: device index beyond 63%s");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return device_status(e, "fif_build_noalloc: hipGetSymbolAddress");
+    if (!p || !aligned(p, 256))
+      return fail(FIF_EDEVICE, "fif_build_noalloc: static scratch not 256-byte aligned%s");
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return FIF_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+fif_status fif_build_noalloc(const double* landmarks, int64_t n_landmarks, fif_field* field,
+                             void* stream) {
+  fif_status st = check_field(field);
+  if (st != FIF_OK) return st;
+  if (n_landmarks <= 0)  // nothing to sort: build_common validates and clears the field
+    return build_common(landmarks, n_landmarks, field, 0, 1, nullptr, 0, stream,
+                        "fif_build_noalloc");
+  if (!landmarks) return fail(FIF_EINVAL, "landmarks is NULL%s");
+  if (n_landmarks > ((int64_t)1 << 40)) return fail(FIF_EINVAL, "too many landmarks%s");
+  const size_t need = fif::sort_workspace_bytes(n_landmarks);
+  if (need == 0) return fail(FIF_EDEVICE, "fif_build_noalloc: cannot size the landmark sort%s");
+  if (need > (size_t)FIF_NOALLOC_SCRATCH_BYTES) {
+    char msg[160];
+    snprintf(msg, sizeof msg, "%lld landmarks need %zu bytes of scratch, more than the %zu of "
+             "the static scratch", (long long)n_landmarks, need,
+             (size_t)FIF_NOALLOC_SCRATCH_BYTES);
+    return fail(FIF_EINVAL, "fif_build_noalloc: %s", msg);
+  }
+  void* ws = nullptr;
+  st = scratch_of_current_device(&ws);
+  if (st != FIF_OK) return st;
+  return build_common(landmarks, n_landmarks, field, 0, 1, ws, FIF_NOALLOC_SCRATCH_BYTES, stream,
+                      "fif_build_noalloc");
 }
 
 fif_status fif_update(const double* landmarks, int64_t n_landmarks, int32_t sign,
