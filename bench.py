@@ -40,6 +40,19 @@ BUILD_FLOPS_CONTRIB = 151
 BUILD_FLOPS_TESTED = 10             # d (3), n^2 (5), two compares
 PC_FLOPS_CONTRIB = 45
 PC_FLOPS_TESTED = 10
+# the paper's layout and formulation, which the moment layout supersedes with
+# the same results: 8 corners x 840 B of blocks + pose + output per query, and
+# ~504 flops per contributing pair (per-landmark FIM, vp, 10 x 21 accumulates)
+PAPER_LAYOUT_BYTES_PER_QUERY = 6772
+PAPER_LAYOUT_FLOPS_PER_PAIR = 504
+# gradient kernel per pose: 8 corner records + pose + dL/dout (3 doubles) +
+# dL/dt and dL/dphi (6 floats); the records' second pass is a cache re-read
+GRAD_BYTES_PER_POSE = 8 * RECORD_BYTES_USED + POSE_BYTES + 24 + 24
+FP64_PEAK_TFLOPS = 78.6
+# optimal-view sweep, log-det, per (position, axis): vr(z) and its
+# normalisation (~25), the contraction 21 x 10 FMAs (420), LDL^T of the 6x6
+# (100) and the log-det sum (11)
+SWEEP_FLOPS_PER_AXIS = 556
 
 
 def parse():
@@ -104,6 +117,19 @@ def query_src_hash():
 
 BUILD_SOURCES = ("fif_build.hip", "fif_device.h")
 PC_SOURCES = ("fif_pc.hip", "fif_device.h")
+GP_SOURCES = ("fif_gp.hip", "fif_device.h", "fif_metrics.h")
+
+
+def sources_of(kernel: str):
+    """The source files that define a kernel of the library (by its name)."""
+    name = kernel.split("::")[-1]
+    if name.startswith("gp_"):
+        return GP_SOURCES
+    if name.startswith("pc_"):
+        return PC_SOURCES
+    if name.startswith(("build_", "fill_side", "gather_box", "morton")):
+        return BUILD_SOURCES
+    return QUERY_SOURCES
 
 
 def src_hash(files):
@@ -129,15 +155,14 @@ def counter_flops(kernel, files):
 
 def counter_traffic(kernel):
     """HBM bytes per launch from the committed rocprofv3 counters, or None when
-    the query kernel's sources changed since they were taken."""
+    the kernel's sources changed since they were taken."""
     path = os.path.join(ROOT, "profiles", "counters.json")
     if not os.path.exists(path):
         return None
-    rec = json.load(open(path))
-    if query_src_hash() != rec.get("query_src_hash"):
+    rec = json.load(open(path)).get("traffic", {}).get(kernel)
+    if not rec or rec.get("src_hash") != src_hash(sources_of(kernel)):
         return None
-    gb = rec.get("traffic_GB_per_launch", {}).get(kernel)
-    return None if gb is None else gb * 1e9
+    return rec["GB_per_launch"] * 1e9
 
 
 def contributing_fraction(torch, lm_d, grid, r_max, n_sample=32768, seed=7):
@@ -280,11 +305,36 @@ def main():
                      "achieved": q_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": q_gbs / HBM_PEAK_GBS,
                      "traffic": counter_traffic("fif::query_info_pipe_kernel"),
-                     "algorithmic_bytes": q_bytes, "bytes_per_query": q_bytes / m},
+                     "algorithmic_bytes": q_bytes, "bytes_per_query": q_bytes / m,
+                     "paper_layout_bytes_per_query": PAPER_LAYOUT_BYTES_PER_QUERY,
+                     "paper_layout_note": "superseded: the field stores 66 bearing moments "
+                                          "per voxel (exactly equivalent to the paper's 10 "
+                                          "blocks; export parity 1e-10), so a query reads "
+                                          "2,164 B, not 6,772 B; the paper-layout bytes over "
+                                          "this time would exceed the HBM peak"},
         "roofline_build": {"kernel": "build_kernel<FP32_COMP>", "bound": "fp32 valu",
                            "achieved": b_tfs, "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
-                           "frac": b_tfs / FP32_PEAK_TFLOPS},
+                           "frac": b_tfs / FP32_PEAK_TFLOPS,
+                           "flops_per_contributing_pair": BUILD_FLOPS_CONTRIB,
+                           "flops_per_rejected_pair": BUILD_FLOPS_TESTED,
+                           "paper_layout_flops_per_pair": PAPER_LAYOUT_FLOPS_PER_PAIR,
+                           "paper_layout_note": "superseded: accumulating monomials of the "
+                                                "bearing (151 flops per pair) replaces forming "
+                                                "the per-landmark FIM and its 10 x 21 products "
+                                                "(504); at this pair rate the paper's flops "
+                                                "would exceed the FP32 peak"},
     }
+    if "grad" in phases:
+        g_bytes = mg * GRAD_BYTES_PER_POSE
+        g_gbs = g_bytes / (med["grad"] / 1e3) / 1e9
+        g_traffic = counter_traffic("fif::query_info_kernel<float, true>")
+        res["roofline_grad"] = {
+            "kernel": "query_info_kernel<float,true>", "bound": "hbm", "achieved": g_gbs,
+            "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": g_gbs / HBM_PEAK_GBS,
+            "bytes_per_pose": GRAD_BYTES_PER_POSE, "algorithmic_bytes": g_bytes,
+            "traffic": g_traffic,
+            "counted_frac": (None if g_traffic is None
+                             else g_traffic / (med["grad"] / 1e3) / 1e9 / HBM_PEAK_GBS)}
     # hardware-counted FLOPs (rocprofv3 SQ_INSTS_VALU_FLOPS_FP32; issued
     # instructions x 64 lanes, so lanes masked off in divergent branches count)
     cb = counter_flops("fif::build_kernel<1, 0>", BUILD_SOURCES)
@@ -306,6 +356,10 @@ def main():
             ctf = cp["fp32"] / (med["pc"] / 1e3) / 1e12
             res["roofline_pc"].update({"counter_achieved": ctf,
                                        "counter_frac": ctf / FP32_PEAK_TFLOPS})
+
+    if "pc" in phases and "query" in phases:
+        res["field_vs_pc_same_poses"] = gap_leg(fif, torch, field, lm_d, vis, t_d, q_d, out,
+                                                pc_out)
 
     if not args.no_sweep:
         res["view_sweep"] = sweep_leg(fif, torch, scenes, g, field, dev)
@@ -391,23 +445,80 @@ def gp_leg(fif, torch, scenes, lm_d, grid, vis, t_d, q_d, contrib, dev, ns=70, m
             "query_info_gbs": gbs, "query_info_hbm_frac": gbs / HBM_PEAK_GBS}
 
 
-def precision_leg(fif, torch, scenes, t_d, q_d, dev, n_landmarks=1_000_000, n_ids=4096,
+def _sym21(v):
+    iu = np.triu_indices(6)
+    F = np.zeros(v.shape[:-1] + (6, 6))
+    F[..., iu[0], iu[1]] = v
+    F[..., iu[1], iu[0]] = v
+    return F
+
+
+def _metric_errs(a, b, lmax):
+    """Errors of metric rows a against b (columns trace, lambda_min, log-det):
+    trace relative; lambda_min relative where lambda_min > 1e-6 lambda_max and
+    |d lambda| / lambda_max everywhere; log-det in nats.  NaN in one row and
+    not in the other is counted, not dropped; NaN in both is a match."""
+    nan_a, nan_b = np.isnan(a), np.isnan(b)
+    fin = ~nan_a & ~nan_b
+    well = fin[:, 1] & (b[:, 1] > 1e-6 * lmax)
+
+    def mx(x):
+        return float(x.max()) if x.size else 0.0
+
+    return {"trace_rel_max": mx(np.abs(a[fin[:, 0], 0] - b[fin[:, 0], 0]) / np.abs(b[fin[:, 0], 0])),
+            "lmin_rel_max": mx(np.abs(a[well, 1] - b[well, 1]) / np.abs(b[well, 1])),
+            "lmin_weyl_max": mx(np.abs(a[fin[:, 1], 1] - b[fin[:, 1], 1]) / lmax[fin[:, 1]]),
+            "logdet_abs_max": mx(np.abs(a[fin[:, 2], 2] - b[fin[:, 2], 2])),
+            "nan_pattern_mismatches": int((nan_a != nan_b).sum()),
+            "rows": int(a.shape[0])}
+
+
+def _block_errs(a, ref):
+    """Per-voxel |dC|_F / |C|_F over the exported blocks [n][10][21]."""
+    w = np.where(np.triu_indices(6)[0] == np.triu_indices(6)[1], 1.0, 2.0)
+    e = np.sqrt(((a - ref) ** 2 * w).sum(axis=(1, 2))) / np.maximum(
+        np.sqrt((ref ** 2 * w).sum(axis=(1, 2))), 1e-300)
+    return float(e.max()), float(np.median(e))
+
+
+def precision_leg(fif, torch, scenes, t_d, q_d, dev, n_landmarks=1_000_000, n_oracle=512,
                   m=100_000, reps=2):
     """Precision sweep: the building scene at 1M landmarks built as FP64, FP32
-    compensated and FP32 naive fields.  Per variant: build time and contributing
-    pairs/s; for the FP32 variants, their error against the FP64 build (itself
-    held to the oracle by the tests): per-voxel block error |dC|_F / |C|_F on
-    sampled voxels, and metric errors on the first 100k building poses."""
+    compensated and FP32 naive fields on the 2M-voxel grid.  Per variant: build
+    time and contributing pairs/s; errors against the FP64 CPU oracle (factors
+    of the corner voxels of 512 of the first 100k building poses, built from
+    all 1M landmarks): per-voxel block error on those voxels and metric errors
+    on those poses; and, for the FP32 variants, metric errors against the GPU
+    FP64 field on all 100k poses."""
+    import oracle
     lm, g, v = scenes.building_scene(n_landmarks=n_landmarks)
     grid = fif.Grid(g.origin, g.h, g.shape)
     vis = fif.Vis(v.half_fov, v.v_alpha, v.sigma, v.r_min, v.r_max)
     lm_d = torch.tensor(lm, dtype=torch.float64, device=dev)
     frac = contributing_fraction(torch, lm_d, grid, v.r_max)
     contrib = frac * grid.n_voxels * n_landmarks
-    gen = torch.Generator(device="cpu").manual_seed(11)
-    ids = torch.randint(0, grid.n_voxels, (n_ids,), generator=gen).to(dev)
-    res = {"landmarks": n_landmarks, "contributing_fraction": frac, "variants": {}}
-    blocks, outs = {}, {}
+    rng = np.random.default_rng(12)
+    pick = np.sort(rng.choice(m, n_oracle, replace=False))
+    t64 = t_d[:m][torch.from_numpy(pick).to(dev)].cpu().numpy().astype(np.float64)
+    q64 = q_d[:m][torch.from_numpy(pick).to(dev)].cpu().numpy().astype(np.float64)
+    ids = oracle.corner_voxels(g.origin, g.h, g.shape, t64)
+    c0 = time.perf_counter()
+    C = oracle.build(lm, g.origin, g.h, g.shape, v.sigma, v.r_min, v.r_max, voxel_ids=ids)
+    ob_s = time.perf_counter() - c0
+    of = oracle.Field(C, g.origin, g.h, g.shape, voxel_ids=ids)
+    oref, _ = oracle.query(of, v.half_fov, v.v_alpha, t64, q64, 7 | 8)
+    olmax = np.linalg.eigvalsh(_sym21(oref[:, 3:]))[:, -1]
+    iu = np.triu_indices(6)
+    oblocks = C[:, :, iu[0], iu[1]]
+    log(f"precision sweep: oracle factors of {ids.size} voxels from {n_landmarks} landmarks "
+        f"in {ob_s:.1f} s ({oracle.num_threads()} threads)")
+    ids_d = torch.from_numpy(ids).to(dev)
+    pick_d = torch.from_numpy(pick).to(dev)
+    res = {"landmarks": n_landmarks, "contributing_fraction": frac,
+           "oracle_sample": {"poses": n_oracle, "corner_voxels": int(ids.size),
+                             "oracle_build_s": ob_s},
+           "variants": {}}
+    outs = {}
     for name, prec in (("FP64", fif.FP64), ("FP32_COMP", fif.FP32_COMP),
                        ("FP32_NAIVE", fif.FP32_NAIVE)):
         f = fif.Field(grid, vis, prec, device=dev)
@@ -424,29 +535,74 @@ def precision_leg(fif, torch, scenes, t_d, q_d, dev, n_landmarks=1_000_000, n_id
             ms.append(a.elapsed_time(b))
         med = float(np.median(ms))
         pdt = f.pose_dtype
-        blocks[name] = fif.export_blocks(f, ids).cpu().numpy()
+        blocks = fif.export_blocks(f, ids_d).cpu().numpy()
         outs[name] = fif.query(f, t_d[:m].to(pdt).contiguous(), q_d[:m].to(pdt).contiguous(),
-                               fif.TRACE | fif.LMIN | fif.LOGDET).cpu().numpy()
+                               fif.TRACE | fif.LMIN | fif.LOGDET | fif.FIM21).cpu().numpy()
         del f
         torch.cuda.empty_cache()
-        res["variants"][name] = {"build_ms": med, "pairs_per_s": contrib / (med / 1e3)}
-    w = np.where(np.triu_indices(6)[0] == np.triu_indices(6)[1], 1.0, 2.0)
-    ref, oref = blocks["FP64"], outs["FP64"]
-    nref = np.sqrt((ref ** 2 * w).sum(axis=(1, 2)))
+        bmax, bmed = _block_errs(blocks, oblocks)
+        vo = _metric_errs(outs[name][pick, :3], oref[:, :3], olmax)
+        entry = {"build_ms": med, "pairs_per_s": contrib / (med / 1e3),
+                 "block_err_max_vs_oracle": bmax, "block_err_median_vs_oracle": bmed}
+        entry.update({k + "_vs_oracle": x for k, x in vo.items()})
+        res["variants"][name] = entry
+    ref = outs["FP64"]
+    lmax = np.linalg.eigvalsh(_sym21(ref[:, 3:]))[:, -1]
     for name in ("FP32_COMP", "FP32_NAIVE"):
-        e = np.sqrt(((blocks[name] - ref) ** 2 * w).sum(axis=(1, 2))) / np.maximum(nref, 1e-300)
-        o = outs[name]
-        tr = np.abs(o[:, 0] - oref[:, 0]) / np.abs(oref[:, 0])
-        lm_rel = np.abs(o[:, 1] - oref[:, 1]) / np.abs(oref[:, 1])
-        ld = np.abs(o[:, 2] - oref[:, 2])
-        res["variants"][name].update({
-            "block_err_max": float(e.max()), "block_err_median": float(np.median(e)),
-            "trace_rel_max": float(np.nanmax(tr)), "lmin_rel_median": float(np.nanmedian(lm_rel)),
-            "lmin_rel_max": float(np.nanmax(lm_rel)), "logdet_abs_max": float(np.nanmax(ld))})
+        vg = _metric_errs(outs[name][:, :3], ref[:, :3], lmax)
+        res["variants"][name].update({k + "_vs_gpu_fp64_100k": x for k, x in vg.items()})
     log("precision sweep (1M landmarks): " + "; ".join(
-        f"{k} {d['build_ms']:.0f} ms {d['pairs_per_s']:.3g} pairs/s"
-        + (f", block err max {d['block_err_max']:.2e}" if "block_err_max" in d else "")
+        f"{k} {d['build_ms']:.0f} ms {d['pairs_per_s']:.3g} pairs/s, vs oracle: blocks "
+        f"{d['block_err_max_vs_oracle']:.2e}, trace {d['trace_rel_max_vs_oracle']:.2e}, "
+        f"log-det {d['logdet_abs_max_vs_oracle']:.2e} nats, NaN mismatches "
+        f"{d['nan_pattern_mismatches_vs_oracle']}"
         for k, d in res["variants"].items()))
+    return res
+
+
+def _fim_gap(a21, b21):
+    """e_FIM = |A - B|_F / |B|_F (the relative FIM difference of Sec. VII-A)."""
+    w = np.where(np.triu_indices(6)[0] == np.triu_indices(6)[1], 1.0, 2.0)
+    return np.sqrt(((a21 - b21) ** 2 * w).sum(-1)) / np.sqrt((b21 ** 2 * w).sum(-1))
+
+
+def _stats(x):
+    x = x[np.isfinite(x)]
+    if not x.size:
+        return {"max": None, "p99": None, "median": None}
+    return {"max": float(x.max()), "p99": float(np.percentile(x, 99)),
+            "median": float(np.median(x))}
+
+
+def gap_leg(fif, torch, field, lm_d, vis, t_d, q_d, out, pc_out, m_fim=100_000):
+    """How far the field's answers are from the point cloud's on the same poses
+    (both under the quadratic visibility): what the field gives up by taking
+    bearings from voxel centres and interpolating (Sec. VI-A), stated next to
+    the speedup.  On all 10M poses: trace relative and log-det in nats; on the
+    first 100k poses, with the full FIMs: e_FIM (Frobenius, as Table II),
+    lambda_min relative and lambda_min / lambda_max."""
+    a, b = out.cpu().numpy(), pc_out.cpu().numpy()
+    tr = np.abs(a[:, 0] - b[:, 0]) / np.abs(b[:, 0])
+    ld = np.abs(a[:, 2] - b[:, 2])
+    nan_mis = int((np.isnan(a) != np.isnan(b)).sum())
+    cols = fif.TRACE | fif.LMIN | fif.LOGDET | fif.FIM21
+    fo = fif.query(field, t_d[:m_fim].contiguous(), q_d[:m_fim].contiguous(), cols).cpu().numpy()
+    po = fif.pc_query(lm_d, vis, t_d[:m_fim].contiguous(), q_d[:m_fim].contiguous(), cols,
+                      prec=fif.FP32_COMP).cpu().numpy()
+    lmax = np.linalg.eigvalsh(_sym21(po[:, 3:]))[:, -1]
+    well = po[:, 1] > 1e-6 * lmax
+    res = {"poses": int(a.shape[0]), "trace_rel": _stats(tr), "logdet_abs_nats": _stats(ld),
+           "nan_pattern_mismatches": nan_mis,
+           "fim_poses": m_fim, "e_fim": _stats(_fim_gap(fo[:, 3:], po[:, 3:])),
+           "lmin_rel": _stats(np.abs(fo[well, 1] - po[well, 1]) / np.abs(po[well, 1])),
+           "lmin_weyl": _stats(np.abs(fo[:, 1] - po[:, 1]) / lmax),
+           "note": "field (FP32 compensated, trilinear) against the GPU point cloud (FP32 "
+                   "compensated) under the same quadratic visibility; both paths' own errors "
+                   "against the FP64 oracle are in rel_err_field_vs_oracle and "
+                   "rel_err_pc_vs_oracle"}
+    log(f"field vs point cloud, same poses: trace rel median {res['trace_rel']['median']:.2e} "
+        f"p99 {res['trace_rel']['p99']:.2e}; log-det median {res['logdet_abs_nats']['median']:.2e}"
+        f" nats; e_FIM median {res['e_fim']['median']:.2e} p99 {res['e_fim']['p99']:.2e}")
     return res
 
 
@@ -582,9 +738,23 @@ def sweep_leg(fif, torch, scenes, g, field, dev, n_pos=200, n_axes=4096, reps=5)
         torch.cuda.synchronize()
         ms.append(e0.elapsed_time(e1))
     med = float(np.median(ms))
-    log(f"view sweep {n_pos} x {n_axes}: {med:.3f} ms")
+    # bytes: 8 corner records + position + the values row + best per position,
+    # and the axes once
+    nbytes = n_pos * (8 * RECORD_BYTES_USED + 12 + 8 * n_axes + 8) + 24 * n_axes
+    gbs = nbytes / (med / 1e3) / 1e9
+    tfs = n_pos * n_axes * SWEEP_FLOPS_PER_AXIS / (med / 1e3) / 1e12
+    traffic = counter_traffic("fif::view_sweep_kernel<float>")
+    log(f"view sweep {n_pos} x {n_axes}: {med:.3f} ms ({tfs:.2f} FP64 TFLOP/s, {gbs:.0f} GB/s)")
     return {"positions": n_pos, "axes": n_axes, "metric": "logdet", "ms": med,
-            "poses_per_s": n_pos * n_axes / (med / 1e3)}
+            "poses_per_s": n_pos * n_axes / (med / 1e3),
+            "roofline": {"kernel": "view_sweep_kernel<float>", "bound": "fp64 valu",
+                         "achieved": tfs, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
+                         "frac": tfs / FP64_PEAK_TFLOPS,
+                         "flops_per_axis": SWEEP_FLOPS_PER_AXIS},
+            "hbm": {"algorithmic_bytes": nbytes, "achieved_gbs": gbs,
+                    "frac": gbs / HBM_PEAK_GBS, "traffic": traffic,
+                    "counted_frac": (None if traffic is None
+                                     else traffic / (med / 1e3) / 1e9 / HBM_PEAK_GBS)}}
 
 
 def serve_leg(args, fif, torch):
@@ -700,9 +870,10 @@ def cpu_leg(args, fif, torch, lm, g, v, t, q, out, pc_out, metrics):
     q_s = (time.perf_counter() - c0) / reps
     n_pc = max(8, ns // 4)
     c0 = time.perf_counter()
-    ref_pc = oracle.pc_query(lm, v.half_fov, v.v_alpha, v.sigma, v.r_min, v.r_max, ts[:n_pc],
-                             qs[:n_pc], metrics)
+    ref_pc_all = oracle.pc_query(lm, v.half_fov, v.v_alpha, v.sigma, v.r_min, v.r_max,
+                                 ts[:n_pc], qs[:n_pc], metrics | 8)
     pc_s = time.perf_counter() - c0
+    ref_pc, ref_pc_fim = ref_pc_all[:, :3], ref_pc_all[:, 3:]
     _, F_ref = oracle.pc_query(lm, v.half_fov, v.v_alpha, v.sigma, v.r_min, v.r_max, ts[:1],
                                qs[:1], 8, want_fim=True)
     gpu = out[torch.from_numpy(pick).to(out.device)].cpu().numpy()
@@ -717,11 +888,12 @@ def cpu_leg(args, fif, torch, lm, g, v, t, q, out, pc_out, metrics):
         lmax.append(np.linalg.eigvalsh(F)[-1])
     lmax = np.array(lmax)
 
-    def errs(a, b, lm_):
-        return {"trace_rel_max": float(np.max(np.abs(a[:, 0] - b[:, 0]) / np.abs(b[:, 0]))),
-                "lmin_weyl_max": float(np.max(np.abs(a[:, 1] - b[:, 1]) / lm_)),
-                "lmin_rel_max": float(np.max(np.abs(a[:, 1] - b[:, 1]) / np.abs(b[:, 1]))),
-                "logdet_abs_max": float(np.nanmax(np.abs(a[:, 2] - b[:, 2])))}
+    errs = _metric_errs
+    # the oracle's own field against the oracle's own point cloud on the same
+    # poses: the interpolation gap without any GPU rounding
+    pc_lmax = np.linalg.eigvalsh(_sym21(ref_pc_fim))[:, -1]
+    of_vs_opc = _metric_errs(ref[:n_pc], ref_pc, pc_lmax)
+    of_vs_opc["e_fim"] = _stats(_fim_gap(ref_fim[:n_pc], ref_pc_fim))
 
     pairs = ids.size * lm.shape[0]
 
@@ -765,7 +937,8 @@ def cpu_leg(args, fif, torch, lm, g, v, t, q, out, pc_out, metrics):
         f"{tiny['all_cores']['build_s']:.2f} s ({nthreads} threads)")
     return {
         "rel_err_field_vs_oracle": errs(gpu, ref, lmax),
-        "rel_err_pc_vs_oracle": errs(gpu_pc, ref_pc, lmax[:n_pc]),
+        "rel_err_pc_vs_oracle": errs(gpu_pc, ref_pc, pc_lmax),
+        "oracle_field_vs_oracle_pc": of_vs_opc,
         "cpu_baseline": {
             "value": ns / q_s, "unit": "queries/s", "cores": nthreads, "kind": "oracle",
             "cpu": cpu_model(),

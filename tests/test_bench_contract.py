@@ -31,8 +31,10 @@ def test_source_hash_ignores_comments_and_whitespace():
 def test_counters_follow_the_source_hash(tmp_path, monkeypatch):
     prof = tmp_path / "profiles"
     prof.mkdir()
-    rec = {"query_src_hash": bench.query_src_hash(),
-           "traffic_GB_per_launch": {"fif::query_info_pipe_kernel": 22.4},
+    rec = {"traffic": {"fif::query_info_pipe_kernel": {"GB_per_launch": 22.4,
+                                                        "src_hash": bench.query_src_hash()},
+                       "fif::pc_kernel<1, false>": {"GB_per_launch": 0.5,
+                                                    "src_hash": bench.src_hash(bench.PC_SOURCES)}},
            "flops": {"fif::build_kernel<1, 0>": {"fp32": 1e13, "src_hash":
                                                  bench.src_hash(bench.BUILD_SOURCES)}}}
     (prof / "counters.json").write_text(json.dumps(rec))
@@ -45,12 +47,17 @@ def test_counters_follow_the_source_hash(tmp_path, monkeypatch):
 
     monkeypatch.setattr(bench.os.path, "join", join)
     assert bench.counter_traffic("fif::query_info_pipe_kernel") == 22.4e9
+    assert bench.counter_traffic("fif::pc_kernel<1, false>") == 0.5e9
     assert bench.counter_flops("fif::build_kernel<1, 0>", bench.BUILD_SOURCES)["fp32"] == 1e13
-    rec["query_src_hash"] = "0" * 16
+    # each kernel's counters follow its own sources
+    rec["traffic"]["fif::query_info_pipe_kernel"]["src_hash"] = "0" * 16
     rec["flops"]["fif::build_kernel<1, 0>"]["src_hash"] = "0" * 16
     (prof / "counters.json").write_text(json.dumps(rec))
     assert bench.counter_traffic("fif::query_info_pipe_kernel") is None
+    assert bench.counter_traffic("fif::pc_kernel<1, false>") == 0.5e9
     assert bench.counter_flops("fif::build_kernel<1, 0>", bench.BUILD_SOURCES) is None
+    assert bench.sources_of("fif::gp_query_trace_kernel<float>") == bench.GP_SOURCES
+    assert bench.sources_of("fif::build_kernel<1, 1>") == bench.BUILD_SOURCES
 
 
 def test_morton_key_of_the_sorted_leg():
