@@ -194,14 +194,34 @@ fif_status fif_query_grad(const fif_field* field, const void* t, const void* q, 
                           uint32_t metrics, const double* dL_dout, void* dL_dt, void* dL_dphi,
                           double* out, void* stream);
 
+/* Bytes of the optional pc_query workspace for n_landmarks landmarks and m
+ * poses (0 for non-positive sizes, an invalid precision or n_landmarks >=
+ * 2^32).  Poses are ordered in passes of at most 2^26, so the size stops
+ * growing with m there. */
+size_t pc_workspace_bytes(int64_t n_landmarks, int64_t m, int32_t prec);
+
 /* Point-cloud brute force (eq:cost_info, eq:vis_fim): F = sum_{i in V_t} v_i I_i
  * for each pose, with v_i the quadratic visibility of z.u_i (cam == NULL,
  * eq:quad_vis_approx, unclamped) or the exact pinhole test (eq:exact_vis_func:
  * in front of the camera and inside [0, width) x [0, height)).
- * t, q: float for FP32 precisions, double for FIF_FP64.  out as fif_query. */
+ * t, q: float for FP32 precisions, double for FIF_FP64.  out as fif_query.
+ * workspace: NULL, or 256-B aligned device memory of at least
+ * pc_workspace_bytes() bytes (FIF_ENOMEM if smaller; scratch only).  With a
+ * workspace and a finite r_max, landmarks and poses are first ordered by the
+ * Morton code of their cell (edge r_max / 32; cell index floor(x * 32 / r_max)
+ * per axis taken modulo 1024, codes sorted stably), and each group of 256
+ * consecutive ordered poses skips every batch of 256 ordered landmarks whose
+ * bounding box is out of range of the group's box.  A skipped batch holds no
+ * landmark in range of those poses, and each pose sums its landmarks in the
+ * ordered sequence, so the results equal those of the call without a
+ * workspace given the landmarks in that order, bit for bit; results are
+ * written in the caller's pose order.  With NULL (or r_max = INFINITY) every
+ * pair is tested in input order.  The sort enqueues hipMemsetAsync: keep calls
+ * given a workspace out of captured HIP graphs. */
 fif_status pc_query(const double* landmarks, int64_t n_landmarks, const fif_vis* vis,
                     const fif_pinhole* cam, int32_t prec, const void* t, const void* q,
-                    int64_t m, uint32_t metrics, double* out, void* stream);
+                    int64_t m, uint32_t metrics, double* out, void* workspace,
+                    size_t workspace_bytes, void* stream);
 
 /* Optimal-view sweep (Sec. VII-A "Relative Measures": the optimal view at a
  * position is the rotation that maximises the metric).  Under the smooth

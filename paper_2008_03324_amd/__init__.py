@@ -102,10 +102,12 @@ EXPORTS = {
                                         ctypes.c_int64, ctypes.c_uint32, ctypes.c_void_p,
                                         ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                         ctypes.c_void_p]),
+    "pc_workspace_bytes": (ctypes.c_size_t, [ctypes.c_int64, ctypes.c_int64, ctypes.c_int32]),
     "pc_query": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int64, ctypes.POINTER(CVis),
                                   ctypes.POINTER(CPinhole), ctypes.c_int32, ctypes.c_void_p,
                                   ctypes.c_void_p, ctypes.c_int64, ctypes.c_uint32,
-                                  ctypes.c_void_p, ctypes.c_void_p]),
+                                  ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t,
+                                  ctypes.c_void_p]),
     "fif_view_sweep": (ctypes.c_int32, [ctypes.POINTER(CField), ctypes.c_void_p, ctypes.c_int64,
                                         ctypes.c_void_p, ctypes.c_int64, ctypes.c_uint32,
                                         ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p,
@@ -266,28 +268,36 @@ class Field:
 
 
 _WORKSPACE = {}
+_PC_WORKSPACE = {}
 
 
-def workspace(grid: Grid, n_landmarks: int, prec: int, device) -> torch.Tensor | None:
-    """Scratch for the spatially sorted build: one buffer per (device, current
-    stream), grown on demand.  Builds enqueued on one stream run in order, so
-    they can share it; builds on different streams get different buffers."""
-    nbytes = int(lib().fif_workspace_bytes(ctypes.byref(grid.c()), int(n_landmarks), prec))
-    if nbytes == 0:
-        return None
+def _cached_workspace(cache: dict, nbytes: int, device) -> torch.Tensor:
+    """One scratch buffer per (device, current stream), grown on demand.  Calls
+    enqueued on one stream run in order, so they can share it; calls on
+    different streams get different buffers."""
     key = (str(device), torch.cuda.current_stream(device).cuda_stream)
-    ws = _WORKSPACE.get(key)
+    ws = cache.get(key)
     if ws is None or ws.numel() < nbytes:
         ws = torch.empty(nbytes, dtype=torch.uint8, device=device)
-        _WORKSPACE[key] = ws
+        cache[key] = ws
     return ws
 
 
+def workspace(grid: Grid, n_landmarks: int, prec: int, device) -> torch.Tensor | None:
+    """Scratch for the spatially sorted build (see _cached_workspace)."""
+    nbytes = int(lib().fif_workspace_bytes(ctypes.byref(grid.c()), int(n_landmarks), prec))
+    if nbytes == 0:
+        return None
+    return _cached_workspace(_WORKSPACE, nbytes, device)
+
+
 def release_workspaces() -> None:
-    """Drop the cached build workspaces (one per device and stream used so far).
-    The memory returns to torch's caching allocator, which reuses it in stream
-    order, so builds still in flight are not disturbed."""
+    """Drop the cached build and point-cloud workspaces (one per device and
+    stream used so far).  The memory returns to torch's caching allocator,
+    which reuses it in stream order, so calls still in flight are not
+    disturbed."""
     _WORKSPACE.clear()
+    _PC_WORKSPACE.clear()
 
 
 @_on_stream
@@ -392,7 +402,11 @@ def view_sweep(field: Field, t: torch.Tensor, dirs: torch.Tensor, metric: int = 
 @_on_stream
 def pc_query(landmarks: torch.Tensor, vis: Vis, t: torch.Tensor, q: torch.Tensor,
              metrics: int = TRACE | LMIN | LOGDET, prec: int = FP32_COMP, pinhole=None,
-             out: torch.Tensor | None = None, stream=None):
+             out: torch.Tensor | None = None, sort: bool = True, stream=None):
+    """Point-cloud FIMs.  With sort (the default) landmarks and poses are
+    ordered spatially in a workspace and landmark batches out of range of a
+    group of poses are skipped; without it every pair is tested in input
+    order."""
     lm = _dev(landmarks, torch.float64, "landmarks", 3)
     dt = torch.float64 if prec == FP64 else torch.float32
     t = _dev(t, dt, "t", 3)
@@ -404,8 +418,13 @@ def pc_query(landmarks: torch.Tensor, vis: Vis, t: torch.Tensor, q: torch.Tensor
     if pinhole is not None:
         fx, fy, cx, cy, W, H = pinhole
         cam = ctypes.byref(CPinhole(fx, fy, cx, cy, int(W), int(H)))
+    ws = None
+    if sort and lm.shape[0] > 0 and m > 0 and math.isfinite(vis.r_max):
+        nbytes = int(lib().pc_workspace_bytes(lm.shape[0], m, prec))
+        ws = _cached_workspace(_PC_WORKSPACE, nbytes, lm.device) if nbytes else None
     _check(lib().pc_query(_ptr(lm), lm.shape[0], ctypes.byref(vis.c()), cam, prec, _ptr(t),
-                          _ptr(q), m, metrics, _ptr(out), _stream(stream)), "pc_query")
+                          _ptr(q), m, metrics, _ptr(out), _ptr(ws),
+                          ws.numel() if ws is not None else 0, _stream(stream)), "pc_query")
     return out
 
 

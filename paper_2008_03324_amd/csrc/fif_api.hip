@@ -179,6 +179,8 @@ static fif_status build_common(const double* landmarks, int64_t n_landmarks, fif
   a.skip2 = INFINITY;
   if (workspace && n_landmarks > 0) {
     if (!aligned(workspace, 256)) return fail(FIF_EINVAL, "workspace must be 256-byte aligned%s");
+    if (n_landmarks >= ((int64_t)1 << 32))
+      return fail(FIF_EUNSUPPORTED, "the sorted build orders fewer than 2^32 landmarks%s");
     const size_t need = fif::sort_workspace_bytes(n_landmarks);
     if (need == 0) return fail(FIF_EDEVICE, "cannot size the landmark sort%s");
     if (ws_bytes < need) return fail(FIF_ENOMEM, "workspace smaller than fif_workspace_bytes()%s");
@@ -334,9 +336,16 @@ fif_status fif_query_grad(const fif_field* field, const void* t, const void* q, 
                       dL_dt, dL_dphi, stream, "fif_query_grad");
 }
 
+size_t pc_workspace_bytes(int64_t n_landmarks, int64_t m, int32_t prec) {
+  if (!prec_ok(prec) || n_landmarks <= 0 || m <= 0) return 0;
+  if (n_landmarks >= ((int64_t)1 << 32)) return 0;
+  return fif::pc_sorted_workspace_bytes(n_landmarks, m);
+}
+
 fif_status pc_query(const double* landmarks, int64_t n_landmarks, const fif_vis* vis,
                     const fif_pinhole* cam, int32_t prec, const void* t, const void* q,
-                    int64_t m, uint32_t metrics, double* out, void* stream) {
+                    int64_t m, uint32_t metrics, double* out, void* workspace,
+                    size_t workspace_bytes, void* stream) {
   if (!vis_ok(vis)) return fail(FIF_EINVAL, "invalid visibility parameters%s");
   if (!prec_ok(prec)) return fail(FIF_EINVAL, "invalid precision%s");
   if (n_landmarks < 0 || m < 0) return fail(FIF_EINVAL, "negative size%s");
@@ -368,6 +377,21 @@ fif_status pc_query(const double* landmarks, int64_t n_landmarks, const fif_vis*
   a.metrics = metrics;
   a.ncols = metric_cols(metrics);
   a.out = out;
+  // with a workspace and a finite range: the sorted, batch-culled pass (with
+  // an unbounded range no batch could be skipped, so the plain pass runs)
+  if (workspace && !aligned(workspace, 256))
+    return fail(FIF_EINVAL, "workspace must be 256-byte aligned%s");
+  if (workspace && n_landmarks > 0 && !isinf(a.hi2)) {
+    if (n_landmarks >= ((int64_t)1 << 32))
+      return fail(FIF_EUNSUPPORTED, "the sorted pass orders fewer than 2^32 landmarks%s");
+    const size_t need = fif::pc_sorted_workspace_bytes(n_landmarks, m);
+    if (need == 0) return fail(FIF_EDEVICE, "cannot size the point-cloud sort%s");
+    if (workspace_bytes < need)
+      return fail(FIF_ENOMEM, "workspace smaller than pc_workspace_bytes()%s");
+    a.inv_cell = 32.0 / vis->r_max;
+    hipError_t e = fif::launch_pc_sorted(a, prec, workspace, workspace_bytes, (hipStream_t)stream);
+    return device_status(e, "pc_query");
+  }
   hipError_t e = fif::launch_pc(a, prec, (hipStream_t)stream);
   return device_status(e, "pc_query");
 }
@@ -466,6 +490,8 @@ fif_status fif_gp_build(const double* landmarks, int64_t n_landmarks, fif_gp_fie
   b.skip2 = INFINITY;
   if (workspace && n_landmarks > 0) {
     if (!aligned(workspace, 256)) return fail(FIF_EINVAL, "workspace must be 256-byte aligned%s");
+    if (n_landmarks >= ((int64_t)1 << 32))
+      return fail(FIF_EUNSUPPORTED, "the sorted build orders fewer than 2^32 landmarks%s");
     const size_t need = fif::sort_workspace_bytes(n_landmarks);
     if (need == 0) return fail(FIF_EDEVICE, "cannot size the landmark sort%s");
     if (workspace_bytes < need) return fail(FIF_ENOMEM, "workspace smaller than fif_workspace_bytes()%s");

@@ -102,7 +102,7 @@ __device__ inline void trace_pair(T acc[10], T dx, T dy, T dz, T rn, T px, T py,
 template <typename T>
 __device__ inline T inv_sqrt(T x);
 template <>
-__device__ inline float inv_sqrt<float>(float x) { return rsqrtf(x); }
+__device__ inline float inv_sqrt<float>(float x) { return rsq_normal(x); }
 template <>
 __device__ inline double inv_sqrt<double>(double x) { return 1.0 / sqrt(x); }
 
@@ -354,6 +354,32 @@ __global__ void morton_kernel(const double* lm, int64_t L, double lox, double lo
   idx[i] = (uint32_t)i;
 }
 
+// 30-bit Morton code of the cell of each of n points (x, y, z at stride 3):
+// cell index floor(x * inv_cell) per axis, taken modulo 1024, so points far
+// apart may share a code (that only costs culling, never a result).  The cell
+// size does not depend on the data, so the order is reproducible from the
+// coordinates alone.  idx[i] = i.
+template <typename T>
+__global__ void morton_cell_kernel(const T* xyz, int64_t n, double inv_cell, uint32_t* keys,
+                                   uint32_t* idx) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= n) return;
+  uint32_t c[3];
+#pragma unroll
+  for (int ax = 0; ax < 3; ++ax) {
+    double g = floor((double)xyz[3 * i + ax] * inv_cell);
+    g = fmin(fmax(g, -1.0e18), 1.0e18);  // NaN -> -1e18
+    c[ax] = (uint32_t)((long long)g & 1023);
+  }
+  uint32_t code = 0;
+#pragma unroll
+  for (int b = 9; b >= 0; --b)
+#pragma unroll
+    for (int ax = 0; ax < 3; ++ax) code = (code << 1) | ((c[ax] >> b) & 1u);
+  keys[i] = code;
+  idx[i] = (uint32_t)i;
+}
+
 // Sorted landmarks and the FP32 bounding box of each batch of kBatch.
 __global__ __launch_bounds__(kBatch) void gather_box_kernel(const double* lm, int64_t L,
                                                             const uint32_t* idx, double4* out,
@@ -418,6 +444,83 @@ size_t radix_tmp_bytes(int64_t L) {
   return e == hipSuccess ? bytes : 0;
 }
 }  // namespace
+
+namespace {
+struct CellSortLayout {
+  size_t keys_in, keys_out, idx_in, idx_out, tmp, total;
+};
+CellSortLayout cell_sort_layout(int64_t n, size_t tmp_bytes) {
+  CellSortLayout s;
+  size_t off = 0;
+  s.keys_in = off; off = align256(off + 4 * (size_t)n);
+  s.keys_out = off; off = align256(off + 4 * (size_t)n);
+  s.idx_in = off; off = align256(off + 4 * (size_t)n);
+  s.idx_out = off; off = align256(off + 4 * (size_t)n);
+  s.tmp = off; off = align256(off + tmp_bytes);
+  s.total = off;
+  return s;
+}
+}  // namespace
+
+size_t cell_sort_bytes(int64_t n) {
+  if (n <= 0) return 0;
+  const size_t tmp = radix_tmp_bytes(n);
+  return tmp == 0 ? 0 : cell_sort_layout(n, tmp).total;
+}
+
+hipError_t cell_sort(const void* xyz, bool dbl, int64_t n, double inv_cell, void* ws,
+                     size_t ws_bytes, hipStream_t stream, const uint32_t** order) {
+  const size_t tmp = radix_tmp_bytes(n);
+  const CellSortLayout lay = cell_sort_layout(n, tmp);
+  if (tmp == 0 || ws_bytes < lay.total) return hipErrorInvalidValue;
+  char* base = reinterpret_cast<char*>(ws);
+  uint32_t* kin = reinterpret_cast<uint32_t*>(base + lay.keys_in);
+  uint32_t* kout = reinterpret_cast<uint32_t*>(base + lay.keys_out);
+  uint32_t* iin = reinterpret_cast<uint32_t*>(base + lay.idx_in);
+  uint32_t* iout = reinterpret_cast<uint32_t*>(base + lay.idx_out);
+  const unsigned nblk = (unsigned)((n + 255) / 256);
+  if (dbl)
+    hipLaunchKernelGGL((morton_cell_kernel<double>), dim3(nblk), dim3(256), 0, stream,
+                       static_cast<const double*>(xyz), n, inv_cell, kin, iin);
+  else
+    hipLaunchKernelGGL((morton_cell_kernel<float>), dim3(nblk), dim3(256), 0, stream,
+                       static_cast<const float*>(xyz), n, inv_cell, kin, iin);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  size_t tb = tmp;
+  e = rocprim::radix_sort_pairs(base + lay.tmp, tb, kin, kout, iin, iout, (size_t)n, 0, 30,
+                                stream);
+  if (e != hipSuccess) return e;
+  *order = iout;
+  return hipSuccess;
+}
+
+size_t cell_sorted_landmarks_bytes(int64_t L) {
+  const size_t cs = cell_sort_bytes(L);
+  if (cs == 0) return 0;
+  return cs + align256(32 * (size_t)L) + align256(32 * (size_t)((L + kBatch - 1) / kBatch));
+}
+
+hipError_t cell_sort_landmarks(const double* lm, int64_t L, double inv_cell, void* ws,
+                               size_t ws_bytes, hipStream_t stream, const double4** sorted,
+                               const float** boxes) {
+  const size_t cs = cell_sort_bytes(L);
+  if (cs == 0 || ws_bytes < cell_sorted_landmarks_bytes(L)) return hipErrorInvalidValue;
+  const uint32_t* order = nullptr;
+  hipError_t e = cell_sort(lm, true, L, inv_cell, ws, cs, stream, &order);
+  if (e != hipSuccess) return e;
+  char* base = reinterpret_cast<char*>(ws) + cs;
+  double4* out = reinterpret_cast<double4*>(base);
+  float* bx = reinterpret_cast<float*>(base + align256(32 * (size_t)L));
+  const unsigned nbatch = (unsigned)((L + kBatch - 1) / kBatch);
+  hipLaunchKernelGGL(gather_box_kernel, dim3(nbatch), dim3(kBatch), 0, stream, lm, L, order, out,
+                     bx);
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  *sorted = out;
+  *boxes = bx;
+  return hipSuccess;
+}
 
 size_t sort_workspace_bytes(int64_t L) {
   if (L <= 0) return 0;

@@ -85,6 +85,13 @@ __host__ __device__ constexpr int u21(int i, int j) {  // i <= j < 6
 }
 __host__ __device__ constexpr int su21(int i, int j) { return i <= j ? u21(i, j) : u21(j, i); }
 
+// 1/sqrt(x) by the hardware instruction (v_rsq_f32).  rsqrtf wraps it in a
+// rescaling for x below the smallest normal FP32 number; the kernels call this
+// only on squared landmark distances that passed the range predicate (n^2 >=
+// 1e-12, or an FP64-derived n^2 of the same pair, far above that), where the
+// two give the same value.
+__device__ inline float rsq_normal(float x) { return __builtin_amdgcn_rsqf(x); }
+
 // ------------------------------------------------------------ pose helpers
 
 // Optical axis z = R(q) e3 for a quaternion (w, x, y, z) of any norm.

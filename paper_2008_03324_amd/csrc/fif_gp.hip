@@ -322,7 +322,7 @@ __global__ __launch_bounds__(kGPThreads) void gp_build_kernel(GPBuildArgs a, int
                                      : (T)__fmaf_rn((float)dz, (float)dz,
                                                     __fmaf_rn((float)dy, (float)dy,
                                                               (float)dx * (float)dx));
-            const T rn = (PREC == 2) ? (T)(1.0 / sqrt((double)nn)) : (T)rsqrtf((float)nn);
+            const T rn = (PREC == 2) ? (T)(1.0 / sqrt((double)nn)) : (T)rsq_normal((float)nn);
             rec.x = dx * rn; rec.y = dy * rn; rec.z = dz * rn;
             if constexpr (KIND == 0) {
               rec.w = rn;

@@ -64,6 +64,15 @@ struct PcArgs {
   uint32_t metrics;
   int32_t ncols;
   double* out;
+  // sorted path (null for the plain one): landmarks in cell order with FP32
+  // boxes of each batch, a batch skipped by a workgroup whose poses' box is
+  // farther than sqrt(skip2) from it, and the pose order (lane i of the launch
+  // takes pose perm[i] and writes its row)
+  const double4* lm_sorted;
+  const float* batch_box;
+  float skip2;
+  const uint32_t* perm;
+  double inv_cell;  // 32 / r_max: cells of the spatial order
 };
 
 struct ExportArgs {
@@ -171,6 +180,20 @@ size_t sort_workspace_bytes(int64_t L);
 hipError_t sort_landmarks(BuildArgs& a, void* ws, size_t ws_bytes, hipStream_t stream);
 hipError_t launch_query(const QueryArgs& a, int prec, int kind, bool grad, hipStream_t stream);
 hipError_t launch_pc(const PcArgs& a, int prec, hipStream_t stream);
+// Order of n points (x, y, z at stride 3; double or float) by the Morton code
+// of their cell of edge 1 / inv_cell (cell indices modulo 1024): scratch bytes,
+// and the stable sort itself (*order points into ws).
+size_t cell_sort_bytes(int64_t n);
+hipError_t cell_sort(const void* xyz, bool dbl, int64_t n, double inv_cell, void* ws,
+                     size_t ws_bytes, hipStream_t stream, const uint32_t** order);
+// Landmarks copied in that order with the FP32 box of each batch of 256.
+size_t cell_sorted_landmarks_bytes(int64_t L);
+hipError_t cell_sort_landmarks(const double* lm, int64_t L, double inv_cell, void* ws,
+                               size_t ws_bytes, hipStream_t stream, const double4** sorted,
+                               const float** boxes);
+// Sorted, culled point cloud: workspace bytes, and the whole pass.
+size_t pc_sorted_workspace_bytes(int64_t L, int64_t m);
+hipError_t launch_pc_sorted(PcArgs a, int prec, void* ws, size_t ws_bytes, hipStream_t stream);
 hipError_t launch_export(const ExportArgs& a, int prec, int kind, hipStream_t stream);
 
 }  // namespace fif

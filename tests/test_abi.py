@@ -85,10 +85,17 @@ def test_host_side_validation_returns_einval():
                             None) == -4
     badvis = fif.Vis(sigma=0.0)
     assert L.pc_query(None, 0, ctypes.byref(badvis.c()), None, 2, None, None, 1, 1, None,
-                      None) == -1
+                      None, 0, None) == -1
     cam = fif.CPinhole(-1.0, 300.0, 300.0, 300.0, 600, 600)
     assert L.pc_query(None, 0, ctypes.byref(vis.c()), ctypes.byref(cam), 2, None, None, 1, 1,
-                      None, None) == -1
+                      None, None, 0, None) == -1
+    # a misaligned point-cloud workspace is refused before anything runs
+    vis15 = fif.Vis(r_max=15.0)
+    assert L.pc_query(4096, 10, ctypes.byref(vis15.c()), None, 2, 4096, 4096, 1, 1, 4096, 4100,
+                      1 << 20, None) == -1
+    assert b"aligned" in L.fif_last_error()
+    assert L.pc_workspace_bytes(0, 10, 1) == 0 and L.pc_workspace_bytes(10, 0, 1) == 0
+    assert L.pc_workspace_bytes(10, 10, 7) == 0
     assert L.fif_field_export(ctypes.byref(f), None, 3, None, None) == -1
     # view sweep: exactly one metric, information fields, valid interp, t/dirs
     assert L.fif_view_sweep(ctypes.byref(f), None, 4, None, 8, 3, 0, None, None, None) == -1

@@ -43,7 +43,7 @@ int main(void) {
   CHECK(fif_build(NULL, 10, &f, NULL, 0, NULL) == FIF_EINVAL);
   CHECK(strlen(fif_last_error()) > 0);
   CHECK(fif_query(&f, NULL, NULL, 10, FIF_TRACE, FIF_TRILINEAR, NULL, NULL, NULL) == FIF_EINVAL);
-  CHECK(pc_query(NULL, 10, &f.vis, NULL, FIF_FP64, NULL, NULL, 10, FIF_TRACE, NULL, NULL) ==
+  CHECK(pc_query(NULL, 10, &f.vis, NULL, FIF_FP64, NULL, NULL, 10, FIF_TRACE, NULL, NULL, 0, NULL) ==
         FIF_EINVAL);
   printf("%s\n", fails ? "FAILED" : "OK");
   return fails ? 1 : 0;

@@ -113,6 +113,60 @@ def test_point_cloud_sampled_vs_oracle(fif, bld):
     assert e_fim(out[:, 3:], ref[:, 3:]).max() <= 1e-4
 
 
+def cell_order(pts, r_max):
+    """The spatial order of pc_query's sorted pass, as its header defines it:
+    the Morton code of the cell floor(x * 32 / r_max) (per axis, modulo 1024;
+    x bit b of the cell at code bit 3b + 2, y at 3b + 1, z at 3b), sorted
+    stably."""
+    g = np.floor(np.asarray(pts, np.float64) * (32.0 / r_max))
+    c = np.fmin(np.fmax(g, -1e18), 1e18).astype(np.int64) & 1023
+    code = np.zeros(len(c), np.int64)
+    for b in range(10):
+        for ax, shift in ((0, 2), (1, 1), (2, 0)):
+            code |= ((c[:, ax] >> b) & 1) << (3 * b + shift)
+    return np.argsort(code, kind="stable")
+
+
+def test_sorted_point_cloud_equals_plain_in_cell_order(fif, bld):
+    """The sorted, batch-culled point cloud skips only batches that hold no
+    landmark in range: it equals the plain pass given the landmarks in the same
+    cell order, bit for bit (all three precisions; quadratic and pinhole
+    visibility; ragged pose counts), and the plain pass in input order within
+    rounding."""
+    print("case: building scene, sorted point cloud vs plain in cell order", flush=True)
+    v = bld["v"]
+    order = cell_order(bld["lm"], v.r_max)
+    lm_cell = torch.from_numpy(np.ascontiguousarray(bld["lm"][order])).cuda()
+    m = 300_000
+    cols = M7 | 8
+    for prec, dt in ((fif.FP32_COMP, torch.float32), (fif.FP32_NAIVE, torch.float32),
+                     (fif.FP64, torch.float64)):
+        t = bld["t_d"][:m].to(dt).contiguous()
+        q = bld["q_d"][:m].to(dt).contiguous()
+        a = fif.pc_query(bld["lm_d"], bld["vis"], t, q, cols, prec=prec, sort=True)
+        b = fif.pc_query(lm_cell, bld["vis"], t, q, cols, prec=prec, sort=False)
+        same = torch.equal(a.nan_to_num(7.0), b.nan_to_num(7.0))
+        print(prec, "sorted vs plain in cell order:", "bitwise equal" if same else "DIFFERENT",
+              flush=True)
+        assert same
+        if prec == fif.FP32_COMP:
+            c = fif.pc_query(bld["lm_d"], bld["vis"], t, q, cols, prec=prec, sort=False)
+            a_, c_ = a.cpu().numpy(), c.cpu().numpy()
+            assert e_fim(a_[:, 3:], c_[:, 3:]).max() <= 1e-5
+    # pinhole visibility, and ragged sizes
+    t, q = bld["t_d"][:100_000].contiguous(), bld["q_d"][:100_000].contiguous()
+    a = fif.pc_query(bld["lm_d"], bld["vis"], t, q, cols, prec=fif.FP32_COMP,
+                     pinhole=scenes.PINHOLE, sort=True)
+    b = fif.pc_query(lm_cell, bld["vis"], t, q, cols, prec=fif.FP32_COMP,
+                     pinhole=scenes.PINHOLE, sort=False)
+    assert torch.equal(a.nan_to_num(7.0), b.nan_to_num(7.0))
+    for mm in (1, 255, 257, 70_001):
+        a = fif.pc_query(bld["lm_d"], bld["vis"], t[:mm].contiguous(), q[:mm].contiguous(), M7)
+        b = fif.pc_query(lm_cell, bld["vis"], t[:mm].contiguous(), q[:mm].contiguous(), M7,
+                         sort=False)
+        assert torch.equal(a.nan_to_num(7.0), b.nan_to_num(7.0)), mm
+
+
 def test_exact_point_cloud_sampled_vs_oracle(fif, bld):
     """Pinhole visibility (600 x 600 px, f = 300) at the building scale: FP64
     and FP32-compensated sums against the oracle on sampled poses.  A landmark

@@ -61,9 +61,11 @@ def test_trace_query_and_point_cloud_past_one_launch(fif, big_poses):
     _check_rows(out, lambda a, b: fif.query(tf, a, b, fif.TRACE), t, q)
     del out
     few = lm_d[:50].contiguous()
-    pc = fif.pc_query(few, vis, t, q, fif.TRACE, prec=fif.FP32_COMP)
-    _check_rows(pc, lambda a, b: fif.pc_query(few, vis, a, b, fif.TRACE, prec=fif.FP32_COMP),
-                t, q)
+    for sort in (True, False):  # poses sorted in passes of 2^26, and the plain pass
+        pc = fif.pc_query(few, vis, t, q, fif.TRACE, prec=fif.FP32_COMP, sort=sort)
+        _check_rows(pc, lambda a, b: fif.pc_query(few, vis, a, b, fif.TRACE,
+                                                  prec=fif.FP32_COMP, sort=sort), t, q)
+        del pc
 
 
 def test_gp_trace_query_and_export_past_one_launch(fif, big_poses):
