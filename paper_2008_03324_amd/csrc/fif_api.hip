@@ -176,7 +176,10 @@ static fif_status build_common(const double* landmarks, int64_t n_landmarks, fif
   a.sign = sign;
   a.lm_sorted = nullptr;
   a.batch_box = nullptr;
+  a.slice_box = nullptr;
   a.skip2 = INFINITY;
+  a.inside_lo2 = INFINITY;  // set by the sort when there is one
+  a.inside_hi2 = -INFINITY;
   if (workspace && n_landmarks > 0) {
     if (!aligned(workspace, 256)) return fail(FIF_EINVAL, "workspace must be 256-byte aligned%s");
     if (n_landmarks >= ((int64_t)1 << 32))

@@ -99,6 +99,11 @@ __device__ inline void trace_pair(T acc[10], T dx, T dy, T dz, T rn, T px, T py,
   acc[9] += tr;
 }
 
+// A value equal on every lane of the wave, moved to a scalar register.
+__device__ inline float uniform_f(float x) {
+  return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(x)));
+}
+
 template <typename T>
 __device__ inline T inv_sqrt(T x);
 template <>
@@ -129,13 +134,16 @@ __device__ inline void store_vec(T* dst, const T* v) {
 
 // PREC: FIF_FP32_NAIVE / FIF_FP32_COMP / FIF_FP64; KIND: info or trace.
 template <int PREC, int KIND>
-__global__ __launch_bounds__(kBuildThreads) void build_kernel(BuildArgs a) {
+__global__ __launch_bounds__(kBuildThreads, 2) void build_kernel(BuildArgs a) {
   using T = typename std::conditional<PREC == 2, double, float>::type;
   using L4 = typename LmT<T>::type;
   constexpr int NACC = (KIND == 0) ? kMom : 10;
   constexpr bool COMP = (PREC == 1);
 
   __shared__ L4 s_lm[kBatch];
+  // the compensated sums' low parts: touched once per batch (in the fold), so
+  // they live in LDS, one column per lane, leaving registers to the pair loops
+  __shared__ float s_lo[COMP ? NACC : 1][kBuildThreads];
 
   const int tid = threadIdx.x;
   const int wave = tid >> 6, lane = tid & 63;
@@ -160,12 +168,12 @@ __global__ __launch_bounds__(kBuildThreads) void build_kernel(BuildArgs a) {
   const float near2 = 1e-4f * (fx * fx + fy * fy + fz * fz) + 1e-4f;
 
   T acc[NACC];
-  float hi[COMP ? NACC : 1], lo[COMP ? NACC : 1];
+  float hi[COMP ? NACC : 1];
 #pragma unroll
   for (int i = 0; i < NACC; ++i) acc[i] = T(0);
   if (COMP) {
 #pragma unroll
-    for (int i = 0; i < NACC; ++i) { hi[i] = 0.f; lo[i] = 0.f; }
+    for (int i = 0; i < NACC; ++i) { hi[i] = 0.f; s_lo[i][tid] = 0.f; }
   }
 
   // workgroup tile bounds (voxel centres, FP32 like the range test)
@@ -184,6 +192,29 @@ __global__ __launch_bounds__(kBuildThreads) void build_kernel(BuildArgs a) {
       m2 = fmaf(e, e, m2);
     }
     near2_tile = 1.0001f * (1e-4f * m2 + 1e-4f);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {  // uniform: keep them in scalar registers
+      tlo[c] = uniform_f(tlo[c]);
+      thi[c] = uniform_f(thi[c]);
+    }
+    near2_tile = uniform_f(near2_tile);
+  }
+  // the wave's own 4x4x4 voxel centres (FP32), for the per-slice decisions of
+  // the compensated build; a wave wholly past the grid edge has none
+  float wlo[3] = {0.f, 0.f, 0.f}, whi[3] = {0.f, 0.f, 0.f};
+  const int wx0 = blockIdx.x * 8 + (wave & 1) * 4, wy0 = blockIdx.y * 8 + (wave >> 1) * 4;
+  const bool wave_empty = wx0 >= a.g.nx || wy0 >= a.g.ny || (int)blockIdx.z * 4 >= a.g.nz;
+  if (COMP && a.slice_box) {
+    const int x0 = wx0, y0 = wy0, z0 = blockIdx.z * 4;
+    const int x1 = min(x0 + 3, a.g.nx - 1), y1 = min(y0 + 3, a.g.ny - 1), z1 = min(z0 + 3, a.g.nz - 1);
+    wlo[0] = (float)(a.g.ox + x0 * a.g.h); whi[0] = (float)(a.g.ox + x1 * a.g.h);
+    wlo[1] = (float)(a.g.oy + y0 * a.g.h); whi[1] = (float)(a.g.oy + y1 * a.g.h);
+    wlo[2] = (float)(a.g.oz + z0 * a.g.h); whi[2] = (float)(a.g.oz + z1 * a.g.h);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      wlo[c] = uniform_f(wlo[c]);
+      whi[c] = uniform_f(whi[c]);
+    }
   }
   for (int64_t base = 0; base < a.L; base += kBatch) {
     const int nb = (int)((a.L - base) < kBatch ? (a.L - base) : kBatch);
@@ -203,43 +234,53 @@ __global__ __launch_bounds__(kBuildThreads) void build_kernel(BuildArgs a) {
       batch_near = d2 <= near2_tile;
     }
     __syncthreads();
-    if (tid < nb) {
-      double px, py, pz;
-      if (a.lm_sorted) {
-        const double4 p4 = a.lm_sorted[base + tid];
-        px = p4.x; py = p4.y; pz = p4.z;
-      } else {
-        const double* p = a.lm + 3 * (base + tid);
-        px = p[0]; py = p[1]; pz = p[2];
-      }
+    {
       L4 v;
-      v.x = (T)px; v.y = (T)py; v.z = (T)pz;
-      v.w = (T)(px * px + py * py + pz * pz);
+      if (tid < nb) {
+        double px, py, pz;
+        if (a.lm_sorted) {
+          const double4 p4 = a.lm_sorted[base + tid];
+          px = p4.x; py = p4.y; pz = p4.z;
+        } else {
+          const double* p = a.lm + 3 * (base + tid);
+          px = p[0]; py = p[1]; pz = p[2];
+        }
+        v.x = (T)px; v.y = (T)py; v.z = (T)pz;
+        v.w = (T)(px * px + py * py + pz * pz);
+      } else {
+        // padding past the last landmark: NaN fails the FP32 range test, so
+        // the loops below need no bound
+        v.x = v.y = v.z = v.w = (T)__builtin_nanf("");
+      }
       s_lm[tid] = v;
     }
     __syncthreads();
-    // landmarks in groups of 4: the LDS reads of a group are issued together;
-    // the loop is instantiated with and without the near-landmark test
-    auto pairs = [&](auto near_test) __attribute__((always_inline)) {
+    // landmarks [ibeg, iend) in groups of 4: the LDS reads of a group are
+    // issued together.  INSIDE: every pair is known to pass the range test
+    // (lanes past the grid edge then compute pairs they never store); NEAR_TEST:
+    // the compensated build's near-landmark test, taken where near_on.
+    auto pairs = [&](auto near_test, auto inside, int ibeg, int iend,
+                     bool near_on) __attribute__((always_inline)) {
     constexpr bool NEAR_TEST = decltype(near_test)::value;
-    for (int i0 = 0; i0 < nb; i0 += 4) {
+    constexpr bool INSIDE = decltype(inside)::value;
+    for (int i0 = ibeg; i0 < iend; i0 += 4) {
       L4 pg[4];
 #pragma unroll
-      for (int k = 0; k < 4; ++k) pg[k] = s_lm[(i0 + k < nb) ? i0 + k : i0];
+      for (int k = 0; k < 4; ++k) pg[k] = s_lm[i0 + k];
 #pragma unroll
       for (int k = 0; k < 4; ++k) {
         const L4 p = pg[k];
         // V_t range test in FP32 (same decision in every precision)
         float ddx = (float)p.x - fx, ddy = (float)p.y - fy, ddz = (float)p.z - fz;
         float n2 = __fmaf_rn(ddz, ddz, __fmaf_rn(ddy, ddy, ddx * ddx));
-        bool in = valid && (i0 + k < nb) && (n2 >= a.lo2) && (n2 <= a.hi2);
+        bool in = INSIDE || (valid && (n2 >= a.lo2) && (n2 <= a.hi2));
         if (in) {
           T dx = p.x - vx, dy = p.y - vy, dz = p.z - vz;
           T nn = (PREC == 2)
                      ? (T)fma((double)dz, (double)dz, fma((double)dy, (double)dy, (double)dx * dx))
                      : (T)n2;
           if constexpr (COMP && NEAR_TEST) {
-            if (n2 < near2) {
+            if (near_on && n2 < near2) {
               const int64_t li = base + i0 + k;
               double qx, qy, qz;
               if (a.lm_sorted) {
@@ -258,19 +299,53 @@ __global__ __launch_bounds__(kBuildThreads) void build_kernel(BuildArgs a) {
           else
             trace_pair<T>(acc, dx, dy, dz, rn, p.x, p.y, p.z, p.w);
         }
+        // with no branch between them the scheduler would interleave the
+        // group's pairs, with the temporaries of four pairs live at once
+        if constexpr (INSIDE) __builtin_amdgcn_sched_barrier(0);
       }
     }
     };
+    const int nb4 = (nb + 3) & ~3;
+    // The compensated build goes through a batch in slices of 64 landmarks and
+    // decides per wave: skip a slice out of range of the wave's voxels, run a
+    // full slice wholly in range of them without the range test, test each
+    // pair otherwise.  The pairs and their order are those of one pass over
+    // the batch.  (Only the compensated build: it holds 255 VGPRs whatever the
+    // loop, while a second copy of the loop costs the other variants
+    // occupancy.)
     if constexpr (COMP) {
-      if (batch_near) pairs(std::true_type{});
-      else pairs(std::false_type{});
+      if (!wave_empty) {
+        for (int sl = 0; 64 * sl < nb; ++sl) {
+          bool inside = false, near_on = batch_near;
+          if (a.slice_box) {
+            const float* sb = a.slice_box + 8 * (4 * (base / kBatch) + sl);
+            float d2 = 0.f, far2 = 0.f;
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+              const float gap = fmaxf(fmaxf(sb[c] - whi[c], wlo[c] - sb[3 + c]), 0.f);
+              d2 = fmaf(gap, gap, d2);
+              const float far = fmaxf(fabsf(sb[3 + c] - wlo[c]), fabsf(whi[c] - sb[c]));
+              far2 = fmaf(far, far, far2);
+            }
+            if (d2 > a.skip2) continue;  // wave-uniform
+            near_on = batch_near && d2 <= near2_tile;
+            inside = !near_on && 64 * sl + 64 <= nb && d2 >= a.inside_lo2 && far2 <= a.inside_hi2;
+          }
+          if (inside)
+            pairs(std::false_type{}, std::true_type{}, 64 * sl, 64 * sl + 64, false);
+          else
+            pairs(std::true_type{}, std::false_type{}, 64 * sl, min(64 * sl + 64, nb4), near_on);
+        }
+      }
     } else {
-      pairs(std::false_type{});
+      pairs(std::false_type{}, std::false_type{}, 0, nb4, false);
     }
     if (COMP) {
 #pragma unroll
       for (int k = 0; k < NACC; ++k) {
-        two_sum_into(hi[k], lo[k], (float)acc[k]);
+        float l = s_lo[k][tid];
+        two_sum_into(hi[k], l, (float)acc[k]);
+        s_lo[k][tid] = l;
         acc[k] = T(0);
       }
     }
@@ -280,7 +355,7 @@ __global__ __launch_bounds__(kBuildThreads) void build_kernel(BuildArgs a) {
   const size_t nvox = (size_t)a.g.nx * a.g.ny * a.g.nz;
   T res[NACC];
 #pragma unroll
-  for (int k = 0; k < NACC; ++k) res[k] = COMP ? (T)(hi[k] + lo[k]) : acc[k];
+  for (int k = 0; k < NACC; ++k) res[k] = COMP ? (T)(hi[k] + s_lo[k][tid]) : acc[k];
   if constexpr (KIND == 0) {
     T* main = reinterpret_cast<T*>(a.out) + vox * kMain;
     T* side = reinterpret_cast<T*>(a.out) + nvox * kMain + vox * kSideRec;  // slot 0
@@ -380,10 +455,12 @@ __global__ void morton_cell_kernel(const T* xyz, int64_t n, double inv_cell, uin
   idx[i] = (uint32_t)i;
 }
 
-// Sorted landmarks and the FP32 bounding box of each batch of kBatch.
+// Sorted landmarks and the FP32 bounding box of each batch of kBatch, and
+// (when slices != nullptr) of each slice of 64 landmarks: slices[8 (4 b + s) +
+// c] (min xyz, max xyz, 2 pad; an empty slice gets min = +inf, max = -inf).
 __global__ __launch_bounds__(kBatch) void gather_box_kernel(const double* lm, int64_t L,
                                                             const uint32_t* idx, double4* out,
-                                                            float* boxes) {
+                                                            float* boxes, float* slices) {
   __shared__ float s_min[3][kBatch], s_max[3][kBatch];
   const int64_t i = (int64_t)blockIdx.x * kBatch + threadIdx.x;
   float mn[3] = {INFINITY, INFINITY, INFINITY}, mx[3] = {-INFINITY, -INFINITY, -INFINITY};
@@ -396,6 +473,20 @@ __global__ __launch_bounds__(kBatch) void gather_box_kernel(const double* lm, in
     mn[0] = mx[0] = (float)x;
     mn[1] = mx[1] = (float)y;
     mn[2] = mx[2] = (float)z;
+  }
+  if (slices) {
+    float v[6] = {mn[0], mn[1], mn[2], -mx[0], -mx[1], -mx[2]};
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1)
+#pragma unroll
+      for (int c = 0; c < 6; ++c) v[c] = fminf(v[c], __shfl_xor(v[c], off, 64));
+    if ((threadIdx.x & 63) < 8) {
+      const int c = threadIdx.x & 63;
+      float w = 0.f;
+#pragma unroll
+      for (int k = 0; k < 6; ++k) w = (c == k) ? (k < 3 ? v[k] : -v[k]) : w;
+      slices[8 * (4 * (int64_t)blockIdx.x + (threadIdx.x >> 6)) + c] = w;
+    }
   }
 #pragma unroll
   for (int c = 0; c < 3; ++c) { s_min[c][threadIdx.x] = mn[c]; s_max[c][threadIdx.x] = mx[c]; }
@@ -420,7 +511,7 @@ __global__ __launch_bounds__(kBatch) void gather_box_kernel(const double* lm, in
 
 namespace {
 struct SortLayout {
-  size_t keys_in, keys_out, idx_in, idx_out, sorted, boxes, tmp, total;
+  size_t keys_in, keys_out, idx_in, idx_out, sorted, boxes, slices, tmp, total;
 };
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 SortLayout sort_layout(int64_t L, size_t tmp_bytes) {
@@ -432,6 +523,7 @@ SortLayout sort_layout(int64_t L, size_t tmp_bytes) {
   s.idx_out = off; off = align256(off + 4 * (size_t)L);
   s.sorted = off; off = align256(off + 32 * (size_t)L);
   s.boxes = off; off = align256(off + 32 * (size_t)((L + kBatch - 1) / kBatch));
+  s.slices = off; off = align256(off + 128 * (size_t)((L + kBatch - 1) / kBatch));
   s.tmp = off; off = align256(off + tmp_bytes);
   s.total = off;
   return s;
@@ -514,7 +606,7 @@ hipError_t cell_sort_landmarks(const double* lm, int64_t L, double inv_cell, voi
   float* bx = reinterpret_cast<float*>(base + align256(32 * (size_t)L));
   const unsigned nbatch = (unsigned)((L + kBatch - 1) / kBatch);
   hipLaunchKernelGGL(gather_box_kernel, dim3(nbatch), dim3(kBatch), 0, stream, lm, L, order, out,
-                     bx);
+                     bx, nullptr);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
   *sorted = out;
@@ -557,16 +649,21 @@ hipError_t sort_landmarks(BuildArgs& a, void* ws, size_t ws_bytes, hipStream_t s
   if (e != hipSuccess) return e;
   double4* sorted = reinterpret_cast<double4*>(base + lay.sorted);
   float* boxes = reinterpret_cast<float*>(base + lay.boxes);
+  float* slices = reinterpret_cast<float*>(base + lay.slices);
   const unsigned nbatch = (unsigned)((a.L + kBatch - 1) / kBatch);
   hipLaunchKernelGGL(gather_box_kernel, dim3(nbatch), dim3(kBatch), 0, stream, a.lm, a.L, iout,
-                     sorted, boxes);
+                     sorted, boxes, slices);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
   a.lm_sorted = sorted;
   a.batch_box = boxes;
+  a.slice_box = slices;
   // conservative skip distance: every landmark of a skipped batch is beyond the
   // FP32 range test with a margin far above FP32 rounding
   a.skip2 = std::isinf(a.hi2) ? INFINITY : a.hi2 * 1.0001f + 1e-3f;
+  // margins far above the FP32 rounding of n^2 and of the box distances
+  a.inside_lo2 = a.lo2 * 1.0001f + 1e-6f;
+  a.inside_hi2 = std::isinf(a.hi2) ? INFINITY : a.hi2 * 0.9999f - 1e-3f;
   return hipSuccess;
 }
 

@@ -19,7 +19,11 @@ struct BuildArgs {
   // (min xyz, max xyz, 2 pad) in FP32; null for the unsorted path
   const double4* lm_sorted;
   const float* batch_box;
+  const float* slice_box;  // boxes of each 64 landmarks of a batch (4 per batch)
   float skip2;  // a batch is skipped when its box is farther than this (squared)
+  // a slice whose box lies between these (squared, nearest and farthest
+  // points) from a wave's voxels is in range of every voxel centre of them
+  float inside_lo2, inside_hi2;
   GridDev g;
   float lo2, hi2;  // FP32 range bounds on n^2
   void* out;       // field records
