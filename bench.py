@@ -682,10 +682,31 @@ def trace_leg(fif, torch, lm_d, grid, vis, t_d, q_d, out_info, dev):
     gbs = qbytes / (q_ms / 1e3) / 1e9
     log(f"trace field: build {b_ms:.1f} ms, 10M trace queries {q_ms:.3f} ms back-to-back "
         f"({gbs:.0f} GB/s), max rel. diff from the information field's trace {rel:.2e}")
-    return {"build_ms": b_ms, "query_ms": q_ms, "queries_per_s": m / (q_ms / 1e3),
-            "timing": "back-to-back, median", "query_gbs": gbs,
-            "query_hbm_frac": gbs / HBM_PEAK_GBS, "bytes_per_query": qbytes / m,
-            "max_rel_diff_vs_information_trace": rel}
+    traffic = counter_traffic("fif::query_trace_kernel<float, false>")
+    res = {"build_ms": b_ms, "query_ms": q_ms, "queries_per_s": m / (q_ms / 1e3),
+           "timing": "back-to-back, median", "query_gbs": gbs,
+           "query_hbm_frac": gbs / HBM_PEAK_GBS, "bytes_per_query": qbytes / m,
+           "field_bytes": ft.nbytes, "traffic": traffic,
+           "max_rel_diff_vs_information_trace": rel}
+    # the same factors stored per cell (8 corners together): one 320-B block
+    # per query instead of 8 scattered records
+    fc = fif.Field(grid, vis, fif.FP32_COMP, fif.KIND_TRACE_CELLS, device=dev)
+    bc_ms = _median_ms(torch, lambda: fif.build(lm_d, grid, vis, field=fc), 3)
+    outc = torch.empty((m, 1), dtype=torch.float64, device=dev)
+    qc_ms = _median_ms(torch, lambda: fif.query(fc, t_d, q_d, fif.TRACE, out=outc), 5)
+    gbs_c = qbytes / (qc_ms / 1e3) / 1e9
+    traffic_c = counter_traffic("fif::query_trace_kernel<float, true>")
+    same = bool(torch.equal(outc, out))
+    log(f"trace field per cell: build {bc_ms:.1f} ms, 10M trace queries {qc_ms:.3f} ms "
+        f"({gbs_c:.0f} GB/s algorithmic), bitwise the per-voxel field's results: {same}")
+    res["cells"] = {"build_ms": bc_ms, "query_ms": qc_ms, "queries_per_s": m / (qc_ms / 1e3),
+                    "query_gbs": gbs_c, "query_hbm_frac": gbs_c / HBM_PEAK_GBS,
+                    "field_bytes": fc.nbytes, "traffic": traffic_c,
+                    "counted_frac": (None if traffic_c is None
+                                     else traffic_c / (qc_ms / 1e3) / 1e9 / HBM_PEAK_GBS),
+                    "bitwise_same_as_per_voxel_field": same}
+    del fc
+    return res
 
 
 def update_leg(fif, torch, scenes, grid, vis, field, dev, n=1000, reps=3):

@@ -70,6 +70,12 @@ typedef int32_t fif_status;
 /* Field kinds. */
 #define FIF_KIND_INFO 0  /* positional information factor C_I (eq:general_info_pif) */
 #define FIF_KIND_TRACE 1 /* positional trace factor C_Tr (eq:general_trace_pif) */
+/* The trace factor stored per cell: each voxel holds the 10 factors of the 8
+ * corners of the cell whose lowest corner it is (320 B in FP32, 6.7x the
+ * FIF_KIND_TRACE field), so that a trilinear query reads one contiguous block
+ * (3 lines of 128 B) instead of 8 scattered records.  Same values, same
+ * results as FIF_KIND_TRACE, bit for bit; trades memory for query traffic. */
+#define FIF_KIND_TRACE_CELLS 2
 
 /* Metric mask; output columns follow this bit order.  FIF_FIM21 appends the 21
  * upper-triangle entries (row-major) of the 6x6 FIM. */
@@ -177,7 +183,8 @@ fif_status fif_update(const double* landmarks, int64_t n_landmarks, int32_t sign
  * (eq:cost_info: trace, smallest eigenvalue, log-det; the latter two in FP64).
  * t: [m][3], q: [m][4]; float for FP32 fields, double for FP64 fields.
  * out: double[m][ncols], ncols = popcount(metrics & 7) + (metrics & FIF_FIM21 ? 21 : 0).
- * flags: uint8[m] or NULL.  For FIF_KIND_TRACE fields only FIF_TRACE is valid.
+ * flags: uint8[m] or NULL.  For trace fields (FIF_KIND_TRACE, FIF_KIND_TRACE_CELLS)
+ * only FIF_TRACE is valid.
  * m = 0 is allowed (nothing is enqueued). */
 fif_status fif_query(const fif_field* field, const void* t, const void* q, int64_t m,
                      uint32_t metrics, int32_t interp, double* out, uint8_t* flags,
@@ -242,7 +249,7 @@ fif_status fif_view_sweep(const fif_field* field, const void* t, int64_t n_pos,
 /* The paper's positional information factor of the listed voxels, recovered
  * from the field: blocks[n][10][21] (double), block k = sum_i vp_k(u_i) I_i in
  * world coordinates (eq:general_info_pif), 21 = upper triangle row-major.
- * For FIF_KIND_TRACE fields: blocks[n][10] = C_Tr.  voxel_ids: int64[n]. */
+ * For trace fields: blocks[n][10] = C_Tr.  voxel_ids: int64[n]. */
 fif_status fif_field_export(const fif_field* field, const int64_t* voxel_ids, int64_t n,
                             double* blocks, void* stream);
 

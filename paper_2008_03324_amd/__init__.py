@@ -24,7 +24,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libfif.so")
 
 FP32_NAIVE, FP32_COMP, FP64 = 0, 1, 2
-KIND_INFO, KIND_TRACE = 0, 1
+KIND_INFO, KIND_TRACE, KIND_TRACE_CELLS = 0, 1, 2
 TRACE, LMIN, LOGDET, FIM21 = 1, 2, 4, 8
 TRILINEAR, NEAREST = 0, 1
 FLAG_CLAMPED, FLAG_NOT_PD, FLAG_LMIN_TIE = 1, 2, 4

@@ -41,7 +41,10 @@ bool grid_ok(const fif_grid* g) {
 }
 
 bool prec_ok(int32_t p) { return p == FIF_FP32_NAIVE || p == FIF_FP32_COMP || p == FIF_FP64; }
-bool kind_ok(int32_t k) { return k == FIF_KIND_INFO || k == FIF_KIND_TRACE; }
+bool kind_ok(int32_t k) {
+  return k == FIF_KIND_INFO || k == FIF_KIND_TRACE || k == FIF_KIND_TRACE_CELLS;
+}
+bool gp_kind_ok(int32_t k) { return k == FIF_KIND_INFO || k == FIF_KIND_TRACE; }
 
 bool vis_ok(const fif_vis* v) {
   if (!v) return false;
@@ -82,7 +85,8 @@ void range_bounds(const fif_vis* v, float* lo2, float* hi2) {
 }
 
 size_t record_scalars(int32_t kind) {
-  return kind == FIF_KIND_INFO ? (size_t)(fif::kMain + fif::kSideRec) : (size_t)fif::kTRec;
+  if (kind == FIF_KIND_INFO) return (size_t)(fif::kMain + fif::kSideRec);
+  return kind == FIF_KIND_TRACE_CELLS ? (size_t)fif::kTCell : (size_t)fif::kTRec;
 }
 size_t scalar_bytes(int32_t prec) { return prec == FIF_FP64 ? 8 : 4; }
 
@@ -99,8 +103,13 @@ bool gp_model_ok(const fif_gp* gp, bool need_kinv) {
   return true;
 }
 
-int64_t gp_stride(int32_t n_s, int32_t kind) {
-  return kind == FIF_KIND_INFO ? (int64_t)n_s * 16 : (int64_t)((n_s + 3) / 4) * 4;
+// Scalars per voxel of a GP field: 16 per axis (information), or the N_s
+// trace factors padded to a whole number of 128-B lines, so that the query's
+// 64-B passes over a row never share a line with the next voxel's row.
+int64_t gp_stride(int32_t n_s, int32_t kind, int32_t prec) {
+  if (kind == FIF_KIND_INFO) return (int64_t)n_s * 16;
+  const int64_t line = prec == FIF_FP64 ? 16 : 32;
+  return (int64_t)((n_s + line - 1) / line) * line;
 }
 
 fif::GPDev gp_dev(const fif_gp* gp, double half_fov) {
@@ -119,7 +128,7 @@ fif_status check_gp_field(const fif_gp_field* f, bool need_kinv) {
   if (!f) return fail(FIF_EINVAL, "field is NULL%s");
   if (!grid_ok(&f->grid)) return fail(FIF_EINVAL, "invalid grid%s");
   if (!prec_ok(f->prec)) return fail(FIF_EINVAL, "invalid precision%s");
-  if (!kind_ok(f->kind)) return fail(FIF_EINVAL, "invalid field kind%s");
+  if (!gp_kind_ok(f->kind)) return fail(FIF_EINVAL, "invalid field kind%s");
   if (!vis_ok(&f->vis)) return fail(FIF_EINVAL, "invalid visibility parameters%s");
   if (!gp_model_ok(&f->gp, need_kinv)) return fail(FIF_EINVAL, "invalid GP model%s");
   if (!f->data) return fail(FIF_EINVAL, "field data is NULL%s");
@@ -174,6 +183,7 @@ static fif_status build_common(const double* landmarks, int64_t n_landmarks, fif
   a.out = field->data;
   a.accumulate = accumulate;
   a.sign = sign;
+  a.trace_cells = field->kind == FIF_KIND_TRACE_CELLS ? 1 : 0;
   a.lm_sorted = nullptr;
   a.batch_box = nullptr;
   a.slice_box = nullptr;
@@ -290,7 +300,7 @@ static fif_status query_common(const fif_field* field, const void* t, const void
   if (m > ((int64_t)1 << 40)) return fail(FIF_EINVAL, "m too large%s");
   if (metrics == 0 || (metrics & ~15u)) return fail(FIF_EINVAL, "invalid metric mask%s");
   if (interp != FIF_TRILINEAR && interp != FIF_NEAREST) return fail(FIF_EINVAL, "invalid interp%s");
-  if (field->kind == FIF_KIND_TRACE && metrics != FIF_TRACE)
+  if (field->kind != FIF_KIND_INFO && metrics != FIF_TRACE)
     return fail(FIF_EINVAL, "a trace field only answers FIF_TRACE%s");
   if (grad) {
     if ((metrics & 7u) == 0 || (metrics & FIF_FIM21))
@@ -450,9 +460,9 @@ fif_status fif_view_sweep(const fif_field* field, const void* t, int64_t n_pos,
 }
 
 size_t fif_gp_field_bytes(const fif_grid* grid, int32_t n_s, int32_t prec, int32_t kind) {
-  if (!grid_ok(grid) || !prec_ok(prec) || !kind_ok(kind)) return 0;
+  if (!grid_ok(grid) || !prec_ok(prec) || !gp_kind_ok(kind)) return 0;
   if (n_s < 1 || n_s > FIF_GP_MAX_NS) return 0;
-  return (size_t)grid->nx * grid->ny * grid->nz * (size_t)gp_stride(n_s, kind) * scalar_bytes(prec);
+  return (size_t)grid->nx * grid->ny * grid->nz * (size_t)gp_stride(n_s, kind, prec) * scalar_bytes(prec);
 }
 
 fif_status fif_gp_setup(const fif_gp* gp, void* stream) {
@@ -512,7 +522,7 @@ fif_status fif_gp_build(const double* landmarks, int64_t n_landmarks, fif_gp_fie
   a.hi2 = b.hi2;
   a.gp = gp_dev(&field->gp, field->vis.half_fov);
   a.out = field->data;
-  a.stride = gp_stride(field->gp.n_s, field->kind);
+  a.stride = gp_stride(field->gp.n_s, field->kind, field->prec);
   hipError_t e = fif::launch_gp_build(a, field->prec, field->kind, (hipStream_t)stream);
   return device_status(e, "fif_gp_build");
 }
@@ -547,7 +557,7 @@ fif_status fif_gp_query(const fif_gp_field* field, const void* t, const void* q,
   a.q.out = out;
   a.q.flags = flags;
   a.gp = gp_dev(&field->gp, field->vis.half_fov);
-  a.stride = gp_stride(field->gp.n_s, field->kind);
+  a.stride = gp_stride(field->gp.n_s, field->kind, field->prec);
   hipError_t e = fif::launch_gp_query(a, field->prec, field->kind, (hipStream_t)stream);
   return device_status(e, "fif_gp_query");
 }
@@ -566,7 +576,7 @@ fif_status fif_gp_export(const fif_gp_field* field, const int64_t* voxel_ids, in
   a.g = grid_dev(&field->grid);
   a.inv_s2 = 1.0 / (field->vis.sigma_bearing * field->vis.sigma_bearing);
   a.gp = gp_dev(&field->gp, field->vis.half_fov);
-  a.stride = gp_stride(field->gp.n_s, field->kind);
+  a.stride = gp_stride(field->gp.n_s, field->kind, field->prec);
   a.ids = voxel_ids;
   a.n = n;
   a.out = blocks;

@@ -367,6 +367,18 @@ __global__ __launch_bounds__(kBuildThreads, 2) void build_kernel(BuildArgs a) {
     }
     store_vec<T, kMain>(main, res);
     store_vec<T, kSide>(side, res + kMain);
+  } else if (a.trace_cells) {
+    // slot 0 of the voxel's cell block; fill_trace_cells_kernel copies it into
+    // the blocks of the cells that have the voxel as another corner
+    T* out = reinterpret_cast<T*>(a.out) + vox * kTCell;
+    T r10[10];
+#pragma unroll
+    for (int k = 0; k < 10; ++k) r10[k] = res[k];
+    if (a.accumulate) {
+#pragma unroll
+      for (int k = 0; k < 10; ++k) r10[k] = out[k] + (T)a.sign * r10[k];
+    }
+    store_vec<T, 10>(out, r10);
   } else {
     T* out = reinterpret_cast<T*>(a.out) + vox * kTRec;
     T r12[kTRec];
@@ -377,6 +389,28 @@ __global__ __launch_bounds__(kBuildThreads, 2) void build_kernel(BuildArgs a) {
       for (int k = 0; k < NACC; ++k) r12[k] = out[k] + (T)a.sign * r12[k];
     }
     store_vec<T, kTRec>(out, r12);
+  }
+}
+
+// Slots 1..7 of every trace cell block from slot 0 of the corner voxels' blocks.
+template <typename T>
+__global__ __launch_bounds__(256) void fill_trace_cells_kernel(GridDev g, void* field) {
+  const size_t nvox = (size_t)g.nx * g.ny * g.nz;
+  const size_t v = (size_t)blockIdx.x * 256 + threadIdx.x;
+  if (v >= nvox) return;
+  T* f = reinterpret_cast<T*>(field);
+  const int32_t ix = (int32_t)(v % g.nx), iy = (int32_t)((v / g.nx) % g.ny),
+                iz = (int32_t)(v / ((size_t)g.nx * g.ny));
+#pragma unroll
+  for (int s = 1; s < 8; ++s) {
+    const int32_t cx = min(ix + (s & 1), g.nx - 1);
+    const int32_t cy = min(iy + ((s >> 1) & 1), g.ny - 1);
+    const int32_t cz = min(iz + (s >> 2), g.nz - 1);
+    const size_t c = (size_t)cx + (size_t)g.nx * ((size_t)cy + (size_t)g.ny * (size_t)cz);
+    T vals[10];
+#pragma unroll
+    for (int k = 0; k < 10; ++k) vals[k] = f[c * kTCell + k];
+    store_vec<T, 10>(f + v * kTCell + 10 * s, vals);
   }
 }
 
@@ -682,9 +716,16 @@ hipError_t launch_build(const BuildArgs& a, int prec, int kind, hipStream_t stre
   }
 #undef FIF_LAUNCH
   hipError_t e = hipGetLastError();
-  if (e != hipSuccess || kind != 0) return e;
+  if (e != hipSuccess || kind == 1) return e;
   const size_t nvox = (size_t)a.g.nx * a.g.ny * a.g.nz;
   dim3 sgrid((unsigned)((nvox + 255) / 256));
+  if (kind == 2) {
+    if (prec == 2)
+      hipLaunchKernelGGL((fill_trace_cells_kernel<double>), sgrid, dim3(256), 0, stream, a.g, a.out);
+    else
+      hipLaunchKernelGGL((fill_trace_cells_kernel<float>), sgrid, dim3(256), 0, stream, a.g, a.out);
+    return hipGetLastError();
+  }
   if (prec == 2)
     hipLaunchKernelGGL((fill_side_kernel<double>), sgrid, dim3(256), 0, stream, a.g, a.out);
   else

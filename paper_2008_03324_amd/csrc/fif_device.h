@@ -34,6 +34,10 @@ constexpr int kSide = 2;   // side moments per voxel
 constexpr int kSideRec = 16;  // scalars per cell side record (8 corners x 2)
 constexpr int kMom = 66;   // moments per voxel
 constexpr int kTRec = 12;  // scalars per voxel record (trace field, 10 used)
+// trace field stored per cell: the 10 factors of the cell's 8 corner voxels
+// (corner j = bits x, y, z of j; clamped at the upper faces), slot 0 = the
+// voxel's own
+constexpr int kTCell = 80;
 constexpr int O_G0_4 = 0, O_G0_3 = 15, O_G2_4 = 25, O_G2_3 = 40, O_G1_3 = 50, O_G1_2 = 60;
 
 // ------------------------------------------------------------ symmetric indices

@@ -610,8 +610,10 @@ __global__ __launch_bounds__(256) void gp_query_trace_kernel(GPQueryArgs ga) {
   // interpolated factors, kH at a time: the rows of all 8 corners for those
   // factors are requested together (many gathers in flight per lane), summed
   // in registers corner by corner, and written once to the lane's LDS column.
+  // A pass reads half of a 128-B line of each row (rows start on a line), and
+  // the next pass the other half, so each line comes from memory once.
   // A corner that nearest mode leaves out reads corner 0's row with weight 0.
-  constexpr int kH = sizeof(FT) == 4 ? 24 : 8;
+  constexpr int kH = sizeof(FT) == 4 ? 16 : 8;
   size_t cvox[8];
   CT cw[8];
 #pragma unroll

@@ -29,6 +29,7 @@ struct BuildArgs {
   void* out;       // field records
   int32_t accumulate;  // 0: overwrite, 1: out += sign * contribution
   int32_t sign;
+  int32_t trace_cells;  // trace factors stored per cell (slot 0 written here)
 };
 
 struct VisDev {

@@ -325,8 +325,29 @@ __global__ __launch_bounds__(kQThreads) void query_info_pipe_kernel(QueryArgs a,
   }
 }
 
-// Trace field (eq:general_trace_pif): one lane per query, 8 gathers of 48 B.
+// Trace field (eq:general_trace_pif): one lane per query, 8 gathers of 40 B
+// (CELLS: one read of the cell's 320-B block, 3 lines of 128 B).  All of a
+// query's loads are issued before the first is used; both layouts hold the
+// same values and sum the corners in the same order.
 template <typename FT>
+__device__ inline void load_trace10(const FT* r, FT* dst) {
+  if constexpr (sizeof(FT) == 4) {
+    const float4 v0 = *reinterpret_cast<const float4*>(r);
+    const float4 v1 = *reinterpret_cast<const float4*>(r + 4);
+    const float2 v2 = *reinterpret_cast<const float2*>(r + 8);
+    dst[0] = v0.x; dst[1] = v0.y; dst[2] = v0.z; dst[3] = v0.w;
+    dst[4] = v1.x; dst[5] = v1.y; dst[6] = v1.z; dst[7] = v1.w;
+    dst[8] = v2.x; dst[9] = v2.y;
+  } else {
+#pragma unroll
+    for (int k = 0; k < 10; k += 2) {
+      const double2 v = *reinterpret_cast<const double2*>(r + k);
+      dst[k] = v.x; dst[k + 1] = v.y;
+    }
+  }
+}
+
+template <typename FT, bool CELLS>
 __global__ __launch_bounds__(kQThreads) void query_trace_kernel(QueryArgs a) {
   const int64_t qi = (int64_t)blockIdx.x * kQThreads + threadIdx.x;
   if (qi >= a.m) return;
@@ -342,13 +363,39 @@ __global__ __launch_bounds__(kQThreads) void query_trace_kernel(QueryArgs a) {
 #pragma unroll
   for (int k = 0; k < 10; ++k) cbar[k] = 0.0;
   bool clamped = false;
-  const int ncorner = (a.interp == 1) ? 1 : 8;
-  for (int j = 0; j < ncorner; ++j) {
-    Corner c = make_corner(a.g, t, j, a.interp);
-    clamped = clamped || c.clamped;
-    const FT* r = field + c.vox * kTRec;
+  if (a.interp == 1) {
+    const Corner c = make_corner(a.g, t, 0, 1);
+    clamped = c.clamped;
+    FT r[10];
+    load_trace10<FT>(field + c.vox * (CELLS ? kTCell : kTRec), r);
 #pragma unroll
     for (int k = 0; k < 10; ++k) cbar[k] = fma(c.w, (double)r[k], cbar[k]);
+  } else {
+    double w[8];
+    FT blk[80];
+    const FT* base = field;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const Corner c = make_corner(a.g, t, j, 0);
+      clamped = clamped || c.clamped;
+      w[j] = c.w;
+      if (CELLS) {
+        if (j == 0) base = field + c.vox * kTCell;
+      } else {
+        load_trace10<FT>(field + c.vox * kTRec, blk + 10 * j);
+      }
+    }
+    if (CELLS) {
+#pragma unroll
+      for (int j = 0; j < 8; ++j) load_trace10<FT>(base + 10 * j, blk + 10 * j);
+    }
+    // keep the compiler from trading loads in flight for registers: every
+    // load of the query is issued before the first is used
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int j = 0; j < 8; ++j)
+#pragma unroll
+      for (int k = 0; k < 10; ++k) cbar[k] = fma(w[j], (double)blk[10 * j + k], cbar[k]);
   }
   double tr = 0.0;
 #pragma unroll
@@ -576,7 +623,7 @@ hipError_t launch_sweep(const SweepArgs& a, int prec, hipStream_t stream) {
   return hipSuccess;
 }
 
-template <typename FT>
+template <typename FT, bool CELLS>
 __global__ void export_trace_kernel(ExportArgs a) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= a.n) return;
@@ -585,7 +632,7 @@ __global__ void export_trace_kernel(ExportArgs a) {
     for (int k = 0; k < 10; ++k) a.out[i * 10 + k] = __builtin_nan("");
     return;
   }
-  const FT* rec = reinterpret_cast<const FT*>(a.field) + (size_t)v * kTRec;
+  const FT* rec = reinterpret_cast<const FT*>(a.field) + (size_t)v * (CELLS ? kTCell : kTRec);
 #pragma unroll
   for (int k = 0; k < 10; ++k) a.out[i * 10 + k] = (double)rec[k] * a.inv_s2;
 }
@@ -615,9 +662,12 @@ hipError_t launch_query(const QueryArgs& a, int prec, int kind, bool grad, hipSt
       } else {
         hipLaunchKernelGGL((query_info_kernel<double, false>), grid, dim3(kQThreads), 0, stream, p);
       }
+    } else if (kind == 1) {
+      if (dbl) hipLaunchKernelGGL((query_trace_kernel<double, false>), grid, dim3(kQThreads), 0, stream, p);
+      else hipLaunchKernelGGL((query_trace_kernel<float, false>), grid, dim3(kQThreads), 0, stream, p);
     } else {
-      if (dbl) hipLaunchKernelGGL((query_trace_kernel<double>), grid, dim3(kQThreads), 0, stream, p);
-      else hipLaunchKernelGGL((query_trace_kernel<float>), grid, dim3(kQThreads), 0, stream, p);
+      if (dbl) hipLaunchKernelGGL((query_trace_kernel<double, true>), grid, dim3(kQThreads), 0, stream, p);
+      else hipLaunchKernelGGL((query_trace_kernel<float, true>), grid, dim3(kQThreads), 0, stream, p);
     }
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
@@ -637,9 +687,12 @@ hipError_t launch_export(const ExportArgs& a, int prec, int kind, hipStream_t st
     if (kind == 0) {
       if (dbl) hipLaunchKernelGGL((export_info_kernel<double>), grid, block, 0, stream, p);
       else hipLaunchKernelGGL((export_info_kernel<float>), grid, block, 0, stream, p);
+    } else if (kind == 1) {
+      if (dbl) hipLaunchKernelGGL((export_trace_kernel<double, false>), grid, block, 0, stream, p);
+      else hipLaunchKernelGGL((export_trace_kernel<float, false>), grid, block, 0, stream, p);
     } else {
-      if (dbl) hipLaunchKernelGGL((export_trace_kernel<double>), grid, block, 0, stream, p);
-      else hipLaunchKernelGGL((export_trace_kernel<float>), grid, block, 0, stream, p);
+      if (dbl) hipLaunchKernelGGL((export_trace_kernel<double, true>), grid, block, 0, stream, p);
+      else hipLaunchKernelGGL((export_trace_kernel<float, true>), grid, block, 0, stream, p);
     }
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;

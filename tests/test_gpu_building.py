@@ -278,6 +278,16 @@ def test_empty_landmark_set_and_tiny_grids(fif):
                            interp=interp).cpu().numpy()
             ref, _ = oracle.query(of, vis.half_fov, vis.v_alpha, tt, qq, M7 | 8, interp)
             assert e_fim(go[:, 3:], ref[:, 3:]).max() <= 1e-10, shape
+        # the trace field per cell: corners clamped at the upper faces
+        fc = fif.build(torch.from_numpy(lm).cuda(), grid, vis, prec=fif.FP64,
+                       kind=fif.KIND_TRACE_CELLS)
+        otf = oracle.TraceField(oracle.trace_build(lm, grid.origin, grid.h, shape, vis.sigma),
+                                grid.origin, grid.h, shape)
+        for interp in (0, 1):
+            go = fif.query(fc, torch.from_numpy(tt).cuda(), torch.from_numpy(qq).cuda(),
+                           fif.TRACE, interp=interp).cpu().numpy()[:, 0]
+            ref, _ = oracle.trace_query(otf, vis.half_fov, vis.v_alpha, tt, qq, interp)
+            assert (np.abs(go - ref) <= 1e-12 * np.abs(ref)).all(), shape
 
 
 def _oracle_trace_field(b, t64):
@@ -288,16 +298,17 @@ def _oracle_trace_field(b, t64):
     return oracle.TraceField(CT, g.origin, g.h, g.shape, voxel_ids=ids)
 
 
+@pytest.mark.parametrize("kind", ["KIND_TRACE", "KIND_TRACE_CELLS"])
 @pytest.mark.parametrize("prec", ["FP32_COMP", "FP64"])
-def test_trace_field_queries_sampled_vs_oracle(fif, bld, prec):
+def test_trace_field_queries_sampled_vs_oracle(fif, bld, prec, kind):
     """eq:general_trace_pif, Sec. VII-A: the trace field's query against the
     oracle's trace-field query (trace factors built in FP64 at the corner
     voxels of the sampled poses), trilinear and nearest; the exported trace
     factors against the oracle's; and the trace of the information field on
     the same poses."""
-    print(f"case: building trace field {prec}", flush=True)
+    print(f"case: building trace field {prec} {kind}", flush=True)
     p = getattr(fif, prec)
-    tf = fif.build(bld["lm_d"], bld["grid"], bld["vis"], prec=p, kind=fif.KIND_TRACE)
+    tf = fif.build(bld["lm_d"], bld["grid"], bld["vis"], prec=p, kind=getattr(fif, kind))
     rng = np.random.default_rng(26)
     pick = rng.choice(bld["t"].shape[0], 384, replace=False)
     t64 = bld["t"][pick].astype(np.float64)
@@ -334,6 +345,44 @@ def test_trace_field_queries_sampled_vs_oracle(fif, bld, prec):
                             voxel_ids=ids)
     assert (np.abs(got - CT).max(axis=1) <= (1e-12 if prec == "FP64" else 1e-5)
             * np.abs(CT).max(axis=1)).all()
+
+
+def test_trace_cells_equal_trace_field(fif, bld):
+    """FIF_KIND_TRACE_CELLS holds the trace factors of each cell's 8 corners
+    together; its queries (trilinear and nearest, inside and outside the
+    hull), exports and incremental updates equal those of FIF_KIND_TRACE bit
+    for bit."""
+    print("case: trace field per cell vs per voxel", flush=True)
+    g = bld["grid"]
+    m = 1_000_000
+    rng = np.random.default_rng(30)
+    ids = torch.from_numpy(np.sort(rng.choice(g.n_voxels, 4096, replace=False))).cuda()
+    for prec, dt in ((fif.FP32_COMP, torch.float32), (fif.FP64, torch.float64)):
+        a = fif.build(bld["lm_d"], g, bld["vis"], prec=prec, kind=fif.KIND_TRACE)
+        b = fif.build(bld["lm_d"], g, bld["vis"], prec=prec, kind=fif.KIND_TRACE_CELLS)
+        assert b.nbytes == a.nbytes * 80 // 12
+        t = bld["t_d"][:m].to(dt).contiguous()
+        q = bld["q_d"][:m].to(dt).contiguous()
+        t[:1000] *= 1.3  # some outside the hull (clamped)
+        for interp in (fif.TRILINEAR, fif.NEAREST):
+            oa, fa = fif.query(a, t, q, fif.TRACE, interp=interp, want_flags=True)
+            ob, fb = fif.query(b, t, q, fif.TRACE, interp=interp, want_flags=True)
+            assert torch.equal(oa, ob) and torch.equal(fa, fb), (prec, interp)
+            assert int((fa & 1).sum()) > 0
+        assert torch.equal(fif.export_blocks(a, ids), fif.export_blocks(b, ids))
+        # add and remove a patch: the cell blocks follow their voxels
+        patch = torch.from_numpy(scenes.wall_patch(500)).cuda()
+        for sign in (+1, -1):
+            fif.update(a, patch, sign)
+            fif.update(b, patch, sign)
+            assert torch.equal(fif.export_blocks(a, ids), fif.export_blocks(b, ids))
+            assert torch.equal(fif.query(a, t, q, fif.TRACE), fif.query(b, t, q, fif.TRACE))
+    # the kind is for quadratic fields only: GP fields and gradients refuse it
+    assert fif.lib().fif_gp_field_bytes(__import__("ctypes").byref(g.c()), 30, fif.FP32_COMP,
+                                        fif.KIND_TRACE_CELLS) == 0
+    with pytest.raises(fif.FifError):
+        fif.query_grad(b, t[:10].contiguous(), q[:10].contiguous(), fif.TRACE,
+                       torch.ones((10, 1), dtype=torch.float64, device="cuda"))
 
 
 _UPDATE_REF = {}
