@@ -623,7 +623,9 @@ __device__ inline bool ldlt6(const double F[21], double L[36], double dinv[6], d
     for (int k = 0; k < j; ++k) s -= L[j * 6 + k] * L[j * 6 + k] * d[k];
     d[j] = s;
     pd = pd && (s > 0.0);
-    double inv = (s > 0.0) ? rcp_nr(s) : 1.0 / s;
+    // past a pivot <= 0 the factor feeds no output (log-det NaN, gradient
+    // NaN or left out), so no exact division is needed there
+    double inv = rcp_nr(s);
     dinv[j] = inv;
 #pragma unroll
     for (int i = j + 1; i < 6; ++i) {
@@ -637,6 +639,34 @@ __device__ inline bool ldlt6(const double F[21], double L[36], double dinv[6], d
   double prod2 = d[3] * d[4] * d[5];
   *logdet = pd ? (log(prod) + log(prod2)) : __builtin_nan("");
   return pd;
+}
+
+// The log-determinant of ldlt6, factorising in place: a[] (21 values, upper
+// triangle row-major) ends up holding L below the diagonal (L[i][j] at a[j][i])
+// and d on it.  The same operations in the same order as ldlt6, so the same
+// value; small enough to keep the whole factorisation in registers inside a
+// loop over many matrices.
+__device__ inline double logdet6_inplace(double a[21]) {
+  bool pd = true;
+#pragma unroll
+  for (int j = 0; j < 6; ++j) {
+    double s = a[u21(j, j)];
+#pragma unroll
+    for (int k = 0; k < j; ++k) s -= a[u21(k, j)] * a[u21(k, j)] * a[u21(k, k)];
+    a[u21(j, j)] = s;
+    pd = pd && (s > 0.0);
+    double inv = rcp_nr(s);  // as ldlt6
+#pragma unroll
+    for (int i = j + 1; i < 6; ++i) {
+      double r = a[u21(j, i)];
+#pragma unroll
+      for (int k = 0; k < j; ++k) r -= a[u21(k, i)] * a[u21(k, j)] * a[u21(k, k)];
+      a[u21(j, i)] = r * inv;
+    }
+  }
+  double prod = a[u21(0, 0)] * a[u21(1, 1)] * a[u21(2, 2)];
+  double prod2 = a[u21(3, 3)] * a[u21(4, 4)] * a[u21(5, 5)];
+  return pd ? (log(prod) + log(prod2)) : __builtin_nan("");
 }
 
 // Unit eigenvector of the smallest eigenvalue of a symmetric 6x6 (21 values)

@@ -429,73 +429,83 @@ __device__ constexpr int vp_a(int k) {
 }
 __device__ constexpr int vp_b(int k) { return k < 3 ? k : (k == 3 ? 1 : (k == 4 ? 2 : 2)); }
 
-// The paper's 10 world-frame blocks (eq:general_info_pif, 21 each, scaled by
-// 1/sigma^2 and `w`) of one voxel with centre tv, from its 66 moments.
+// Block k of the paper's 10 world-frame blocks (eq:general_info_pif, 21
+// entries, scaled by 1/sigma^2 and `w`) of one voxel with centre tv, from its
+// 66 moments rec[] (any memory; k may vary across lanes).  Lower-degree moments
+// follow from |u| = 1 as sums of higher ones, added in a fixed order.
 template <typename FT>
-__device__ inline void paper_blocks(const FT* rec, const double tv[3], double scale, double* out) {
-  double S4[15], S3[10], S2[6], S1[3], S0;   // G0
-  double T4[15], T3[10], T2[6], T1[3], T0;   // G2
-  expand_group<FT>(rec + O_G0_4, rec + O_G0_3, S4, S3, S2, S1, &S0);
-  expand_group<FT>(rec + O_G2_4, rec + O_G2_3, T4, T3, T2, T1, &T0);
-  double R3[10], R2[6], R1[3];
-#pragma unroll
-  for (int e = 0; e < 10; ++e) R3[e] = (double)rec[O_G1_3 + e];
-#pragma unroll
-  for (int e = 0; e < 6; ++e) R2[e] = (double)rec[O_G1_2 + e];
-#pragma unroll
-  for (int c = 0; c < 3; ++c) R1[c] = R3[s3(c, 0, 0)] + R3[s3(c, 1, 1)] + R3[s3(c, 2, 2)];
-#pragma unroll
-  for (int k = 0; k < 10; ++k) {
-    double sv0, sv2, Q0[6], Q2[6], bv[3];
-    const int pa = vp_a(k), pb = vp_b(k);
-    if (k < 6) {
-      sv0 = S2[s2(pa, pb)];
-      sv2 = T2[s2(pa, pb)];
-#pragma unroll
-      for (int c = 0; c < 3; ++c)
-#pragma unroll
-        for (int d = c; d < 3; ++d) {
-          Q0[i2(c, d)] = S4[s4(pa, pb, c, d)];
-          Q2[i2(c, d)] = T4[s4(pa, pb, c, d)];
-        }
-#pragma unroll
-      for (int c = 0; c < 3; ++c) bv[c] = R3[s3(pa, pb, c)];
-    } else if (k < 9) {
-      sv0 = S1[pa];
-      sv2 = T1[pa];
-#pragma unroll
-      for (int c = 0; c < 3; ++c)
-#pragma unroll
-        for (int d = c; d < 3; ++d) {
-          Q0[i2(c, d)] = S3[s3(pa, c, d)];
-          Q2[i2(c, d)] = T3[s3(pa, c, d)];
-        }
-#pragma unroll
-      for (int c = 0; c < 3; ++c) bv[c] = R2[s2(pa, c)];
-    } else {
-      sv0 = S0;
-      sv2 = T0;
-#pragma unroll
-      for (int e = 0; e < 6; ++e) { Q0[e] = S2[e]; Q2[e] = T2[e]; }
-#pragma unroll
-      for (int c = 0; c < 3; ++c) bv[c] = R1[c];
-    }
-    double A[6], D[6], B[9];
+__device__ inline void paper_block(const FT* rec, const double tv[3], double scale, int k,
+                                   double* out) {
+  // degree-2 moment (a, b) of group G (G0 or G2) from its degree-4 ones
+  auto deg2 = [&](int o4, int a2, int b2) __attribute__((always_inline)) {
+    return (double)rec[o4 + s4(a2, b2, 0, 0)] + (double)rec[o4 + s4(a2, b2, 1, 1)] +
+           (double)rec[o4 + s4(a2, b2, 2, 2)];
+  };
+  double sv0, sv2, Q0[6], Q2[6], bv[3];
+  const int pa = vp_a(k), pb = vp_b(k);
+  if (k < 6) {
+    sv0 = deg2(O_G0_4, pa, pb);
+    sv2 = deg2(O_G2_4, pa, pb);
 #pragma unroll
     for (int c = 0; c < 3; ++c)
 #pragma unroll
       for (int d = c; d < 3; ++d) {
-        A[i2(c, d)] = (c == d ? sv2 : 0.0) - Q2[i2(c, d)];
-        D[i2(c, d)] = (c == d ? sv0 : 0.0) - Q0[i2(c, d)];
+        Q0[i2(c, d)] = (double)rec[O_G0_4 + s4(pa, pb, c, d)];
+        Q2[i2(c, d)] = (double)rec[O_G2_4 + s4(pa, pb, c, d)];
       }
-    B[0] = 0.0;    B[1] = bv[2];  B[2] = -bv[1];
-    B[3] = -bv[2]; B[4] = 0.0;    B[5] = bv[0];
-    B[6] = bv[1];  B[7] = -bv[0]; B[8] = 0.0;
-    double W[21];
-    shift_frame<double>(A, B, D, tv, W);
 #pragma unroll
-    for (int e = 0; e < 21; ++e) out[k * 21 + e] = W[e] * scale;
+    for (int c = 0; c < 3; ++c) bv[c] = (double)rec[O_G1_3 + s3(pa, pb, c)];
+  } else if (k < 9) {
+    sv0 = (double)rec[O_G0_3 + s3(pa, 0, 0)] + (double)rec[O_G0_3 + s3(pa, 1, 1)] +
+          (double)rec[O_G0_3 + s3(pa, 2, 2)];
+    sv2 = (double)rec[O_G2_3 + s3(pa, 0, 0)] + (double)rec[O_G2_3 + s3(pa, 1, 1)] +
+          (double)rec[O_G2_3 + s3(pa, 2, 2)];
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+#pragma unroll
+      for (int d = c; d < 3; ++d) {
+        Q0[i2(c, d)] = (double)rec[O_G0_3 + s3(pa, c, d)];
+        Q2[i2(c, d)] = (double)rec[O_G2_3 + s3(pa, c, d)];
+      }
+#pragma unroll
+    for (int c = 0; c < 3; ++c) bv[c] = (double)rec[O_G1_2 + s2(pa, c)];
+  } else {
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+#pragma unroll
+      for (int d = c; d < 3; ++d) {
+        Q0[i2(c, d)] = deg2(O_G0_4, c, d);
+        Q2[i2(c, d)] = deg2(O_G2_4, c, d);
+      }
+    sv0 = Q0[0] + Q0[3] + Q0[5];
+    sv2 = Q2[0] + Q2[3] + Q2[5];
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+      bv[c] = (double)rec[O_G1_3 + s3(c, 0, 0)] + (double)rec[O_G1_3 + s3(c, 1, 1)] +
+              (double)rec[O_G1_3 + s3(c, 2, 2)];
   }
+  double A[6], D[6], B[9];
+#pragma unroll
+  for (int c = 0; c < 3; ++c)
+#pragma unroll
+    for (int d = c; d < 3; ++d) {
+      A[i2(c, d)] = (c == d ? sv2 : 0.0) - Q2[i2(c, d)];
+      D[i2(c, d)] = (c == d ? sv0 : 0.0) - Q0[i2(c, d)];
+    }
+  B[0] = 0.0;    B[1] = bv[2];  B[2] = -bv[1];
+  B[3] = -bv[2]; B[4] = 0.0;    B[5] = bv[0];
+  B[6] = bv[1];  B[7] = -bv[0]; B[8] = 0.0;
+  double W[21];
+  shift_frame<double>(A, B, D, tv, W);
+#pragma unroll
+  for (int e = 0; e < 21; ++e) out[e] = W[e] * scale;
+}
+
+// All 10 blocks of one voxel: out[k * 21 + e].
+template <typename FT>
+__device__ inline void paper_blocks(const FT* rec, const double tv[3], double scale, double* out) {
+#pragma unroll
+  for (int k = 0; k < 10; ++k) paper_block<FT>(rec, tv, scale, k, out + 21 * k);
 }
 
 template <typename FT>
@@ -518,15 +528,20 @@ __global__ void export_info_kernel(ExportArgs a) {
 
 // ------------------------------------------------------------ view sweep
 
-constexpr int kSweepThreads = 256;
+constexpr int kSweepThreads = 512;
 
-// One workgroup per position: the 8 corner lanes expand their voxel into the
-// paper's world-frame blocks, the workgroup sums them (interpolation done
-// once), then every thread contracts the blocks with vr(z) for its axes.
-template <typename FT>
+// One workgroup per position.  The corner records are staged in LDS, 80
+// threads expand one (corner, block) each into the paper's world-frame blocks,
+// the workgroup sums the corners (interpolation done once), then every thread
+// contracts the blocks with vr(z) for its axes and evaluates the metric (a
+// template argument, so each kernel holds only its own metric's code).
+template <typename FT, uint32_t METRIC>
 __global__ __launch_bounds__(kSweepThreads) void view_sweep_kernel(SweepArgs a) {
   __shared__ double s_part[8][210];
   __shared__ double s_cbar[210];
+  __shared__ FT s_rec[8][kMom];
+  __shared__ double s_tv[8][4];
+  __shared__ double s_w[8];
   __shared__ double s_bv[kSweepThreads];
   __shared__ int64_t s_bi[kSweepThreads];
   const int tid = threadIdx.x;
@@ -540,13 +555,24 @@ __global__ __launch_bounds__(kSweepThreads) void view_sweep_kernel(SweepArgs a) 
       FT rec[kMom];
       const size_t cell = c.vox;  // own values sit in slot 0 of the voxel's own record
       load_record<FT>(reinterpret_cast<const FT*>(a.field), nvox, c.vox, cell, 0, rec);
+#pragma unroll
+      for (int e = 0; e < kMom; ++e) s_rec[tid][e] = rec[e];
       const int64_t ix = c.vox % a.g.nx, iy = (c.vox / a.g.nx) % a.g.ny,
                     iz = c.vox / ((size_t)a.g.nx * a.g.ny);
-      const double tvx[3] = {a.g.ox + (double)ix * a.g.h, a.g.oy + (double)iy * a.g.h,
-                             a.g.oz + (double)iz * a.g.h};
-      paper_blocks<FT>(rec, tvx, a.vis.inv_s2 * c.w, s_part[tid]);
+      s_tv[tid][0] = a.g.ox + (double)ix * a.g.h;
+      s_tv[tid][1] = a.g.oy + (double)iy * a.g.h;
+      s_tv[tid][2] = a.g.oz + (double)iz * a.g.h;
+    }
+    s_w[tid] = c.active ? a.vis.inv_s2 * c.w : 0.0;
+  }
+  __syncthreads();
+  if (tid < 80) {
+    const int j = tid / 10, k = tid % 10;
+    if (s_w[j] != 0.0 || s_w[j] != s_w[j]) {
+      const double tv[3] = {s_tv[j][0], s_tv[j][1], s_tv[j][2]};
+      paper_block<FT>(s_rec[j], tv, s_w[j], k, &s_part[j][21 * k]);
     } else {
-      for (int e = 0; e < 210; ++e) s_part[tid][e] = 0.0;
+      for (int e = 0; e < 21; ++e) s_part[j][21 * k + e] = 0.0;
     }
   }
   __syncthreads();
@@ -560,7 +586,11 @@ __global__ __launch_bounds__(kSweepThreads) void view_sweep_kernel(SweepArgs a) 
   const double k2 = a.vis.k2, k1 = a.vis.k1, k0 = a.vis.k0;
   double best = -__builtin_inf();
   int64_t bi = -1;
+#pragma unroll 1
   for (int64_t d = tid; d < a.n_dir; d += kSweepThreads) {
+    // the 210 interpolated block entries stay in LDS: read per axis rather
+    // than hoisted into registers (420 VGPRs) by the compiler
+    asm volatile("" ::: "memory");
     double z[3] = {a.dirs[3 * d], a.dirs[3 * d + 1], a.dirs[3 * d + 2]};
     const double inv = 1.0 / sqrt(z[0] * z[0] + z[1] * z[1] + z[2] * z[2]);
     z[0] *= inv; z[1] *= inv; z[2] *= inv;
@@ -568,17 +598,26 @@ __global__ __launch_bounds__(kSweepThreads) void view_sweep_kernel(SweepArgs a) 
                            2.0 * k2 * z[0] * z[1], 2.0 * k2 * z[0] * z[2], 2.0 * k2 * z[1] * z[2],
                            k1 * z[0],              k1 * z[1],              k1 * z[2],
                            k0};
+    // F = sum_k vr_k Cbar_k, one block of 21 at a time (each entry's sum in
+    // the order k = 0..9), so that only one block is read into registers
     double F[21];
 #pragma unroll
-    for (int e = 0; e < 21; ++e) {
-      double f = 0.0;
+    for (int e = 0; e < 21; ++e) F[e] = 0.0;
 #pragma unroll
-      for (int k = 0; k < 10; ++k) f = fma(vr[k], s_cbar[k * 21 + e], f);
-      F[e] = f;
+    for (int k = 0; k < 10; ++k) {
+#pragma unroll
+      for (int e = 0; e < 21; ++e) F[e] = fma(vr[k], s_cbar[k * 21 + e], F[e]);
+      __builtin_amdgcn_sched_barrier(0);
     }
     double val;
     uint8_t flag = 0;
-    eval_metrics<false>(F, a.metric, &val, &flag, nullptr, nullptr, false);
+    if constexpr (METRIC == M_LOGDET) {
+      // in place: the general LDL^T with its separate factor held the kernel
+      // at one wave per SIMD
+      val = logdet6_inplace(F);
+    } else {
+      eval_metrics<false>(F, METRIC, &val, &flag, nullptr, nullptr, false);
+    }
     if (a.values) a.values[p * a.n_dir + d] = val;
     if (val > best) {  // NaN never wins; d grows, so the first of equal values stays
       best = val;
@@ -604,6 +643,13 @@ __global__ __launch_bounds__(kSweepThreads) void view_sweep_kernel(SweepArgs a) 
   if (tid == 0 && a.best) a.best[p] = s_bi[0];
 }
 
+template <typename FT>
+static void launch_sweep_metric(const SweepArgs& p, dim3 grid, dim3 block, hipStream_t stream) {
+  if (p.metric == M_TRACE) hipLaunchKernelGGL((view_sweep_kernel<FT, M_TRACE>), grid, block, 0, stream, p);
+  else if (p.metric == M_LMIN) hipLaunchKernelGGL((view_sweep_kernel<FT, M_LMIN>), grid, block, 0, stream, p);
+  else hipLaunchKernelGGL((view_sweep_kernel<FT, M_LOGDET>), grid, block, 0, stream, p);
+}
+
 hipError_t launch_sweep(const SweepArgs& a, int prec, hipStream_t stream) {
   if (a.n_pos <= 0) return hipSuccess;
   const int64_t per = kMaxLaunchItems / kSweepThreads;  // positions per launch
@@ -615,8 +661,8 @@ hipError_t launch_sweep(const SweepArgs& a, int prec, hipStream_t stream) {
     if (a.values) p.values = a.values + (size_t)off * a.n_dir;
     if (a.best) p.best = a.best + off;
     dim3 grid((unsigned)p.n_pos), block(kSweepThreads);
-    if (prec == 2) hipLaunchKernelGGL((view_sweep_kernel<double>), grid, block, 0, stream, p);
-    else hipLaunchKernelGGL((view_sweep_kernel<float>), grid, block, 0, stream, p);
+    if (prec == 2) launch_sweep_metric<double>(p, grid, block, stream);
+    else launch_sweep_metric<float>(p, grid, block, stream);
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }

@@ -96,13 +96,14 @@ def test_view_sweep_past_one_launch(fif):
     vis = fif.Vis(v.half_fov, v.v_alpha, v.sigma, v.r_min, v.r_max)
     field = fif.build(torch.tensor(lm, dtype=torch.float64, device="cuda"), grid, vis,
                       prec=fif.FP32_COMP)
-    per = SLICE // 256  # positions per launch (one 256-lane workgroup each)
-    n = per + 100
+    per = SLICE // 512  # positions per launch (one 512-lane workgroup each)
+    n = 2 * per + 100
     rng = np.random.default_rng(2102)
     t = torch.from_numpy(scenes.uniform_in_hull(rng, g, n).astype(np.float32)).cuda()
     dirs = torch.from_numpy(scenes.sphere_axes(4)).cuda()
     vals, best = fif.view_sweep(field, t, dirs, fif.LOGDET)
-    rows = torch.from_numpy(np.array([0, per - 2, per - 1, per, per + 1, n - 1])).cuda()
+    rows = torch.from_numpy(np.array([0, per - 2, per - 1, per, per + 1, 2 * per - 1, 2 * per,
+                                      n - 1])).cuda()
     v2, b2 = fif.view_sweep(field, t[rows].contiguous(), dirs, fif.LOGDET)
     assert torch.equal(vals[rows].nan_to_num(7.0), v2.nan_to_num(7.0))
     assert torch.equal(best[rows], b2)
