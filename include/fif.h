@@ -190,7 +190,9 @@ fif_status fif_query(const fif_field* field, const void* t, const void* q, int64
                      uint32_t metrics, int32_t interp, double* out, uint8_t* flags,
                      void* stream);
 
-/* Gradient of L = sum_r sum_c dL_dout[r][c] s_c(pose_r) w.r.t. each pose:
+/* Gradient of L = sum_r sum_c dL_dout[r][c] s_c(pose_r) w.r.t. each pose
+ * (a metric whose dL_dout is 0 is left out of L: a FIM that is not positive
+ * definite gives NaN gradients only where its log-det weight is nonzero):
  *   dL_dt[m][3]   through the trilinear weights,
  *   dL_dphi[m][3] w.r.t. the left so(3) perturbation of R_wc.
  * metrics: subset of FIF_TRACE | FIF_LMIN | FIF_LOGDET (dL_dout has that many
@@ -355,17 +357,19 @@ fif_status fif_gp_export(const fif_gp_field* field, const int64_t* voxel_ids, in
  *     the run; *elapsed is the run's length.
  * Each request's results equal those of fif_query (metrics FIF_TRACE |
  * FIF_LMIN | FIF_LOGDET, trilinear) or fif_query_grad (the same metrics,
- * dL/dout = 1) on that request alone: a pose's arithmetic does not depend on
- * the other poses of a launch.  The request buffers must be ready on the
- * device before the call and stay allocated until it returns; the call
+ * dL/dout = the request's weights for every pose) on that request alone: a
+ * pose's arithmetic does not depend on the other poses of a launch.  The
+ * request buffers must be ready on the device before the call and stay
+ * allocated until it returns; the call
  * returns after all work has completed.  The run uses the current device
  * (where the fields, requests and workspace must live); the workspace holds
  * the streams' batch buffers for the whole call, so calls that overlap in time
  * need workspaces of their own.
  * Errors: FIF_EINVAL (before anything is enqueued) for invalid fields,
- * requests (field index, kind, m < 1, NULL or misaligned buffers, a request
- * larger than hbm_budget or max_batch) or configuration; FIF_ENOMEM for a
- * workspace smaller than fif_serve_workspace_bytes(cfg); FIF_EDEVICE for a
+ * requests (field index, kind, m < 1, NULL or misaligned buffers, weights
+ * not finite, a request larger than hbm_budget or max_batch) or
+ * configuration; FIF_ENOMEM for a workspace smaller than
+ * fif_serve_workspace_bytes(cfg); FIF_EDEVICE for a
  * HIP error during the run (the remaining requests keep done = NaN). */
 #define FIF_SERVE_PLAN 0
 #define FIF_SERVE_OPT 1
@@ -382,6 +386,8 @@ typedef struct {
   double* out;     /* device [m][3]: trace, lambda_min, log-det */
   void* grad_t;    /* device [m][3] (FIF_SERVE_OPT; pose precision) */
   void* grad_phi;  /* device [m][3] (FIF_SERVE_OPT; left so(3)) */
+  double weights[3]; /* host (FIF_SERVE_OPT): dL/dout of every pose for trace,
+                        lambda_min, log-det; 0 leaves a metric out of L */
   double admitted; /* written by fif_serve_run */
   double done;     /* written by fif_serve_run */
 } fif_serve_request;

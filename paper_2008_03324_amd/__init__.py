@@ -75,8 +75,8 @@ class CServeRequest(ctypes.Structure):
     _fields_ = [("arrival", ctypes.c_double), ("field", ctypes.c_int32), ("kind", ctypes.c_int32),
                 ("m", ctypes.c_int64), ("t", ctypes.c_void_p), ("q", ctypes.c_void_p),
                 ("out", ctypes.c_void_p), ("grad_t", ctypes.c_void_p),
-                ("grad_phi", ctypes.c_void_p), ("admitted", ctypes.c_double),
-                ("done", ctypes.c_double)]
+                ("grad_phi", ctypes.c_void_p), ("weights", ctypes.c_double * 3),
+                ("admitted", ctypes.c_double), ("done", ctypes.c_double)]
 
 
 class CServeConfig(ctypes.Structure):

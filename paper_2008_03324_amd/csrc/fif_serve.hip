@@ -33,9 +33,11 @@ struct PackArgs {
   double* out[kMaxPack];
   void* gt[kMaxPack];
   void* gphi[kMaxPack];
+  double w[kMaxPack][3];  // the requests' metric weights (dL/dout)
   // batch buffers
   void* bt;
   void* bq;
+  double* bup;
   const double* bout;
   const void* bgt;
   const void* bgphi;
@@ -67,6 +69,8 @@ __global__ __launch_bounds__(kPackThreads) void pack_kernel(PackArgs a) {
   const char* q = static_cast<const char*>(a.q[r]) + (size_t)j * 4 * a.sb;
   copy_scalars(static_cast<char*>(a.bt) + (size_t)i * 3 * a.sb, t, 3, a.sb);
   copy_scalars(static_cast<char*>(a.bq) + (size_t)i * 4 * a.sb, q, 4, a.sb);
+  if (a.opt)
+    for (int k = 0; k < 3; ++k) a.bup[(size_t)i * 3 + k] = a.w[r][k];
 }
 
 // Results of pose i back to its request.
@@ -85,11 +89,6 @@ __global__ __launch_bounds__(kPackThreads) void unpack_kernel(PackArgs a) {
   }
 }
 
-__global__ void fill_ones_kernel(double* p, int64_t n) {
-  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (i < n) p[i] = 1.0;
-}
-
 fif_status serve_fail(fif_status st, const std::string& msg) {
   set_last_error("fif_serve_run: " + msg);
   return st;
@@ -97,8 +96,8 @@ fif_status serve_fail(fif_status st, const std::string& msg) {
 
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
-// Per-stream batch buffers: poses (t, q), outputs, upstream ones, gradients,
-// each for max_batch poses at 8 bytes per scalar.
+// Per-stream batch buffers: poses (t, q), outputs, upstream weights,
+// gradients, each for max_batch poses at 8 bytes per scalar.
 struct LaneLayout {
   size_t t, q, out, up, gt, gphi, bytes;
 };
@@ -177,6 +176,9 @@ fif_status fif_serve_run(const fif_field* fields, int32_t n_fields, fif_serve_re
     if (r.kind == FIF_SERVE_OPT &&
         (!r.grad_t || !r.grad_phi || ((uintptr_t)r.grad_t % sb) || ((uintptr_t)r.grad_phi % sb)))
       return serve_fail(FIF_EINVAL, id + "NULL or misaligned gradient buffer");
+    if (r.kind == FIF_SERVE_OPT &&
+        !(isfinite(r.weights[0]) && isfinite(r.weights[1]) && isfinite(r.weights[2])))
+      return serve_fail(FIF_EINVAL, id + "weights not finite");
     if (request_bytes(r) > cfg->hbm_budget)
       return serve_fail(FIF_EINVAL, id + "larger than the HBM budget");
   }
@@ -203,11 +205,6 @@ fif_status fif_serve_run(const fif_field* fields, int32_t n_fields, fif_serve_re
     lanes[s].base = static_cast<char*>(workspace) + (size_t)s * L.bytes;
     hipError_t e = hipStreamCreateWithFlags(&lanes[s].stream, hipStreamNonBlocking);
     if (e != hipSuccess) { lanes[s].stream = nullptr; device_fail(e, "hipStreamCreate"); break; }
-    const int64_t nup = cfg->max_batch * 3;
-    hipLaunchKernelGGL(fill_ones_kernel, dim3((unsigned)((nup + 255) / 256)), dim3(256), 0,
-                       lanes[s].stream, reinterpret_cast<double*>(lanes[s].base + L.up), nup);
-    e = hipGetLastError();
-    if (e != hipSuccess) device_fail(e, "fill");
   }
   for (int k = 0; k < cfg->max_inflight + 1 && status == FIF_OK; ++k) {
     hipEvent_t ev;
@@ -250,12 +247,14 @@ fif_status fif_serve_run(const fif_field* fields, int32_t n_fields, fif_serve_re
       const fif_serve_request& r = reqs[group[k]];
       a.off[k] = m;
       a.t[k] = r.t; a.q[k] = r.q; a.out[k] = r.out; a.gt[k] = r.grad_t; a.gphi[k] = r.grad_phi;
+      for (int c = 0; c < 3; ++c) a.w[k][c] = r.weights[c];
       m += r.m;
     }
     a.off[group.size()] = m;
     a.m = m;
     a.bt = ln.base + L.t;
     a.bq = ln.base + L.q;
+    a.bup = reinterpret_cast<double*>(ln.base + L.up);
     a.bout = reinterpret_cast<const double*>(ln.base + L.out);
     a.bgt = ln.base + L.gt;
     a.bgphi = ln.base + L.gphi;

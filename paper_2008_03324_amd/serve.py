@@ -45,6 +45,9 @@ class Request:
     kind: str               # "plan" or "opt"
     t: torch.Tensor         # [m, 3] device
     q: torch.Tensor         # [m, 4] device
+    # "opt": dL/dout of every pose for trace, lambda_min, log-det (a zero
+    # weight leaves that metric out of the gradient)
+    weights: tuple = (1.0, 1.0, 1.0)
     # filled by the server
     out: torch.Tensor | None = None      # [m, 3] float64
     grad_t: torch.Tensor | None = None   # [m, 3]
@@ -67,6 +70,23 @@ def size_class(m: int, smallest: int = 256) -> int:
     while c < m:
         c *= 2
     return c
+
+
+def _fill_weights(up: torch.Tensor, reqs: list[Request]):
+    """Each request's metric weights into its rows of the batch's upstream
+    buffer, by fills with scalar arguments (no host-to-device copy); runs of
+    requests with equal weights share one fill per metric."""
+    off = 0
+    i = 0
+    while i < len(reqs):
+        j, n = i, 0
+        while j < len(reqs) and reqs[j].weights == reqs[i].weights:
+            n += reqs[j].m
+            j += 1
+        for c, w in enumerate(reqs[i].weights):
+            up[off:off + n, c].fill_(float(w))
+        off += n
+        i = j
 
 
 class _Lane:
@@ -204,6 +224,8 @@ class Server:
             else:
                 torch.cat([r.t for r in reqs], out=b["t"][:m])
                 torch.cat([r.q for r in reqs], out=b["q"][:m])
+            if kind == "opt":
+                _fill_weights(b["up"], reqs)
             lane.launch(fid, kind, cap, self.use_graphs)
             out = b["out"][:m].clone()
             if kind == "opt":
@@ -312,7 +334,8 @@ class NativeServer:
             arr[i] = CServeRequest(r.arrival, r.field, 1 if opt else 0, r.m, r.t.data_ptr(),
                                    r.q.data_ptr(), r.out.data_ptr(),
                                    r.grad_t.data_ptr() if opt else None,
-                                   r.grad_phi.data_ptr() if opt else None, 0.0, 0.0)
+                                   r.grad_phi.data_ptr() if opt else None,
+                                   (ctypes.c_double * 3)(*map(float, r.weights)), 0.0, 0.0)
         self.cfg.realtime = int(realtime)
         elapsed = ctypes.c_double(0.0)
         # the loop creates its streams on the current device: the fields' one

@@ -187,8 +187,9 @@ def test_serve_host_side_validation():
         assert L.fif_serve_workspace_bytes(ctypes.byref(bad)) == 0
     fields = (fif.CField * 1)(fif.CField(g.c(), vis.c(), fif.FP32_COMP, fif.KIND_INFO, 4096))
     el = ctypes.c_double()
+    ones = (ctypes.c_double * 3)(1.0, 1.0, 1.0)
     req = (fif.CServeRequest * 1)(fif.CServeRequest(0.0, 0, 0, 10, 4096, 4096, 4096, None, None,
-                                                    0.0, 0.0))
+                                                    ones, 0.0, 0.0))
     run = lambda f, nf, r, n, c, ws, nb: L.fif_serve_run(f, nf, r, n, ctypes.byref(c), ws, nb,
                                                          ctypes.byref(el))
     bad_cfg = fif.CServeConfig(0, 8, 1 << 20, 1024, 1, 0)
@@ -199,8 +200,13 @@ def test_serve_host_side_validation():
     for fld, kind, m in ((1, 0, 10), (0, 2, 10), (0, 0, 0), (0, 0, 2048), (0, 1, 10)):
         # field index, kind, m < 1, m > max_batch, gradient buffers missing
         r = (fif.CServeRequest * 1)(fif.CServeRequest(0.0, fld, kind, m, 4096, 4096, 4096, None,
-                                                      None, 0.0, 0.0))
+                                                      None, ones, 0.0, 0.0))
         assert run(fields, 1, r, 1, ok, 4096, 1 << 30) == -1, (fld, kind, m)
+    nan_w = (ctypes.c_double * 3)(1.0, float("nan"), 1.0)
+    r = (fif.CServeRequest * 1)(fif.CServeRequest(0.0, 0, 1, 10, 4096, 4096, 4096, 4096, 4096,
+                                                  nan_w, 0.0, 0.0))
+    assert run(fields, 1, r, 1, ok, 4096, 1 << 30) == -1
+    assert b"weights" in L.fif_last_error()
     small = fif.CServeConfig(2, 8, 100, 1024, 1, 0)  # 10 poses need 240 B
     assert run(fields, 1, req, 1, small, 4096, 1 << 30) == -1
     assert b"budget" in L.fif_last_error()

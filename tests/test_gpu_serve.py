@@ -44,7 +44,7 @@ def _check_vs_oracle(reqs, n_each=6, rows=48):
     kind, up to `rows` poses of each) against the FP64 oracle on oracle-built
     factors of the poses' corner voxels, at the FP32-field bar of 1e-3:
     trace relative, lambda_min / lambda_max, log-det in nats; gradients
-    |dg| / max|g| per pose (dL/dout = 1 for each metric), poses within 1e-3 of
+    |dg| / max|g| per pose (dL/dout = the request's weights), poses within 1e-3 of
     a cell face or with a near-repeated lambda_min left out (one-sided or
     undefined derivative)."""
     worst = {"out": 0.0, "grad": 0.0}
@@ -71,12 +71,13 @@ def _check_vs_oracle(reqs, n_each=6, rows=48):
             if kind == "opt":
                 n_opt += 1
                 rgt, rgphi = oracle.query_grad(of, v.half_fov, v.v_alpha, t64, q64, 7,
-                                               np.ones((len(sel), 3)))
+                                               np.tile(np.asarray(r.weights), (len(sel), 1)))
                 gg = (t64 - np.asarray(g.origin)) / g.h
                 fr = gg - np.floor(gg)
                 ev = np.linalg.eigvalsh(sym_from21(ref[:, 3:]))
                 ok = ((fr > 1e-3) & (fr < 1 - 1e-3)).all(axis=1)
-                ok &= (ev[:, 1] - ev[:, 0]) > 1e-6 * np.abs(ev).max(axis=1)
+                if r.weights[1]:
+                    ok &= (ev[:, 1] - ev[:, 0]) > 1e-6 * np.abs(ev).max(axis=1)
                 assert ok.sum() >= len(sel) // 2
                 for a, b in ((r.grad_t.cpu().numpy()[sel], rgt),
                              (r.grad_phi.cpu().numpy()[sel], rgphi)):
@@ -84,6 +85,7 @@ def _check_vs_oracle(reqs, n_each=6, rows=48):
                     worst["grad"] = max(worst["grad"], rel.max())
                     assert rel.max() <= 1e-3, r.rid
     assert n_opt == n_each
+    assert len({r.weights for r in reqs if r.kind == "opt"}) == len(_WEIGHTS)
     return worst
 
 
@@ -106,12 +108,18 @@ def test_served_requests_vs_oracle(setup, loop):
     print(loop, "served vs oracle, worst", worst)
 
 
+# optimizer requests' metric weights (trace, lambda_min, log-det), in turn:
+# all three, log-det left out, lambda_min left out, lambda_min alone
+_WEIGHTS = ((1.0, 1.0, 1.0), (1.0, 1.0, 0.0), (0.5, 0.0, 2.0), (0.0, 1.0, 0.0))
+
+
 def _make(serve, pools, specs):
     reqs = []
     for sp in specs:
         t, q = pools[sp.field][sp.kind]
         reqs.append(serve.Request(sp.rid, sp.arrival, sp.field, sp.kind,
-                                  t[sp.offset:sp.offset + sp.m], q[sp.offset:sp.offset + sp.m]))
+                                  t[sp.offset:sp.offset + sp.m], q[sp.offset:sp.offset + sp.m],
+                                  weights=_WEIGHTS[sp.rid % len(_WEIGHTS)]))
     return reqs
 
 
@@ -119,7 +127,7 @@ def _alone(fif, fields, r):
     f = fields[r.field]
     if r.kind == "plan":
         return fif.query(f, r.t.contiguous(), r.q.contiguous(), 7), None, None
-    up = torch.ones((r.m, 3), dtype=torch.float64, device="cuda")
+    up = torch.tensor(r.weights, dtype=torch.float64, device="cuda").expand(r.m, 3).contiguous()
     gt, gphi, out = fif.query_grad(f, r.t.contiguous(), r.q.contiguous(), 7, up, want_out=True)
     return out, gt, gphi
 
@@ -204,15 +212,16 @@ def test_native_admission_and_errors(setup):
     one = (fif.CServeRequest * 1)()
     r0 = reqs[0]
     r0.out = torch.empty((r0.m, 3), dtype=torch.float64, device="cuda")
+    w = (ctypes.c_double * 3)(1.0, 1.0, 1.0)
     one[0] = fif.CServeRequest(0.0, r0.field, 0, r0.m, r0.t.data_ptr(), r0.q.data_ptr(),
-                               r0.out.data_ptr(), None, None, 0.0, 0.0)
+                               r0.out.data_ptr(), None, None, w, 0.0, 0.0)
     cf = (fif.CField * len(fields))(*[f.cstruct for f in fields])
     el = ctypes.c_double()
     L = fif.lib()
     assert L.fif_serve_run(cf, len(fields), one, 1, ctypes.byref(cfg),
                            ctypes.c_void_p(ws.data_ptr()), need - 1, ctypes.byref(el)) == -2
     bad = fif.CServeRequest(0.0, 7, 0, r0.m, r0.t.data_ptr(), r0.q.data_ptr(),
-                            r0.out.data_ptr(), None, None, 0.0, 0.0)
+                            r0.out.data_ptr(), None, None, w, 0.0, 0.0)
     one[0] = bad
     assert L.fif_serve_run(cf, len(fields), one, 1, ctypes.byref(cfg),
                            ctypes.c_void_p(ws.data_ptr()), need, ctypes.byref(el)) == -1
