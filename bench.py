@@ -127,7 +127,7 @@ def sources_of(kernel: str):
         return GP_SOURCES
     if name.startswith("pc_"):
         return PC_SOURCES
-    if name.startswith(("build_", "fill_side", "gather_box", "morton")):
+    if name.startswith(("build_", "fill_side", "fill_trace", "gather_box", "morton")):
         return BUILD_SOURCES
     return QUERY_SOURCES
 
@@ -163,6 +163,34 @@ def counter_traffic(kernel):
     if not rec or rec.get("src_hash") != src_hash(sources_of(kernel)):
         return None
     return rec["GB_per_launch"] * 1e9
+
+
+def hbm_probe(torch, dev, nbytes=4 << 30, reps=5):
+    """Plain library HBM rates on this GPU, best of `reps`: torch's sum over a
+    4 GiB float32 tensor (reads only) and a 2 GiB device-to-device copy (reads
+    and writes), as context for the kernels' fractions of the 8 TB/s peak."""
+    x = torch.ones(nbytes // 4, dtype=torch.float32, device=dev)
+    a = torch.empty(nbytes // 2, dtype=torch.uint8, device=dev)
+    b = torch.empty_like(a)
+    best = {"read": 0.0, "copy": 0.0}
+    for _ in range(reps):
+        for kind in ("read", "copy"):
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record()
+            if kind == "read":
+                x.sum()
+                moved = nbytes
+            else:
+                b.copy_(a)
+                moved = 2 * a.numel()
+            e1.record()
+            e1.synchronize()
+            best[kind] = max(best[kind], moved / (e0.elapsed_time(e1) / 1e3) / 1e9)
+    del x, a, b
+    torch.cuda.empty_cache()
+    return {"read_gbs": best["read"], "copy_gbs": best["copy"],
+            "read_frac": best["read"] / HBM_PEAK_GBS, "copy_frac": best["copy"] / HBM_PEAK_GBS}
 
 
 def contributing_fraction(torch, lm_d, grid, r_max, n_sample=32768, seed=7):
@@ -324,6 +352,11 @@ def main():
                                                 "(504); at this pair rate the paper's flops "
                                                 "would exceed the FP32 peak"},
     }
+    probe = hbm_probe(torch, dev)
+    res["hbm_probe"] = probe
+    res["roofline"]["frac_of_read_probe"] = q_gbs / probe["read_gbs"]
+    log(f"HBM probe: torch sum {probe['read_gbs']:.0f} GB/s, copy {probe['copy_gbs']:.0f} GB/s; "
+        f"query {q_gbs:.0f} GB/s")
     if "grad" in phases:
         g_bytes = mg * GRAD_BYTES_PER_POSE
         g_gbs = g_bytes / (med["grad"] / 1e3) / 1e9
@@ -347,11 +380,15 @@ def main():
         pc_flops = frac * pc_tested * PC_FLOPS_CONTRIB + (1 - frac) * pc_tested * PC_FLOPS_TESTED
         res["pc_queries_per_s"] = pc_rate
         res["speedup_vs_pc"] = q_rate / pc_rate
-        res["roofline_pc"] = {"kernel": "pc_kernel<FP32_COMP>", "bound": "fp32 valu",
+        res["roofline_pc"] = {"kernel": "pc_kernel<FP32_COMP, sorted>", "bound": "fp32 valu",
                               "achieved": pc_flops / (med["pc"] / 1e3) / 1e12,
-                              "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s"}
+                              "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
+                              "note": "flops of the plain pass (every pose tests every "
+                                      "landmark); the sorted pass skips landmark batches "
+                                      "outside a workgroup's pose box, so this is an "
+                                      "effective rate; counter_achieved is what ran"}
         res["roofline_pc"]["frac"] = res["roofline_pc"]["achieved"] / FP32_PEAK_TFLOPS
-        cp = counter_flops("fif::pc_kernel<1, false>", PC_SOURCES)
+        cp = counter_flops("fif::pc_kernel<1, false, true>", PC_SOURCES)
         if cp:
             ctf = cp["fp32"] / (med["pc"] / 1e3) / 1e12
             res["roofline_pc"].update({"counter_achieved": ctf,
@@ -764,7 +801,7 @@ def sweep_leg(fif, torch, scenes, g, field, dev, n_pos=200, n_axes=4096, reps=5)
     nbytes = n_pos * (8 * RECORD_BYTES_USED + 12 + 8 * n_axes + 8) + 24 * n_axes
     gbs = nbytes / (med / 1e3) / 1e9
     tfs = n_pos * n_axes * SWEEP_FLOPS_PER_AXIS / (med / 1e3) / 1e12
-    traffic = counter_traffic("fif::view_sweep_kernel<float>")
+    traffic = counter_traffic("fif::view_sweep_kernel<float, 4u>")
     log(f"view sweep {n_pos} x {n_axes}: {med:.3f} ms ({tfs:.2f} FP64 TFLOP/s, {gbs:.0f} GB/s)")
     return {"positions": n_pos, "axes": n_axes, "metric": "logdet", "ms": med,
             "poses_per_s": n_pos * n_axes / (med / 1e3),

@@ -556,6 +556,9 @@ fif_status fif_gp_query(const fif_gp_field* field, const void* t, const void* q,
   a.q.interp = interp;
   a.q.out = out;
   a.q.flags = flags;
+  if (field->kind == FIF_KIND_TRACE &&
+      (uint64_t)field->grid.nx * field->grid.ny * field->grid.nz > UINT32_MAX)
+    return fail(FIF_EINVAL, "GP trace fields of more than 2^32 voxels are not supported%s");
   a.gp = gp_dev(&field->gp, field->vis.half_fov);
   a.stride = gp_stride(field->gp.n_s, field->kind, field->prec);
   hipError_t e = fif::launch_gp_query(a, field->prec, field->kind, (hipStream_t)stream);

@@ -16,6 +16,7 @@
 // (FP64), each corner block is contracted with w, moved to the query frame and
 // interpolated; the FP64 world shift and metrics follow per query.
 #include <cmath>
+#include <type_traits>
 
 #include "fif_kernels.h"
 #include "fif_metrics.h"
@@ -589,97 +590,190 @@ __attribute__((amdgpu_waves_per_eu(sizeof(FT) == 4 ? 2 : 1))) void gp_query_kern
   }
 }
 
-// Trace fields: one lane per pose.  The lane interpolates its pose's N_s
-// trace factors into an LDS column, then accumulates
-//   Tr = sum_g K_z[g] sum_h kinv[g][h] Tbar_h
-// with the inverse read at wave-uniform addresses (scalar loads, once per
-// wave instead of once per pose) and K_z formed per lane in FP64.
-template <typename FT>
-__global__ __launch_bounds__(256) void gp_query_trace_kernel(GPQueryArgs ga) {
+// Trace fields (eq:general_trace_pif with the GP weights of Sec. V-B):
+//   Tr(pose) = K_z^T (K^s + noise I)^-1 Tbar,  Tbar = sum_j w_j T_j
+// over the pose's 8 corner rows T_j of N_s trace factors.  Two phases per
+// wave of 64 poses:
+//  1. interpolation, pose by pose with the whole wave: lane l reads factors
+//     2l and 2l+1 of each corner row (NW windows of 128 factors), so one load
+//     instruction reads a row's consecutive bytes, and writes the weighted sum
+//     (corners in order 0..7) to the pose's LDS column;
+//  2. W = kinv Tbar for the wave's 64 columns on the FP64 matrix cores
+//     (v_mfma_f64_16x16x4: A = 16 rows x 4 factors of kinv, B = 4 factors x 16
+//     poses), then Tr = sum_g K_z[g] W[g] with K_z formed in FP64 per (g, pose)
+//     and the four lanes that hold one pose's rows summed.
+// A lane's value from another lane of the wave (k wave-uniform).
+__device__ inline float lane_value(float v, int k) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), k));
+}
+__device__ inline double lane_value(double v, int k) {
+  const int64_t b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)(uint32_t)b, k);
+  const int hi = __builtin_amdgcn_readlane((int)(uint32_t)(b >> 32), k);
+  return __longlong_as_double((int64_t)(((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo));
+}
+
+template <typename FT, int NW>
+__global__ __launch_bounds__(256, 2) void gp_query_trace_kernel(GPQueryArgs ga) {
   using CT = FT;
+  using FT2 = typename std::conditional<sizeof(FT) == 4, float2, double2>::type;
   extern __shared__ unsigned char s_dyn[];
-  CT* col = reinterpret_cast<CT*>(s_dyn);  // [ns][blockDim.x]
+  const int nt = blockDim.x;
+  const int cs = nt + 1;  // column stride: a pose's factors fall in different banks
+  CT* col = reinterpret_cast<CT*>(s_dyn);  // [ns][cs]
+  // the sample axes, after the columns (16-B aligned)
+  double* s_ax =
+      reinterpret_cast<double*>(s_dyn + ((size_t)ga.gp.ns * cs * sizeof(CT) + 15) / 16 * 16);
+  for (int i = threadIdx.x; i < 3 * ga.gp.ns; i += blockDim.x) s_ax[i] = ga.gp.axes[i];
+  __syncthreads();
   const QueryArgs& a = ga.q;
   const int ns = ga.gp.ns;
-  const int tid = threadIdx.x, nt = blockDim.x;
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wbase = tid - lane;
   const int64_t qi = (int64_t)blockIdx.x * nt + tid;
   const bool valid = qi < a.m;
   const int64_t ql = valid ? qi : a.m - 1;
   const QSlot<CT> sl = make_slot<FT>(a, ql);
   const FT* field = reinterpret_cast<const FT*>(a.field);
-  // interpolated factors, kH at a time: the rows of all 8 corners for those
-  // factors are requested together (many gathers in flight per lane), summed
-  // in registers corner by corner, and written once to the lane's LDS column.
-  // A pass reads half of a 128-B line of each row (rows start on a line), and
-  // the next pass the other half, so each line comes from memory once.
-  // A corner that nearest mode leaves out reads corner 0's row with weight 0.
-  constexpr int kH = sizeof(FT) == 4 ? 16 : 8;
-  size_t cvox[8];
+  // this lane's pose: corner rows (voxel index < 2^32, checked by the caller)
+  // and weights; a corner that nearest mode leaves out reads corner 0's row
+  // with weight 0
+  uint32_t cvox[8];
   CT cw[8];
 #pragma unroll
   for (int j = 0; j < 8; ++j) {
     const CornerC<CT> c = slot_corner(sl, a.g, j);
-    cvox[j] = c.vox;
+    cvox[j] = (uint32_t)c.vox;
     cw[j] = c.active ? c.w : CT(0);
   }
 #pragma unroll
   for (int j = 1; j < 8; ++j)
     if (cw[j] == CT(0)) cvox[j] = cvox[0];
-  for (int h0 = 0; h0 < ns; h0 += kH) {
-    FT x[8][kH];
+  const int npair = (ns + 1) >> 1;
+  const size_t stride = (size_t)ga.stride;
+  auto load = [&](int k, FT2 (&x)[8][NW]) {
 #pragma unroll
     for (int j = 0; j < 8; ++j) {
-      const FT* row = field + cvox[j] * (size_t)ga.stride + h0;
+      const FT* row = field + (size_t)(uint32_t)__builtin_amdgcn_readlane((int)cvox[j], k) * stride;
 #pragma unroll
-      for (int q = 0; q < kH / 4; ++q) {
-        if (h0 + 4 * q < ns) {
-          if constexpr (sizeof(FT) == 4) {
-            const float4 v4 = *reinterpret_cast<const float4*>(row + 4 * q);
-            x[j][4 * q] = v4.x; x[j][4 * q + 1] = v4.y; x[j][4 * q + 2] = v4.z; x[j][4 * q + 3] = v4.w;
-          } else {
-            const double2 v0 = *reinterpret_cast<const double2*>(row + 4 * q);
-            const double2 v1 = *reinterpret_cast<const double2*>(row + 4 * q + 2);
-            x[j][4 * q] = v0.x; x[j][4 * q + 1] = v0.y; x[j][4 * q + 2] = v1.x; x[j][4 * q + 3] = v1.y;
+      for (int w = 0; w < NW; ++w) {
+        // lanes past the row read its last pair again: no branch around the load
+        const int p = min(64 * w + lane, npair - 1);
+        x[j][w] = *reinterpret_cast<const FT2*>(row + 2 * p);
+      }
+    }
+  };
+  // phase 1, G poses' rows in flight together
+  constexpr int G = 8 / (int)(sizeof(FT) / 4) / NW;
+#pragma unroll 1
+  for (int k0 = 0; k0 < 64; k0 += G) {
+    FT2 x[G][8][NW];
+#pragma unroll
+    for (int u = 0; u < G; ++u) load(k0 + u, x[u]);
+#pragma unroll
+    for (int u = 0; u < G; ++u) {
+      const int k = k0 + u;
+      CT w8[8];
+#pragma unroll
+      for (int j = 0; j < 8; ++j) w8[j] = lane_value(cw[j], k);
+#pragma unroll
+      for (int w = 0; w < NW; ++w) {
+        const int p = 64 * w + lane;
+        if (p < npair) {
+          CT e0 = CT(0), e1 = CT(0);
+#pragma unroll
+          for (int j = 0; j < 8; ++j) {
+            e0 = fma(w8[j], (CT)x[u][j][w].x, e0);
+            e1 = fma(w8[j], (CT)x[u][j][w].y, e1);
           }
-        } else {
-#pragma unroll
-          for (int e = 0; e < 4; ++e) x[j][4 * q + e] = FT(0);
+          col[(size_t)(2 * p) * cs + wbase + k] = e0;
+          if (2 * p + 1 < ns) col[(size_t)(2 * p + 1) * cs + wbase + k] = e1;
         }
       }
     }
+  }
+  wave_sync();
+  // phase 2.  MFMA lane layout (16x16x4 FP64): A[i][k] and B[k][j] in lane
+  // i + 16 k and j + 16 k; D[4 r + k][j] in register r of lane j + 16 k.
+  // Lane (i16, k4) thus accumulates W rows g = 16 m + 4 r + k4 of the poses
+  // 16 n + i16 (N tiles n = 0..3); MG M tiles of kinv are accumulated together
+  // so that each B fragment is read from LDS once per group.
+  typedef double d4 __attribute__((ext_vector_type(4)));
+  const int i16 = lane & 15, k4 = lane >> 4;
+  double zq[4][3];  // axes of the poses 16 n + i16 of this wave
 #pragma unroll
-    for (int e = 0; e < kH; ++e) {
-      CT acc = CT(0);
+  for (int n = 0; n < 4; ++n)
 #pragma unroll
-      for (int j = 0; j < 8; ++j) acc = fma(cw[j], (CT)x[j][e], acc);
-      if (h0 + e < ns) col[(size_t)(h0 + e) * nt + tid] = acc;
+    for (int c = 0; c < 3; ++c) zq[n][c] = (double)__shfl(sl.z[c], 16 * n + i16);
+  const double* kinv = ga.gp.kinv;
+  const int nm = (ns + 15) >> 4, nk = (ns + 3) >> 2;
+  constexpr int MG = 5;  // M tiles (16 rows of kinv each) accumulated together
+  double part[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll 1
+  for (int m0 = 0; m0 < nm; m0 += MG) {
+    // A fragments of step s: kinv[16 m + i16][4 s + k4]; entries past row or
+    // column ns are zero (read clamped, then masked by a multiply so that the
+    // load is not moved into a branch).  B fragments: Tbar[4 s + k4][16 n +
+    // i16] (a clamped row past ns: finite, and its A entries are zero).
+    const double* krow[MG];
+    bool gv[MG];
+#pragma unroll
+    for (int mm = 0; mm < MG; ++mm) {
+      const int g = 16 * (m0 + mm) + i16;
+      gv[mm] = g < ns;
+      krow[mm] = kinv + (size_t)min(g, ns - 1) * ns;
+    }
+    auto load = [&](int st, double (&av)[MG], double (&bv)[4]) {
+      const int h = 4 * st + k4;
+      const double mask = h < ns ? 1.0 : 0.0;
+      const int hc = min(h, ns - 1);
+#pragma unroll
+      for (int mm = 0; mm < MG; ++mm) av[mm] = krow[mm][hc] * (gv[mm] ? mask : 0.0);
+      const CT* crow = col + (size_t)hc * cs + wbase + i16;
+#pragma unroll
+      for (int n = 0; n < 4; ++n) bv[n] = (double)crow[16 * n];
+    };
+    d4 acc[MG][4];
+#pragma unroll
+    for (int mm = 0; mm < MG; ++mm)
+#pragma unroll
+      for (int n = 0; n < 4; ++n) acc[mm][n] = d4{0.0, 0.0, 0.0, 0.0};
+    double an[MG], bn[4];
+    load(0, an, bn);
+#pragma unroll 1
+    for (int st = 0; st < nk; ++st) {
+      double av[MG], bv[4];
+#pragma unroll
+      for (int mm = 0; mm < MG; ++mm) av[mm] = an[mm];
+#pragma unroll
+      for (int n = 0; n < 4; ++n) bv[n] = bn[n];
+      load(min(st + 1, nk - 1), an, bn);
+#pragma unroll
+      for (int mm = 0; mm < MG; ++mm)
+#pragma unroll
+        for (int n = 0; n < 4; ++n)
+          acc[mm][n] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[mm], bv[n], acc[mm][n], 0, 0, 0);
+    }
+    // W rows g = 16 m + 4 r + k4 of poses 16 n + i16, weighted by K_z
+#pragma unroll
+    for (int mm = 0; mm < MG; ++mm) {
+      if (m0 + mm >= nm) break;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int gr = min(16 * (m0 + mm) + 4 * r + k4, ns - 1);
+        const double ax[3] = {s_ax[3 * gr], s_ax[3 * gr + 1], s_ax[3 * gr + 2]};
+#pragma unroll
+        for (int n = 0; n < 4; ++n)
+          part[n] = fma(se_kernel(zq[n], ax, ga.gp.inv_2l2), acc[mm][n][r], part[n]);
+      }
     }
   }
-  // Tr = K_z^T (K^s + noise I)^-1 Tbar in FP64, kRows rows of the inverse at a
-  // time (each streamed along h; every Tbar_h read feeds kRows accumulators)
-  constexpr int kRows = 4;
-  const double z[3] = {(double)sl.z[0], (double)sl.z[1], (double)sl.z[2]};
-  double tr = 0.0;
-  for (int g0 = 0; g0 < ns; g0 += kRows) {
-    const double* kr[kRows];
 #pragma unroll
-    for (int k = 0; k < kRows; ++k)
-      kr[k] = ga.gp.kinv + (size_t)(g0 + k < ns ? g0 + k : g0) * ns;
-    double y[kRows];
-#pragma unroll
-    for (int k = 0; k < kRows; ++k) y[k] = 0.0;
-    // unrolled so that the scalar loads of several h are in flight together
-    // (2.14 -> 1.65 ms for 1M poses at N_s = 70; 16 is slower again)
-#pragma unroll 8
-    for (int h = 0; h < ns; ++h) {
-      const double th = (double)col[(size_t)h * nt + tid];
-#pragma unroll
-      for (int k = 0; k < kRows; ++k) y[k] = fma(kr[k][h], th, y[k]);
-    }
-#pragma unroll
-    for (int k = 0; k < kRows; ++k)
-      if (g0 + k < ns) tr = fma(se_kernel(z, ga.gp.axes + 3 * (g0 + k), ga.gp.inv_2l2), y[k], tr);
+  for (int n = 0; n < 4; ++n) {
+    part[n] += __shfl_xor(part[n], 16);
+    part[n] += __shfl_xor(part[n], 32);
   }
+  const double tr = k4 == 0 ? part[0] : k4 == 1 ? part[1] : k4 == 2 ? part[2] : part[3];
   if (valid) {
     if (a.out) a.out[ql * a.ncols] = tr * a.vis.inv_s2;
     if (a.flags) a.flags[ql] = (sl.bits & 8) ? FL_CLAMPED : 0;
@@ -798,14 +892,22 @@ hipError_t launch_gp_query(const GPQueryArgs& a, int prec, int kind, hipStream_t
   if (kind == 1) {
     // one lane per pose; the LDS columns (N_s per lane) set the workgroup size
     const size_t sb = prec == 2 ? 8 : 4;
-    const int nt = ((size_t)a.gp.ns * 256 * sb <= 80 * 1024) ? 256 : 64;
-    const size_t lds = (size_t)a.gp.ns * nt * sb;
+    // LDS: the poses' columns (stride nt + 1) and the sample axes; 256 lanes
+    // while that fits two workgroups per CU, else one wave per workgroup
+    auto lds_of = [&](int nt) {
+      return ((size_t)a.gp.ns * (nt + 1) * sb + 15) / 16 * 16 + (size_t)a.gp.ns * 24;
+    };
+    const int nt = lds_of(256) <= 80 * 1024 ? 256 : 64;
+    const size_t lds = lds_of(nt);
+    const bool two = (a.gp.ns + 1) / 2 > 64;  // rows longer than 128 factors
     for (int64_t off = 0; off < a.q.m; off += kMaxLaunchItems) {
       GPQueryArgs p = a;
       p.q = query_part(a.q, off, std::min(kMaxLaunchItems, a.q.m - off), sb);
       dim3 tgrid((unsigned)((p.q.m + nt - 1) / nt)), tblock(nt);
-      if (prec == 2) hipLaunchKernelGGL((gp_query_trace_kernel<double>), tgrid, tblock, lds, stream, p);
-      else hipLaunchKernelGGL((gp_query_trace_kernel<float>), tgrid, tblock, lds, stream, p);
+      if (prec == 2 && two) hipLaunchKernelGGL((gp_query_trace_kernel<double, 2>), tgrid, tblock, lds, stream, p);
+      else if (prec == 2) hipLaunchKernelGGL((gp_query_trace_kernel<double, 1>), tgrid, tblock, lds, stream, p);
+      else if (two) hipLaunchKernelGGL((gp_query_trace_kernel<float, 2>), tgrid, tblock, lds, stream, p);
+      else hipLaunchKernelGGL((gp_query_trace_kernel<float, 1>), tgrid, tblock, lds, stream, p);
       const hipError_t e = hipGetLastError();
       if (e != hipSuccess) return e;
     }
