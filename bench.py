@@ -469,8 +469,14 @@ def gp_leg(fif, torch, scenes, lm_d, grid, vis, t_d, q_d, contrib, dev, ns=70, m
     q_tr = timed(lambda: fif.gp_query(ft, tq, qq, fif.TRACE, out=out1))
     qbytes = 8 * ns * 15 * 4 + POSE_BYTES + OUT_BYTES_3  # 15 terms per axis and corner
     gbs = m * qbytes / (q_info / 1e3) / 1e9
+    tbytes = 8 * ns * 4 + POSE_BYTES + 8  # N_s trace factors per corner, one output
+    tgbs = m * tbytes / (q_tr / 1e3) / 1e9
+    t_traffic = counter_traffic("fif::gp_query_trace_kernel<float, 1>")
+    # FP64 work of the trace query: the kinv product (N_s^2 FMAs) per pose
+    t_fp64_floor_ms = m * 2.0 * ns * ns / (FP64_PEAK_TFLOPS * 1e12) * 1e3
     log(f"GP N_s={ns}: length {length:.4f} ({fit_ms:.1f} ms), build info {b_info:.1f} ms, "
-        f"trace {b_tr:.1f} ms; query info {q_info:.3f} ms ({gbs:.0f} GB/s), trace {q_tr:.3f} ms")
+        f"trace {b_tr:.1f} ms; query info {q_info:.3f} ms ({gbs:.0f} GB/s), trace {q_tr:.3f} ms "
+        f"({tgbs:.0f} GB/s)")
     # matrix-core work of the information build: 2 * 16 terms * N_s per pair
     mfma_tflops = contrib * 2.0 * 16 * ns / (b_info / 1e3) / 1e12
     return {"n_s": ns, "length": length, "fit_ms": fit_ms, "field_bytes": fi.nbytes,
@@ -479,7 +485,13 @@ def gp_leg(fif, torch, scenes, lm_d, grid, vis, t_d, q_d, contrib, dev, ns=70, m
             "build_mfma_tflops": mfma_tflops,
             "query_poses": m, "query_info_ms": q_info, "query_trace_ms": q_tr,
             "query_info_per_s": m / (q_info / 1e3), "query_bytes_per_pose": qbytes,
-            "query_info_gbs": gbs, "query_info_hbm_frac": gbs / HBM_PEAK_GBS}
+            "query_info_gbs": gbs, "query_info_hbm_frac": gbs / HBM_PEAK_GBS,
+            "query_trace_bytes_per_pose": tbytes, "query_trace_gbs": tgbs,
+            "query_trace_hbm_frac": tgbs / HBM_PEAK_GBS, "query_trace_traffic": t_traffic,
+            "query_trace_counted_frac": (None if t_traffic is None
+                                         else t_traffic / (q_tr / 1e3) / 1e9 / HBM_PEAK_GBS),
+            "query_trace_hbm_floor_ms": m * tbytes / (HBM_PEAK_GBS * 1e9) * 1e3,
+            "query_trace_fp64_floor_ms": t_fp64_floor_ms}
 
 
 def _sym21(v):
