@@ -193,19 +193,38 @@ def hbm_probe(torch, dev, nbytes=4 << 30, reps=5):
             "read_frac": best["read"] / HBM_PEAK_GBS, "copy_frac": best["copy"] / HBM_PEAK_GBS}
 
 
-def contributing_fraction(torch, lm_d, grid, r_max, n_sample=32768, seed=7):
-    """Fraction of (voxel, landmark) pairs inside the range (sampled voxels)."""
-    g = torch.Generator(device="cpu").manual_seed(seed)
-    shape = torch.tensor(grid.shape)
-    idx = torch.stack([torch.randint(0, int(s), (n_sample,), generator=g) for s in grid.shape], 1)
-    tv = (torch.tensor(grid.origin) + idx.double() * grid.h).float().cuda()
+def contributing_fraction(torch, lm_d, grid, r_max, n_sample=None, seed=7):
+    """Fraction of (voxel, landmark) pairs inside the range cutoff: counted over
+    every voxel of the grid (n_sample None) or over n_sample random voxels.
+    Squared FP32 distances of the FP32 voxel centre and landmark, as the
+    kernels' predicate; the sum order differs from the kernels' fma chain, so
+    a pair within rounding of the cutoff may count differently."""
     lm = lm_d.float()
+    lx, ly, lz = (lm[:, c].contiguous() for c in range(3))
+    chunk = max(64, min(8192, int(1e9) // lm.shape[0]))  # about 4 GB per [chunk, L] tensor
     r2 = float(np.float32(r_max * r_max))
+    nx, ny, nz = grid.shape
+    n_vox = nx * ny * nz
+    o = torch.tensor(grid.origin, dtype=torch.float64, device=lm.device)
+    if n_sample is None:
+        ids = None
+        n = n_vox
+    else:
+        g = torch.Generator(device="cpu").manual_seed(seed)
+        ids = torch.randint(0, n_vox, (n_sample,), generator=g).to(lm.device)
+        n = n_sample
     inside = 0
-    for c in range(0, n_sample, 1024):
-        d = ((tv[c:c + 1024, None, :] - lm[None, :, :]) ** 2).sum(-1)
-        inside += int((d <= r2).sum().item())
-    return inside / (n_sample * lm.shape[0])
+    for c in range(0, n, chunk):
+        idx = (torch.arange(c, min(n, c + chunk), device=lm.device) if ids is None
+               else ids[c:c + chunk])
+        ijk = torch.stack([idx % nx, (idx // nx) % ny, idx // (nx * ny)], 1)
+        tv = (o + ijk.double() * grid.h).float()
+        d2 = (tv[:, 0:1] - lx[None]) ** 2
+        d2 += (tv[:, 1:2] - ly[None]) ** 2
+        d2 += (tv[:, 2:3] - lz[None]) ** 2
+        inside += int(((d2 <= r2) & (d2 >= 1e-12)).sum().item())
+        del d2
+    return inside / (n * lm.shape[0])
 
 
 def main():
@@ -248,7 +267,7 @@ def main():
     tested = float(grid.n_voxels) * args.landmarks
     contrib = frac * tested
     pc_tested = float(m) * args.landmarks
-    log(f"contributing fraction {frac:.4f} (sampled)")
+    log(f"contributing fraction {frac:.4f} (counted over all {grid.n_voxels} voxels)")
 
     phases = [p for p in args.phases.split(",") if p]
     if args.no_pc and "pc" in phases:
@@ -544,7 +563,7 @@ def precision_leg(fif, torch, scenes, t_d, q_d, dev, n_landmarks=1_000_000, n_or
     grid = fif.Grid(g.origin, g.h, g.shape)
     vis = fif.Vis(v.half_fov, v.v_alpha, v.sigma, v.r_min, v.r_max)
     lm_d = torch.tensor(lm, dtype=torch.float64, device=dev)
-    frac = contributing_fraction(torch, lm_d, grid, v.r_max)
+    frac = contributing_fraction(torch, lm_d, grid, v.r_max, n_sample=262_144)
     contrib = frac * grid.n_voxels * n_landmarks
     rng = np.random.default_rng(12)
     pick = np.sort(rng.choice(m, n_oracle, replace=False))

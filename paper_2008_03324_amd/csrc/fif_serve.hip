@@ -89,6 +89,17 @@ __global__ __launch_bounds__(kPackThreads) void unpack_kernel(PackArgs a) {
   }
 }
 
+// The upstream weights of a batch of one optimizer request (dL/dout of its m
+// poses), for the gradient call made on the request's own buffers.
+__global__ __launch_bounds__(kPackThreads) void fill_up_kernel(double* up, int64_t m, double w0,
+                                                               double w1, double w2) {
+  const int64_t i = (int64_t)blockIdx.x * kPackThreads + threadIdx.x;
+  if (i >= m) return;
+  up[i * 3] = w0;
+  up[i * 3 + 1] = w1;
+  up[i * 3 + 2] = w2;
+}
+
 fif_status serve_fail(fif_status st, const std::string& msg) {
   set_last_error("fif_serve_run: " + msg);
   return st;
@@ -237,6 +248,39 @@ fif_status fif_serve_run(const fif_field* fields, int32_t n_fields, fif_serve_re
     const fif_field& f = fields[r0.field];
     Lane& ln = lanes[next_lane];
     next_lane = (next_lane + 1) % cfg->n_streams;
+    const uint32_t metrics = FIF_TRACE | FIF_LMIN | FIF_LOGDET;
+    auto record = [&]() {
+      Batch b;
+      b.ev = free_events.back();
+      free_events.pop_back();
+      const hipError_t er = hipEventRecord(b.ev, ln.stream);
+      if (er != hipSuccess) { free_events.push_back(b.ev); device_fail(er, "hipEventRecord"); return; }
+      b.reqs = group;
+      inflight.push_back(std::move(b));
+    };
+    if (group.size() == 1) {
+      // a batch of one request runs on the request's own buffers: no gather or
+      // scatter launch (fewer host calls per batch; the same per-pose results)
+      fif_status st;
+      if (r0.kind == FIF_SERVE_OPT) {
+        double* up = reinterpret_cast<double*>(ln.base + L.up);
+        const dim3 grid((unsigned)((r0.m + kPackThreads - 1) / kPackThreads)), block(kPackThreads);
+        hipLaunchKernelGGL(fill_up_kernel, grid, block, 0, ln.stream, up, r0.m, r0.weights[0],
+                           r0.weights[1], r0.weights[2]);
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) { device_fail(e, "fill"); return; }
+        st = fif_query_grad(&f, r0.t, r0.q, r0.m, metrics, up, r0.grad_t, r0.grad_phi, r0.out,
+                            ln.stream);
+      } else {
+        st = fif_query(&f, r0.t, r0.q, r0.m, metrics, FIF_TRILINEAR, r0.out, nullptr, ln.stream);
+      }
+      if (st != FIF_OK) {
+        if (status == FIF_OK) { status = st; error_text = fif_last_error(); }
+        return;
+      }
+      record();
+      return;
+    }
     PackArgs a;
     memset(&a, 0, sizeof(a));
     a.n = (int32_t)group.size();
@@ -262,7 +306,6 @@ fif_status fif_serve_run(const fif_field* fields, int32_t n_fields, fif_serve_re
     hipLaunchKernelGGL(pack_kernel, grid, block, 0, ln.stream, a);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) { device_fail(e, "pack"); return; }
-    const uint32_t metrics = FIF_TRACE | FIF_LMIN | FIF_LOGDET;
     fif_status st;
     if (a.opt)
       st = fif_query_grad(&f, ln.base + L.t, ln.base + L.q, m, metrics,
@@ -278,13 +321,7 @@ fif_status fif_serve_run(const fif_field* fields, int32_t n_fields, fif_serve_re
     hipLaunchKernelGGL(unpack_kernel, grid, block, 0, ln.stream, a);
     e = hipGetLastError();
     if (e != hipSuccess) { device_fail(e, "unpack"); return; }
-    Batch b;
-    b.ev = free_events.back();
-    free_events.pop_back();
-    e = hipEventRecord(b.ev, ln.stream);
-    if (e != hipSuccess) { free_events.push_back(b.ev); device_fail(e, "hipEventRecord"); return; }
-    b.reqs = group;
-    inflight.push_back(std::move(b));
+    record();
   };
 
   while (status == FIF_OK && finished < n_req) {
