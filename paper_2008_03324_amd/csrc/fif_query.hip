@@ -217,19 +217,29 @@ __global__ __launch_bounds__(kQThreads) void query_info_kernel(QueryArgs a) {
 
 // Forward query on FP32 fields with persistent waves.  Each wave takes
 // batches of 64 queries in turn (the same per-query arithmetic and order as
-// query_info_kernel, so the results are bitwise identical).  The records of a
-// batch's next corner step are loaded before the current step is contracted,
-// and the first step of the wave's next batch is loaded before the current
+// query_info_kernel, so the results are bitwise identical).  The main records
+// of a corner step are loaded straight into LDS (global_load_lds_dwordx4),
+// 16 lanes per record so that each load instruction reads whole records, and
+// each lane then reads its own record from LDS; a lane loading its own record
+// instead (64 records per instruction) moves fewer bytes per second.  The
+// records of a batch's next corner step are loaded before the current step is
+// contracted, and the first step of the wave's next batch before the current
 // batch's FP64 metric step, so the gathers stay in flight throughout.  The LDS
-// slots are private to a wave and no workgroup barrier is used: a wave leaves
-// as soon as its batches are done.
+// slots and records are private to a wave and no workgroup barrier is used: a
+// wave leaves as soon as its batches are done.  Voxel indices are 32-bit here
+// (grids of 2^32 voxels or more take query_info_kernel).
 constexpr int kPipeWaves = kQThreads / 64;
 
 
-__global__ __launch_bounds__(kQThreads) void query_info_pipe_kernel(QueryArgs a, int64_t nbatch) {
+constexpr int kRecF4 = kMain / 4;  // float4 per main record
+
+__global__ __launch_bounds__(kQThreads, 2) void query_info_pipe_kernel(QueryArgs a, int64_t nbatch) {
   using FT = float;
   using CT = float;
-  __shared__ QSlot<CT> s_q[kPipeWaves][2][64];
+  typedef const void __attribute__((address_space(1)))* gptr;
+  typedef void __attribute__((address_space(3)))* lptr;
+  __shared__ QSlot<CT> s_q[kPipeWaves][64];
+  __shared__ float4 s_rec[kPipeWaves][64 * kRecF4];  // a corner step's 64 main records
   const int tid = threadIdx.x;
   const int lane = tid & 63, wv = tid >> 6;
   const int grp = lane >> 3, j = lane & 7;
@@ -237,6 +247,7 @@ __global__ __launch_bounds__(kQThreads) void query_info_pipe_kernel(QueryArgs a,
   const int64_t nw = (int64_t)gridDim.x * kPipeWaves;
   if (gw >= nbatch) return;  // whole wave
   const FT* field = reinterpret_cast<const FT*>(a.field);
+  const float4* field4 = reinterpret_cast<const float4*>(a.field);
   const size_t nvox = (size_t)a.g.nx * a.g.ny * a.g.nz;
   const CT k2 = (CT)a.vis.k2, k1 = (CT)a.vis.k1, k0 = (CT)a.vis.k0;
   const FT* T = reinterpret_cast<const FT*>(a.t);
@@ -251,28 +262,69 @@ __global__ __launch_bounds__(kQThreads) void query_info_pipe_kernel(QueryArgs a,
     quat_axis((double)tr[3], (double)tr[4], (double)tr[5], (double)tr[6], z);
     return make_slot_from<FT>(a, t, z);
   };
-  auto fetch = [&](const QSlot<CT>* sq, int it, FT* rec) {
-    const CornerC<CT> c = slot_corner(sq[grp * 8 + it], a.g, j);
-    if (c.active) load_record<FT>(field, nvox, c.vox, c.cell, j, rec);
+  // Corner step `it` serves record r = lane r's (corner j of query 8 grp + it).
+  // The 64 main records go straight to LDS: load k (0..15) covers records
+  // 4k .. 4k+3 with 16 lanes each, so one load instruction reads four whole
+  // 256-B records; lane s of record r reads piece (s - r) & 15, which puts
+  // piece i of record r in slot (i + r) & 15 of its 256 B, so that the 64
+  // lanes reading piece i of their own records fall in different banks.  A
+  // corner that nearest mode leaves out reads corner 0's record (unused).
+  float2 sideP;
+  auto issue = [&](int it) __attribute__((always_inline)) {
+    const QSlot<CT> sl = s_q[wv][grp * 8 + it];
+    const CornerC<CT> c = slot_corner(sl, a.g, j);
+    const size_t v0 = (size_t)sl.i0[0] + (size_t)a.g.nx * ((size_t)sl.i0[1] +
+                                                          (size_t)a.g.ny * (size_t)sl.i0[2]);
+    const int v = (int)(uint32_t)(c.active ? c.vox : v0);
+    sideP = *reinterpret_cast<const float2*>(field + nvox * kMain + c.cell * kSideRec + 2 * j);
+    const int s = lane & 15;
+    // the voxels of records 4k + (lane >> 4), k = 0..15, exchanged through the
+    // record buffer itself (its previous records have been read)
+    __builtin_amdgcn_s_waitcnt(0xC07F);  // lgkmcnt(0): the step's LDS reads are done
+    int* sv = reinterpret_cast<int*>(&s_rec[wv][0]);
+    sv[(lane & 3) * 16 + (lane >> 2)] = v;
+    wave_sync();
+    int vk[16];
+#pragma unroll
+    for (int q4 = 0; q4 < 4; ++q4) {
+      const int4 x = reinterpret_cast<const int4*>(sv)[(lane >> 4) * 4 + q4];
+      vk[4 * q4] = x.x; vk[4 * q4 + 1] = x.y; vk[4 * q4 + 2] = x.z; vk[4 * q4 + 3] = x.w;
+    }
+    __builtin_amdgcn_s_waitcnt(0xC07F);  // lgkmcnt(0): before the loads overwrite the buffer
+    wave_sync();
+#pragma unroll
+    for (int k = 0; k < 16; ++k) {
+      const int r = 4 * k + (lane >> 4);
+      const float4* src = field4 + (size_t)(uint32_t)vk[k] * kRecF4 + ((s - r) & 15);
+      __builtin_amdgcn_global_load_lds((gptr)src, (lptr)&s_rec[wv][k * 64], 16, 0, 0);
+    }
+  };
+  auto stage = [&](FT rec[kMom]) __attribute__((always_inline)) {
+    __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0): the step's records are in LDS
+    wave_sync();
+    const float4* rr = &s_rec[wv][lane * kRecF4];
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+      const float4 x = rr[(i + lane) & 15];
+      rec[4 * i] = x.x; rec[4 * i + 1] = x.y; rec[4 * i + 2] = x.z; rec[4 * i + 3] = x.w;
+    }
+    rec[kMain] = sideP.x;
+    rec[kMain + 1] = sideP.y;
   };
 
-  int buf = 0;
   {
     FT tr[7];
     raw_pose(gw, tr);
-    s_q[wv][0][lane] = slot_of(tr);
+    s_q[wv][lane] = slot_of(tr);
   }
   wave_sync();
-  FT recN[kMom];
-  fetch(s_q[wv][0], 0, recN);
+  issue(0);
 
   for (int64_t b = gw; b < nbatch; b += nw) {
     // corner steps (gathers + FP32 contraction) at a raised wave priority and
     // the FP64 metric step at the normal one, so that a wave about to issue
     // gathers is not held back behind another wave's long FP64 stretch
-    // (4.50 -> 4.35 ms right after a build)
     __builtin_amdgcn_s_setprio(1);
-    const QSlot<CT>* sq = s_q[wv][buf];
     const bool more = b + nw < nbatch;
     FT trn[7];
     if (more) raw_pose(b + nw, trn);
@@ -281,12 +333,11 @@ __global__ __launch_bounds__(kQThreads) void query_info_pipe_kernel(QueryArgs a,
     for (int e = 0; e < 21; ++e) Z[e] = 0;
 #pragma unroll 1
     for (int it = 0; it < 8; ++it) {
-      const QSlot<CT> sl = sq[grp * 8 + it];
+      const QSlot<CT> sl = s_q[wv][grp * 8 + it];
       const CornerC<CT> c = slot_corner(sl, a.g, j);
       FT rec[kMom];
-#pragma unroll
-      for (int e = 0; e < kMom; ++e) rec[e] = recN[e];
-      if (it < 7) fetch(sq, it + 1, recN);
+      stage(rec);
+      if (it < 7) issue(it + 1);
       CT Y[21];
       if (c.active) {
         corner_fim<CT>(rec, vis_weights<CT>(sl.z, k2, k1, k0), c.dl, Y);
@@ -300,11 +351,12 @@ __global__ __launch_bounds__(kQThreads) void query_info_pipe_kernel(QueryArgs a,
 #pragma unroll
       for (int e = 0; e < 21; ++e) Z[e] = (j == it) ? Y[e] : Z[e];
     }
-    const QSlot<CT> own = sq[lane];
+    const QSlot<CT> own = s_q[wv][lane];
     if (more) {
-      s_q[wv][buf ^ 1][lane] = slot_of(trn);
+      wave_sync();  // every lane's reads of this batch's slots come first
+      s_q[wv][lane] = slot_of(trn);
       wave_sync();
-      fetch(s_q[wv][buf ^ 1], 0, recN);
+      issue(0);
     }
 
     __builtin_amdgcn_s_setprio(0);
@@ -321,7 +373,6 @@ __global__ __launch_bounds__(kQThreads) void query_info_pipe_kernel(QueryArgs a,
     double* row = (valid && a.out) ? a.out + qi * a.ncols : nullptr;
     eval_metrics<false>(F, a.metrics, row, &flag, nullptr, nullptr, a.flags != nullptr);
     if (valid && a.flags) a.flags[qi] = flag;
-    buf ^= 1;
   }
 }
 
@@ -684,13 +735,15 @@ __global__ void export_trace_kernel(ExportArgs a) {
 }
 
 // Workgroups of the persistent query: 8 per CU of the current device (two are
-// resident per CU at this kernel's register count; the rest even out the tail).
+// resident per CU at this kernel's register count and 80 KB of LDS; the rest
+// even out the tail).
 static int64_t pipe_blocks() { return (int64_t)current_device_cus() * 8; }
 
 hipError_t launch_query(const QueryArgs& a, int prec, int kind, bool grad, hipStream_t stream) {
   if (a.m <= 0) return hipSuccess;
   const bool dbl = (prec == 2);
-  if (kind == 0 && !grad && !dbl) {  // persistent: any m in one launch
+  const uint64_t nvox = (uint64_t)a.g.nx * a.g.ny * a.g.nz;
+  if (kind == 0 && !grad && !dbl && nvox <= UINT32_MAX) {  // persistent: any m in one launch
     const int64_t nbatch = (a.m + 63) / 64;
     const int64_t want = (nbatch + kPipeWaves - 1) / kPipeWaves;
     const int64_t cap = pipe_blocks();
