@@ -11,9 +11,10 @@
 // FIM of its own query and evaluates the FP64 metrics, so no lane idles in the
 // eigen-solve.  The fused backward repeats the corner gathers with the metric
 // gradient broadcast to the group.  Forward queries on FP32 fields run in
-// query_info_pipe_kernel, the same arithmetic with persistent waves and the
-// gathers issued one corner step (and one batch) ahead.  Also here: the trace
-// field query, the optimal-view sweep and the export of the paper's blocks.
+// query_info_pipe_kernel: one query per lane, the same per-corner arithmetic,
+// persistent waves and the gathers issued one corner step (and one batch)
+// ahead.  Also here: the trace field query, the optimal-view sweep and the
+// export of the paper's blocks.
 #include "fif_kernels.h"
 #include "fif_metrics.h"
 #include "fif_slot.h"
@@ -216,33 +217,88 @@ __global__ __launch_bounds__(kQThreads) void query_info_kernel(QueryArgs a) {
 }
 
 // Forward query on FP32 fields with persistent waves.  Each wave takes
-// batches of 64 queries in turn (the same per-query arithmetic and order as
-// query_info_kernel, so the results are bitwise identical).  The main records
-// of a corner step are loaded straight into LDS (global_load_lds_dwordx4),
+// batches of 64 queries in turn, one query per lane, and visits the 8 cell
+// corners in 8 steps: step k gathers corner k of all 64 queries.  The main
+// records of a step are loaded straight into LDS (global_load_lds_dwordx4),
 // 16 lanes per record so that each load instruction reads whole records, and
 // each lane then reads its own record from LDS; a lane loading its own record
 // instead (64 records per instruction) moves fewer bytes per second.  The
-// records of a batch's next corner step are loaded before the current step is
-// contracted, and the first step of the wave's next batch before the current
-// batch's FP64 metric step, so the gathers stay in flight throughout.  The LDS
-// slots and records are private to a wave and no workgroup barrier is used: a
-// wave leaves as soon as its batches are done.  Voxel indices are 32-bit here
-// (grids of 2^32 voxels or more take query_info_kernel).
+// records of the next step are loaded before the current step is contracted,
+// and the first step of the wave's next batch (with each lane's 64-B cell side
+// record, read whole into registers once per batch) before the current
+// batch's FP64 metric step, so the gathers stay in flight throughout; no load
+// is issued where the next wait on the step's records would cover it before
+// it is needed.  Each corner
+// term is the one query_info_kernel computes; a lane adds its query's 8 terms
+// with a chain of FMAs (weight times block, in corner order), where
+// query_info_kernel rounds each weighted block and sums them in an 8-lane
+// butterfly, so the two agree to FP32 rounding of that sum (bitwise for
+// nearest-voxel queries, which take step 0 only).  The LDS slots and records
+// are private to a wave and no workgroup barrier is used: a wave leaves as
+// soon as its batches are done.  Voxel indices are 32-bit here (grids of 2^32
+// voxels or more take query_info_kernel).
 constexpr int kPipeWaves = kQThreads / 64;
 
 
 constexpr int kRecF4 = kMain / 4;  // float4 per main record
+
+// The per-query data a lane keeps for its own query (QSlot without d f / d t).
+struct PSlot {
+  float t[3], z[3], f[3];
+  int32_t i0[3];
+  int32_t bits;
+};
+
+__device__ inline PSlot pslot(const QSlot<float>& q) {
+  PSlot p;
+#pragma unroll
+  for (int ax = 0; ax < 3; ++ax) {
+    p.t[ax] = q.t[ax]; p.z[ax] = q.z[ax]; p.f[ax] = q.f[ax]; p.i0[ax] = q.i0[ax];
+  }
+  p.bits = q.bits;
+  return p;
+}
+
+// Corner data of one query that do not depend on the corner: for each axis the
+// lower and upper trilinear weights and shifts, and the voxel-index steps.
+struct LaneCell {
+  float wlo[3], whi[3], dlo[3], dhi[3];
+  uint32_t v0, sx, sy, sz;
+};
+
+__device__ inline LaneCell lane_cell(const PSlot& s, const GridDev& g) {
+  LaneCell c;
+  const double o[3] = {g.ox, g.oy, g.oz};
+  const bool nearest = (s.bits & 16) != 0;
+#pragma unroll
+  for (int ax = 0; ax < 3; ++ax) {
+    const int step = (s.bits >> ax) & 1;
+    c.wlo[ax] = nearest ? 1.0f + s.f[ax] : 1.0f - s.f[ax];
+    c.whi[ax] = nearest ? 1.0f + s.f[ax] : s.f[ax];
+    c.dlo[ax] = (float)((o[ax] + (double)s.i0[ax] * g.h) - (double)s.t[ax]);
+    c.dhi[ax] = (float)((o[ax] + (double)(s.i0[ax] + step) * g.h) - (double)s.t[ax]);
+  }
+  const uint32_t nx = (uint32_t)g.nx, nxy = (uint32_t)g.nx * (uint32_t)g.ny;
+  c.v0 = (uint32_t)s.i0[0] + nx * ((uint32_t)s.i0[1] + (uint32_t)g.ny * (uint32_t)s.i0[2]);
+  c.sx = (uint32_t)(s.bits & 1);
+  c.sy = ((s.bits >> 1) & 1) ? nx : 0u;
+  c.sz = ((s.bits >> 2) & 1) ? nxy : 0u;
+  return c;
+}
+
+__device__ inline uint32_t lane_vox(const LaneCell& c, int k) {
+  return c.v0 + ((k & 1) ? c.sx : 0u) + ((k & 2) ? c.sy : 0u) + ((k & 4) ? c.sz : 0u);
+}
 
 __global__ __launch_bounds__(kQThreads, 2) void query_info_pipe_kernel(QueryArgs a, int64_t nbatch) {
   using FT = float;
   using CT = float;
   typedef const void __attribute__((address_space(1)))* gptr;
   typedef void __attribute__((address_space(3)))* lptr;
-  __shared__ QSlot<CT> s_q[kPipeWaves][64];
+  __shared__ PSlot s_q[kPipeWaves][64];  // each lane's query of the next batch
   __shared__ float4 s_rec[kPipeWaves][64 * kRecF4];  // a corner step's 64 main records
   const int tid = threadIdx.x;
   const int lane = tid & 63, wv = tid >> 6;
-  const int grp = lane >> 3, j = lane & 7;
   const int64_t gw = (int64_t)blockIdx.x * kPipeWaves + wv;
   const int64_t nw = (int64_t)gridDim.x * kPipeWaves;
   if (gw >= nbatch) return;  // whole wave
@@ -250,6 +306,7 @@ __global__ __launch_bounds__(kQThreads, 2) void query_info_pipe_kernel(QueryArgs
   const float4* field4 = reinterpret_cast<const float4*>(a.field);
   const size_t nvox = (size_t)a.g.nx * a.g.ny * a.g.nz;
   const CT k2 = (CT)a.vis.k2, k1 = (CT)a.vis.k1, k0 = (CT)a.vis.k0;
+  const int nsteps = a.interp == 1 ? 1 : 8;
   const FT* T = reinterpret_cast<const FT*>(a.t);
   const FT* Q = reinterpret_cast<const FT*>(a.q);
   auto raw_pose = [&](int64_t b, FT tr[7]) {
@@ -262,27 +319,21 @@ __global__ __launch_bounds__(kQThreads, 2) void query_info_pipe_kernel(QueryArgs
     quat_axis((double)tr[3], (double)tr[4], (double)tr[5], (double)tr[6], z);
     return make_slot_from<FT>(a, t, z);
   };
-  // Corner step `it` serves record r = lane r's (corner j of query 8 grp + it).
-  // The 64 main records go straight to LDS: load k (0..15) covers records
-  // 4k .. 4k+3 with 16 lanes each, so one load instruction reads four whole
-  // 256-B records; lane s of record r reads piece (s - r) & 15, which puts
-  // piece i of record r in slot (i + r) & 15 of its 256 B, so that the 64
-  // lanes reading piece i of their own records fall in different banks.  A
-  // corner that nearest mode leaves out reads corner 0's record (unused).
-  float2 sideP;
-  auto issue = [&](int it) __attribute__((always_inline)) {
-    const QSlot<CT> sl = s_q[wv][grp * 8 + it];
-    const CornerC<CT> c = slot_corner(sl, a.g, j);
-    const size_t v0 = (size_t)sl.i0[0] + (size_t)a.g.nx * ((size_t)sl.i0[1] +
-                                                          (size_t)a.g.ny * (size_t)sl.i0[2]);
-    const int v = (int)(uint32_t)(c.active ? c.vox : v0);
-    sideP = *reinterpret_cast<const float2*>(field + nvox * kMain + c.cell * kSideRec + 2 * j);
+  // Step k loads record r = corner k of lane r's query.  The 64 main records
+  // go straight to LDS: load q (0..15) covers records 4q .. 4q+3 with 16 lanes
+  // each, so one load instruction reads four whole 256-B records; lane s of
+  // record r reads piece (s - r) & 15, which puts piece i of record r in slot
+  // (i + r) & 15 of its 256 B, so that the 64 lanes reading piece i of their
+  // own records fall in different banks.
+  auto issue = [&](uint32_t v) __attribute__((always_inline)) {
     const int s = lane & 15;
-    // the voxels of records 4k + (lane >> 4), k = 0..15, exchanged through the
-    // record buffer itself (its previous records have been read)
+    // the voxels of records 4q + (lane >> 4), q = 0..15, exchanged through the
+    // record buffer itself (its previous records have been read); done before
+    // any load of the step is issued, so that no wait on the step's loads is
+    // needed before these LDS accesses
     __builtin_amdgcn_s_waitcnt(0xC07F);  // lgkmcnt(0): the step's LDS reads are done
     int* sv = reinterpret_cast<int*>(&s_rec[wv][0]);
-    sv[(lane & 3) * 16 + (lane >> 2)] = v;
+    sv[(lane & 3) * 16 + (lane >> 2)] = (int)v;
     wave_sync();
     int vk[16];
 #pragma unroll
@@ -293,10 +344,10 @@ __global__ __launch_bounds__(kQThreads, 2) void query_info_pipe_kernel(QueryArgs
     __builtin_amdgcn_s_waitcnt(0xC07F);  // lgkmcnt(0): before the loads overwrite the buffer
     wave_sync();
 #pragma unroll
-    for (int k = 0; k < 16; ++k) {
-      const int r = 4 * k + (lane >> 4);
-      const float4* src = field4 + (size_t)(uint32_t)vk[k] * kRecF4 + ((s - r) & 15);
-      __builtin_amdgcn_global_load_lds((gptr)src, (lptr)&s_rec[wv][k * 64], 16, 0, 0);
+    for (int q = 0; q < 16; ++q) {
+      const int r = 4 * q + (lane >> 4);
+      const float4* src = field4 + (size_t)(uint32_t)vk[q] * kRecF4 + ((s - r) & 15);
+      __builtin_amdgcn_global_load_lds((gptr)src, (lptr)&s_rec[wv][q * 64], 16, 0, 0);
     }
   };
   auto stage = [&](FT rec[kMom]) __attribute__((always_inline)) {
@@ -308,17 +359,28 @@ __global__ __launch_bounds__(kQThreads, 2) void query_info_pipe_kernel(QueryArgs
       const float4 x = rr[(i + lane) & 15];
       rec[4 * i] = x.x; rec[4 * i + 1] = x.y; rec[4 * i + 2] = x.z; rec[4 * i + 3] = x.w;
     }
-    rec[kMain] = sideP.x;
-    rec[kMain + 1] = sideP.y;
+  };
+  // the lane's cell side record (the 2 extra moments of each of the 8
+  // corners), read whole once per batch
+  float side[kSideRec];
+  auto load_side = [&](uint32_t cell) __attribute__((always_inline)) {
+    const float4* sp = reinterpret_cast<const float4*>(field + nvox * kMain + (size_t)cell * kSideRec);
+#pragma unroll
+    for (int i = 0; i < kSideRec / 4; ++i) {
+      const float4 x = sp[i];
+      side[4 * i] = x.x; side[4 * i + 1] = x.y; side[4 * i + 2] = x.z; side[4 * i + 3] = x.w;
+    }
   };
 
   {
     FT tr[7];
     raw_pose(gw, tr);
-    s_q[wv][lane] = slot_of(tr);
+    const PSlot sl = pslot(slot_of(tr));
+    s_q[wv][lane] = sl;
+    const LaneCell lc = lane_cell(sl, a.g);
+    issue(lc.v0);
+    load_side(lc.v0);
   }
-  wave_sync();
-  issue(0);
 
   for (int64_t b = gw; b < nbatch; b += nw) {
     // corner steps (gathers + FP32 contraction) at a raised wave priority and
@@ -327,36 +389,45 @@ __global__ __launch_bounds__(kQThreads, 2) void query_info_pipe_kernel(QueryArgs
     __builtin_amdgcn_s_setprio(1);
     const bool more = b + nw < nbatch;
     FT trn[7];
-    if (more) raw_pose(b + nw, trn);
+    const PSlot own = s_q[wv][lane];
+    const LaneCell lc = lane_cell(own, a.g);
+    const VisW<CT> vw = vis_weights<CT>(own.z, k2, k1, k0);
     CT Z[21];
 #pragma unroll
     for (int e = 0; e < 21; ++e) Z[e] = 0;
 #pragma unroll 1
-    for (int it = 0; it < 8; ++it) {
-      const QSlot<CT> sl = s_q[wv][grp * 8 + it];
-      const CornerC<CT> c = slot_corner(sl, a.g, j);
+    for (int k = 0; k < nsteps; ++k) {
       FT rec[kMom];
       stage(rec);
-      if (it < 7) issue(it + 1);
+      // the next batch's poses (the last batch re-reads its own), requested
+      // after the first wait on the step loads so that no wait covers them
+      // before the step after
+      if (k == 0) raw_pose(more ? b + nw : b, trn);
+      rec[kMain] = side[0];
+      rec[kMain + 1] = side[1];
+#pragma unroll
+      for (int i = 0; i < kSideRec - 2; ++i) side[i] = side[i + 2];
+      if (k + 1 < nsteps) issue(lane_vox(lc, k + 1));
+      const int bx = k & 1, by = (k >> 1) & 1, bz = k >> 2;
+      const CT w = (bx ? lc.whi[0] : lc.wlo[0]) * (by ? lc.whi[1] : lc.wlo[1]) *
+                   (bz ? lc.whi[2] : lc.wlo[2]);
+      const CT dl[3] = {bx ? lc.dhi[0] : lc.dlo[0], by ? lc.dhi[1] : lc.dlo[1],
+                        bz ? lc.dhi[2] : lc.dlo[2]};
       CT Y[21];
-      if (c.active) {
-        corner_fim<CT>(rec, vis_weights<CT>(sl.z, k2, k1, k0), c.dl, Y);
+      corner_fim<CT>(rec, vw, dl, Y);
 #pragma unroll
-        for (int e = 0; e < 21; ++e) Y[e] *= c.w;
-      } else {
-#pragma unroll
-        for (int e = 0; e < 21; ++e) Y[e] = 0;
-      }
-      sum8_arr<21>(Y);
-#pragma unroll
-      for (int e = 0; e < 21; ++e) Z[e] = (j == it) ? Y[e] : Z[e];
+      for (int e = 0; e < 21; ++e) Z[e] = fmaf(Y[e], w, Z[e]);
     }
-    const QSlot<CT> own = s_q[wv][lane];
-    if (more) {
-      wave_sync();  // every lane's reads of this batch's slots come first
-      s_q[wv][lane] = slot_of(trn);
-      wave_sync();
-      issue(0);
+    {
+      // the side record is read on every path (no merge of loaded registers
+      // before the metric step, which would wait for the loads)
+      const PSlot nx = pslot(slot_of(trn));
+      const LaneCell nc = lane_cell(nx, a.g);
+      if (more) {
+        s_q[wv][lane] = nx;
+        issue(nc.v0);
+      }
+      load_side(nc.v0);
     }
 
     __builtin_amdgcn_s_setprio(0);
