@@ -379,9 +379,9 @@ def main():
     if "grad" in phases:
         g_bytes = mg * GRAD_BYTES_PER_POSE
         g_gbs = g_bytes / (med["grad"] / 1e3) / 1e9
-        g_traffic = counter_traffic("fif::query_info_kernel<float, true>")
+        g_traffic = counter_traffic("fif::query_grad_pipe_kernel")
         res["roofline_grad"] = {
-            "kernel": "query_info_kernel<float,true>", "bound": "hbm", "achieved": g_gbs,
+            "kernel": "query_grad_pipe_kernel", "bound": "hbm", "achieved": g_gbs,
             "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": g_gbs / HBM_PEAK_GBS,
             "bytes_per_pose": GRAD_BYTES_PER_POSE, "algorithmic_bytes": g_bytes,
             "traffic": g_traffic,

@@ -17,6 +17,8 @@ __device__ inline void eval_metrics(const double F[21], uint32_t metrics, double
                                     uint8_t* flag, const double* up, double G[21],
                                     bool want_pd = true) {
   int col = 0, upc = 0;
+  // up[upc] with constant indices only (a runtime index would put up in scratch)
+  auto upat = [&](int c) { return c == 0 ? up[0] : (c == 1 ? up[1] : up[2]); };
   if (GRAD) {
 #pragma unroll
     for (int e = 0; e < 21; ++e) G[e] = 0.0;
@@ -27,7 +29,7 @@ __device__ inline void eval_metrics(const double F[21], uint32_t metrics, double
     if (row) row[col] = tr;
     ++col;
     if (GRAD) {
-      double g = up[upc++];
+      double g = upat(upc++);
 #pragma unroll
       for (int i = 0; i < 6; ++i) G[u21(i, i)] += g;
     }
@@ -60,7 +62,7 @@ __device__ inline void eval_metrics(const double F[21], uint32_t metrics, double
       // tie, which is flagged); v by inverse iteration with the shift
       // 1e-10 max|lambda| below lambda_min, more than the Jacobi error of
       // lambda_min (1e-11 |F|), so that F - sigma I stays positive definite
-      double g = up[upc++];
+      double g = upat(upc++);
       double v[6];
       lmin_vector6(F, lmin - fmax(1e-10 * amax, 1e-300), v);
 #pragma unroll
@@ -77,7 +79,7 @@ __device__ inline void eval_metrics(const double F[21], uint32_t metrics, double
       if (row) row[col] = ld;
       ++col;
       if (GRAD) {
-        double g = up[upc++];
+        double g = upat(upc++);
         double inv[21];
         ldlt6_inverse(L, dinv, inv);
         // a zero weight leaves the log-det out of L, so a FIM that is not

@@ -1,20 +1,21 @@
 // Batched pose queries, their fused backward, and the export of the paper's
 // factor blocks (Sec. VI-A, eq:fim_separation).
 //
-// Information field, trilinear: a wave serves 64 queries.  Lanes are grouped
-// by 8; in pass `it` group g serves query 8g + it and lane j of the group
-// gathers trilinear corner j (a 264-B record for FP32 fields), contracts its
-// moments with the optical axis into the voxel's 6x6 block, moves it to the
-// query position (the blocks are taken about different voxel centres, so
-// each corner is shifted before the weighted sum), and the 8 partial sums
-// are reduced with cross-lane shuffles.  After 8 passes every lane holds the
-// FIM of its own query and evaluates the FP64 metrics, so no lane idles in the
-// eigen-solve.  The fused backward repeats the corner gathers with the metric
-// gradient broadcast to the group.  Forward queries on FP32 fields run in
-// query_info_pipe_kernel: one query per lane, the same per-corner arithmetic,
-// persistent waves and the gathers issued one corner step (and one batch)
-// ahead.  Also here: the trace field query, the optimal-view sweep and the
-// export of the paper's blocks.
+// Information field, trilinear.  Each trilinear corner (a 264-B record for
+// FP32 fields) has its moments contracted with the optical axis into the
+// voxel's 6x6 block, which is moved to the query position (the blocks are
+// taken about different voxel centres, so each corner is shifted before the
+// weighted sum); every lane then evaluates the FP64 metrics of its own query.
+// On FP32 fields (up to 2^32 voxels) the forward query and its gradient run in
+// persistent waves with one query per lane (query_info_pipe_kernel,
+// query_grad_pipe_kernel): corner step k gathers corner k of the wave's 64
+// queries straight into LDS, one step (and one batch) ahead of the arithmetic.
+// query_info_kernel serves FP64 fields and larger grids: lanes grouped by 8,
+// in pass `it` group g serves query 8g + it and lane j gathers corner j; the
+// 8 partial sums are reduced with cross-lane moves, and the fused backward
+// repeats the corner gathers with the metric gradient broadcast to the group.
+// Also here: the trace field query, the optimal-view sweep and the export of
+// the paper's blocks.
 #include "fif_kernels.h"
 #include "fif_metrics.h"
 #include "fif_slot.h"
@@ -233,7 +234,10 @@ __global__ __launch_bounds__(kQThreads) void query_info_kernel(QueryArgs a) {
 // with a chain of FMAs (weight times block, in corner order), where
 // query_info_kernel rounds each weighted block and sums them in an 8-lane
 // butterfly, so the two agree to FP32 rounding of that sum (bitwise for
-// nearest-voxel queries, which take step 0 only).  The LDS slots and records
+// nearest-voxel queries, which take step 0 only).  The gradient on the same
+// fields runs in query_grad_pipe_kernel, whose forward part is this one's, so
+// a pose's forward values do not depend on which of the two computed them.
+// The LDS slots and records
 // are private to a wave and no workgroup barrier is used: a wave leaves as
 // soon as its batches are done.  Voxel indices are 32-bit here (grids of 2^32
 // voxels or more take query_info_kernel).
@@ -290,11 +294,102 @@ __device__ inline uint32_t lane_vox(const LaneCell& c, int k) {
   return c.v0 + ((k & 1) ? c.sx : 0u) + ((k & 2) ? c.sy : 0u) + ((k & 4) ? c.sz : 0u);
 }
 
+typedef const void __attribute__((address_space(1)))* gptr_t;
+typedef void __attribute__((address_space(3)))* lptr_t;
+
+// One corner step's gathers into the wave's record buffer `buf` (64 main
+// records of 256 B): record r is the voxel `v` of lane r.  Load q (0..15)
+// covers records 4q .. 4q+3 with 16 lanes each, so one load instruction reads
+// four whole records; lane s of record r reads piece (s - r) & 15, which puts
+// piece i of record r in slot (i + r) & 15 of its 256 B, so that the 64 lanes
+// reading piece i of their own records fall in different banks.  The voxels
+// are exchanged through the buffer itself (its previous records have been
+// read) before any load of the step is issued, so that no wait on the step's
+// loads is needed before these LDS accesses.
+__device__ __forceinline__ void pipe_issue(float4* buf, const float4* field4, uint32_t v, int lane) {
+  const int s = lane & 15;
+  __builtin_amdgcn_s_waitcnt(0xC07F);  // lgkmcnt(0): the step's LDS reads are done
+  int* sv = reinterpret_cast<int*>(buf);
+  sv[(lane & 3) * 16 + (lane >> 2)] = (int)v;
+  wave_sync();
+  int vk[16];
+#pragma unroll
+  for (int q4 = 0; q4 < 4; ++q4) {
+    const int4 x = reinterpret_cast<const int4*>(sv)[(lane >> 4) * 4 + q4];
+    vk[4 * q4] = x.x; vk[4 * q4 + 1] = x.y; vk[4 * q4 + 2] = x.z; vk[4 * q4 + 3] = x.w;
+  }
+  __builtin_amdgcn_s_waitcnt(0xC07F);  // lgkmcnt(0): before the loads overwrite the buffer
+  wave_sync();
+#pragma unroll
+  for (int q = 0; q < 16; ++q) {
+    const int r = 4 * q + (lane >> 4);
+    const float4* src = field4 + (size_t)(uint32_t)vk[q] * kRecF4 + ((s - r) & 15);
+    __builtin_amdgcn_global_load_lds((gptr_t)src, (lptr_t)&buf[q * 64], 16, 0, 0);
+  }
+}
+
+// Waits for the step's gathers and reads the lane's own record from `buf`.
+__device__ __forceinline__ void pipe_stage(const float4* buf, int lane, float rec[kMom]) {
+  __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0): the step's records are in LDS
+  wave_sync();
+  const float4* rr = &buf[lane * kRecF4];
+#pragma unroll
+  for (int i = 0; i < 16; ++i) {
+    const float4 x = rr[(i + lane) & 15];
+    rec[4 * i] = x.x; rec[4 * i + 1] = x.y; rec[4 * i + 2] = x.z; rec[4 * i + 3] = x.w;
+  }
+}
+
+// The lane's cell side record (the 2 extra moments of each of the 8 corners),
+// read whole into registers once per batch.
+__device__ __forceinline__ void load_side16(const float* field, size_t nvox, uint32_t cell,
+                                            float side[kSideRec]) {
+  const float4* sp = reinterpret_cast<const float4*>(field + nvox * kMain + (size_t)cell * kSideRec);
+#pragma unroll
+  for (int i = 0; i < kSideRec / 4; ++i) {
+    const float4 x = sp[i];
+    side[4 * i] = x.x; side[4 * i + 1] = x.y; side[4 * i + 2] = x.z; side[4 * i + 3] = x.w;
+  }
+}
+
+// Corner k's pair of the side record into rec, then the record rotated by one
+// pair (after 8 steps it is back in corner order).
+__device__ __forceinline__ void take_side(float rec[kMom], float side[kSideRec]) {
+  const float s0 = side[0], s1 = side[1];
+  rec[kMain] = s0;
+  rec[kMain + 1] = s1;
+#pragma unroll
+  for (int i = 0; i < kSideRec - 2; ++i) side[i] = side[i + 2];
+  side[kSideRec - 2] = s0;
+  side[kSideRec - 1] = s1;
+}
+
+// Trilinear weight and shift (voxel centre - frame point) of corner k.
+__device__ __forceinline__ float corner_of(const LaneCell& lc, int k, float dl[3]) {
+  const int bx = k & 1, by = (k >> 1) & 1, bz = k >> 2;
+  dl[0] = bx ? lc.dhi[0] : lc.dlo[0];
+  dl[1] = by ? lc.dhi[1] : lc.dlo[1];
+  dl[2] = bz ? lc.dhi[2] : lc.dlo[2];
+  return (bx ? lc.whi[0] : lc.wlo[0]) * (by ? lc.whi[1] : lc.wlo[1]) * (bz ? lc.whi[2] : lc.wlo[2]);
+}
+
+__device__ __forceinline__ void raw_pose7(const QueryArgs& a, int64_t b, int lane, float tr[7]) {
+  const float* T = reinterpret_cast<const float*>(a.t);
+  const float* Q = reinterpret_cast<const float*>(a.q);
+  const int64_t i = min(b * 64 + lane, a.m - 1);
+  tr[0] = T[3 * i]; tr[1] = T[3 * i + 1]; tr[2] = T[3 * i + 2];
+  tr[3] = Q[4 * i]; tr[4] = Q[4 * i + 1]; tr[5] = Q[4 * i + 2]; tr[6] = Q[4 * i + 3];
+}
+
+__device__ __forceinline__ QSlot<float> slot7(const QueryArgs& a, const float tr[7]) {
+  double t[3] = {(double)tr[0], (double)tr[1], (double)tr[2]}, z[3];
+  quat_axis((double)tr[3], (double)tr[4], (double)tr[5], (double)tr[6], z);
+  return make_slot_from<float>(a, t, z);
+}
+
 __global__ __launch_bounds__(kQThreads, 2) void query_info_pipe_kernel(QueryArgs a, int64_t nbatch) {
   using FT = float;
   using CT = float;
-  typedef const void __attribute__((address_space(1)))* gptr;
-  typedef void __attribute__((address_space(3)))* lptr;
   __shared__ PSlot s_q[kPipeWaves][64];  // each lane's query of the next batch
   __shared__ float4 s_rec[kPipeWaves][64 * kRecF4];  // a corner step's 64 main records
   const int tid = threadIdx.x;
@@ -304,82 +399,19 @@ __global__ __launch_bounds__(kQThreads, 2) void query_info_pipe_kernel(QueryArgs
   if (gw >= nbatch) return;  // whole wave
   const FT* field = reinterpret_cast<const FT*>(a.field);
   const float4* field4 = reinterpret_cast<const float4*>(a.field);
+  float4* buf = &s_rec[wv][0];
   const size_t nvox = (size_t)a.g.nx * a.g.ny * a.g.nz;
   const CT k2 = (CT)a.vis.k2, k1 = (CT)a.vis.k1, k0 = (CT)a.vis.k0;
   const int nsteps = a.interp == 1 ? 1 : 8;
-  const FT* T = reinterpret_cast<const FT*>(a.t);
-  const FT* Q = reinterpret_cast<const FT*>(a.q);
-  auto raw_pose = [&](int64_t b, FT tr[7]) {
-    const int64_t i = min(b * 64 + lane, a.m - 1);
-    tr[0] = T[3 * i]; tr[1] = T[3 * i + 1]; tr[2] = T[3 * i + 2];
-    tr[3] = Q[4 * i]; tr[4] = Q[4 * i + 1]; tr[5] = Q[4 * i + 2]; tr[6] = Q[4 * i + 3];
-  };
-  auto slot_of = [&](const FT tr[7]) {
-    double t[3] = {(double)tr[0], (double)tr[1], (double)tr[2]}, z[3];
-    quat_axis((double)tr[3], (double)tr[4], (double)tr[5], (double)tr[6], z);
-    return make_slot_from<FT>(a, t, z);
-  };
-  // Step k loads record r = corner k of lane r's query.  The 64 main records
-  // go straight to LDS: load q (0..15) covers records 4q .. 4q+3 with 16 lanes
-  // each, so one load instruction reads four whole 256-B records; lane s of
-  // record r reads piece (s - r) & 15, which puts piece i of record r in slot
-  // (i + r) & 15 of its 256 B, so that the 64 lanes reading piece i of their
-  // own records fall in different banks.
-  auto issue = [&](uint32_t v) __attribute__((always_inline)) {
-    const int s = lane & 15;
-    // the voxels of records 4q + (lane >> 4), q = 0..15, exchanged through the
-    // record buffer itself (its previous records have been read); done before
-    // any load of the step is issued, so that no wait on the step's loads is
-    // needed before these LDS accesses
-    __builtin_amdgcn_s_waitcnt(0xC07F);  // lgkmcnt(0): the step's LDS reads are done
-    int* sv = reinterpret_cast<int*>(&s_rec[wv][0]);
-    sv[(lane & 3) * 16 + (lane >> 2)] = (int)v;
-    wave_sync();
-    int vk[16];
-#pragma unroll
-    for (int q4 = 0; q4 < 4; ++q4) {
-      const int4 x = reinterpret_cast<const int4*>(sv)[(lane >> 4) * 4 + q4];
-      vk[4 * q4] = x.x; vk[4 * q4 + 1] = x.y; vk[4 * q4 + 2] = x.z; vk[4 * q4 + 3] = x.w;
-    }
-    __builtin_amdgcn_s_waitcnt(0xC07F);  // lgkmcnt(0): before the loads overwrite the buffer
-    wave_sync();
-#pragma unroll
-    for (int q = 0; q < 16; ++q) {
-      const int r = 4 * q + (lane >> 4);
-      const float4* src = field4 + (size_t)(uint32_t)vk[q] * kRecF4 + ((s - r) & 15);
-      __builtin_amdgcn_global_load_lds((gptr)src, (lptr)&s_rec[wv][q * 64], 16, 0, 0);
-    }
-  };
-  auto stage = [&](FT rec[kMom]) __attribute__((always_inline)) {
-    __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0): the step's records are in LDS
-    wave_sync();
-    const float4* rr = &s_rec[wv][lane * kRecF4];
-#pragma unroll
-    for (int i = 0; i < 16; ++i) {
-      const float4 x = rr[(i + lane) & 15];
-      rec[4 * i] = x.x; rec[4 * i + 1] = x.y; rec[4 * i + 2] = x.z; rec[4 * i + 3] = x.w;
-    }
-  };
-  // the lane's cell side record (the 2 extra moments of each of the 8
-  // corners), read whole once per batch
   float side[kSideRec];
-  auto load_side = [&](uint32_t cell) __attribute__((always_inline)) {
-    const float4* sp = reinterpret_cast<const float4*>(field + nvox * kMain + (size_t)cell * kSideRec);
-#pragma unroll
-    for (int i = 0; i < kSideRec / 4; ++i) {
-      const float4 x = sp[i];
-      side[4 * i] = x.x; side[4 * i + 1] = x.y; side[4 * i + 2] = x.z; side[4 * i + 3] = x.w;
-    }
-  };
-
   {
     FT tr[7];
-    raw_pose(gw, tr);
-    const PSlot sl = pslot(slot_of(tr));
+    raw_pose7(a, gw, lane, tr);
+    const PSlot sl = pslot(slot7(a, tr));
     s_q[wv][lane] = sl;
     const LaneCell lc = lane_cell(sl, a.g);
-    issue(lc.v0);
-    load_side(lc.v0);
+    pipe_issue(buf, field4, lc.v0, lane);
+    load_side16(field, nvox, lc.v0, side);
   }
 
   for (int64_t b = gw; b < nbatch; b += nw) {
@@ -398,21 +430,15 @@ __global__ __launch_bounds__(kQThreads, 2) void query_info_pipe_kernel(QueryArgs
 #pragma unroll 1
     for (int k = 0; k < nsteps; ++k) {
       FT rec[kMom];
-      stage(rec);
+      pipe_stage(buf, lane, rec);
       // the next batch's poses (the last batch re-reads its own), requested
       // after the first wait on the step loads so that no wait covers them
       // before the step after
-      if (k == 0) raw_pose(more ? b + nw : b, trn);
-      rec[kMain] = side[0];
-      rec[kMain + 1] = side[1];
-#pragma unroll
-      for (int i = 0; i < kSideRec - 2; ++i) side[i] = side[i + 2];
-      if (k + 1 < nsteps) issue(lane_vox(lc, k + 1));
-      const int bx = k & 1, by = (k >> 1) & 1, bz = k >> 2;
-      const CT w = (bx ? lc.whi[0] : lc.wlo[0]) * (by ? lc.whi[1] : lc.wlo[1]) *
-                   (bz ? lc.whi[2] : lc.wlo[2]);
-      const CT dl[3] = {bx ? lc.dhi[0] : lc.dlo[0], by ? lc.dhi[1] : lc.dlo[1],
-                        bz ? lc.dhi[2] : lc.dlo[2]};
+      if (k == 0) raw_pose7(a, more ? b + nw : b, lane, trn);
+      take_side(rec, side);
+      if (k + 1 < nsteps) pipe_issue(buf, field4, lane_vox(lc, k + 1), lane);
+      CT dl[3];
+      const CT w = corner_of(lc, k, dl);
       CT Y[21];
       corner_fim<CT>(rec, vw, dl, Y);
 #pragma unroll
@@ -421,13 +447,13 @@ __global__ __launch_bounds__(kQThreads, 2) void query_info_pipe_kernel(QueryArgs
     {
       // the side record is read on every path (no merge of loaded registers
       // before the metric step, which would wait for the loads)
-      const PSlot nx = pslot(slot_of(trn));
+      const PSlot nx = pslot(slot7(a, trn));
       const LaneCell nc = lane_cell(nx, a.g);
       if (more) {
         s_q[wv][lane] = nx;
-        issue(nc.v0);
+        pipe_issue(buf, field4, nc.v0, lane);
       }
-      load_side(nc.v0);
+      load_side16(field, nvox, nc.v0, side);
     }
 
     __builtin_amdgcn_s_setprio(0);
@@ -444,6 +470,166 @@ __global__ __launch_bounds__(kQThreads, 2) void query_info_pipe_kernel(QueryArgs
     double* row = (valid && a.out) ? a.out + qi * a.ncols : nullptr;
     eval_metrics<false>(F, a.metrics, row, &flag, nullptr, nullptr, a.flags != nullptr);
     if (valid && a.flags) a.flags[qi] = flag;
+  }
+}
+
+// Forward query and its gradient on FP32 fields with persistent waves, the
+// layout of query_info_pipe_kernel: one pose per lane, 8 forward corner steps
+// (the same arithmetic and order, so the forward values are bitwise those of
+// the forward query), the FP64 metric step with G = ds/dF, then 8 backward
+// corner steps that gather the records again (mostly from cache) and add up
+// the corner terms of ds/dt (through the trilinear weights) and ds/dz
+// (through vr(z)) in the lane.  The gathers of the backward pass's first
+// corner are issued before the metric step, those of the next batch's first
+// corner before the last backward step.
+__global__ __launch_bounds__(kQThreads, 2) void query_grad_pipe_kernel(QueryArgs a, int64_t nbatch) {
+  using FT = float;
+  using CT = float;
+  __shared__ QSlot<CT> s_q[kPipeWaves][64];  // each lane's query of the next batch
+  __shared__ float4 s_rec[kPipeWaves][64 * kRecF4];
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wv = tid >> 6;
+  const int64_t gw = (int64_t)blockIdx.x * kPipeWaves + wv;
+  const int64_t nw = (int64_t)gridDim.x * kPipeWaves;
+  if (gw >= nbatch) return;  // whole wave
+  const FT* field = reinterpret_cast<const FT*>(a.field);
+  const float4* field4 = reinterpret_cast<const float4*>(a.field);
+  float4* buf = &s_rec[wv][0];
+  const size_t nvox = (size_t)a.g.nx * a.g.ny * a.g.nz;
+  const CT k2 = (CT)a.vis.k2, k1 = (CT)a.vis.k1, k0 = (CT)a.vis.k0;
+  const int nmet = (int)((a.metrics & 1u) != 0) + (int)((a.metrics & 2u) != 0) +
+                   (int)((a.metrics & 4u) != 0);
+  FT* gt_out = reinterpret_cast<FT*>(a.dL_dt);
+  FT* gp_out = reinterpret_cast<FT*>(a.dL_dphi);
+  float side[kSideRec];
+  {
+    FT tr[7];
+    raw_pose7(a, gw, lane, tr);
+    const QSlot<CT> sl = slot7(a, tr);
+    s_q[wv][lane] = sl;
+    const LaneCell lc = lane_cell(pslot(sl), a.g);
+    pipe_issue(buf, field4, lc.v0, lane);
+    load_side16(field, nvox, lc.v0, side);
+  }
+
+  for (int64_t b = gw; b < nbatch; b += nw) {
+    __builtin_amdgcn_s_setprio(1);
+    const bool more = b + nw < nbatch;
+    CT Z[21];
+    double td[3];
+    int32_t bits;
+    {
+      const QSlot<CT> own = s_q[wv][lane];
+      const LaneCell lc = lane_cell(pslot(own), a.g);
+      const VisW<CT> vw = vis_weights<CT>(own.z, k2, k1, k0);
+#pragma unroll
+      for (int e = 0; e < 21; ++e) Z[e] = 0;
+#pragma unroll 1
+      for (int k = 0; k < 8; ++k) {
+        FT rec[kMom];
+        pipe_stage(buf, lane, rec);
+        take_side(rec, side);
+        // corner k + 1, and after corner 7 the backward pass's corner 0
+        pipe_issue(buf, field4, lane_vox(lc, (k + 1) & 7), lane);
+        CT dl[3];
+        const CT w = corner_of(lc, k, dl);
+        CT Y[21];
+        corner_fim<CT>(rec, vw, dl, Y);
+#pragma unroll
+        for (int e = 0; e < 21; ++e) Z[e] = fmaf(Y[e], w, Z[e]);
+      }
+      td[0] = own.t[0]; td[1] = own.t[1]; td[2] = own.t[2];
+      bits = own.bits;
+    }
+
+    // ------------------------------------------------ metrics and ds/dF (FP64)
+    // (the lane's slot, cell data and side record are read again afterwards,
+    // so that they do not occupy registers through the FP64 step)
+    __builtin_amdgcn_s_setprio(0);
+    const int64_t qi = b * 64 + lane;
+    const bool valid = qi < a.m;
+    const int64_t ql = valid ? qi : a.m - 1;
+    CT Gt[21];
+    {
+      double Zd[21], F[21], G[21];
+#pragma unroll
+      for (int e = 0; e < 21; ++e) Zd[e] = (double)Z[e];
+      shift21<double>(Zd, td, F);
+#pragma unroll
+      for (int e = 0; e < 21; ++e) F[e] *= a.vis.inv_s2;
+      uint8_t flag = (bits & 8) ? FL_CLAMPED : 0;
+      // upstream weights (constant indices: the array stays in registers)
+      const double* du = a.dL_dout + ql * nmet;
+      const double up[3] = {(valid && nmet > 0) ? du[0] : 0.0, (valid && nmet > 1) ? du[1] : 0.0,
+                            (valid && nmet > 2) ? du[2] : 0.0};
+      double* row = (valid && a.out) ? a.out + qi * a.ncols : nullptr;
+      eval_metrics<true>(F, a.metrics, row, &flag, up, G, a.flags != nullptr);
+      if (valid && a.flags) a.flags[qi] = flag;
+      double Gw[21];
+      shift21_adj<double>(G, td, Gw);
+#pragma unroll
+      for (int e = 0; e < 21; ++e) Gt[e] = (CT)(valid ? Gw[e] * a.vis.inv_s2 : 0.0);
+    }
+
+    // ------------------------------------------------ backward corner steps
+    __builtin_amdgcn_s_setprio(1);
+    const QSlot<CT> own = s_q[wv][lane];
+    const LaneCell lc = lane_cell(pslot(own), a.g);
+    load_side16(field, nvox, lc.v0, side);
+    FT trn[7];
+    CT keep[6] = {0, 0, 0, 0, 0, 0};
+    auto bstep = [&](int k) __attribute__((always_inline)) {
+      FT rec[kMom];
+      pipe_stage(buf, lane, rec);
+      // the next batch's poses (the last batch re-reads its own), requested
+      // after the first wait on the step loads
+      if (k == 0) raw_pose7(a, more ? b + nw : b, lane, trn);
+      take_side(rec, side);
+      if (k < 7) {
+        pipe_issue(buf, field4, lane_vox(lc, k + 1), lane);
+      } else {
+        // the next batch: its slot, first gathers and side record (the side
+        // record read on every path, so no loaded registers are merged)
+        const QSlot<CT> nx = slot7(a, trn);
+        const LaneCell nc = lane_cell(pslot(nx), a.g);
+        if (more) {
+          s_q[wv][lane] = nx;
+          pipe_issue(buf, field4, nc.v0, lane);
+        }
+        load_side16(field, nvox, nc.v0, side);
+      }
+      const int bx = k & 1, by = (k >> 1) & 1, bz = k >> 2;
+      CT dl[3];
+      const CT w = corner_of(lc, k, dl);
+      const CT wc[3] = {bx ? lc.whi[0] : lc.wlo[0], by ? lc.whi[1] : lc.wlo[1],
+                        bz ? lc.whi[2] : lc.wlo[2]};
+      const CT dwc[3] = {bx ? own.df[0] : -own.df[0], by ? own.df[1] : -own.df[1],
+                         bz ? own.df[2] : -own.df[2]};
+      const CT dw[3] = {dwc[0] * wc[1] * wc[2], wc[0] * dwc[1] * wc[2], wc[0] * wc[1] * dwc[2]};
+      CT Gp[21];
+      shift21_adj<CT>(Gt, dl, Gp);
+      CT val, gz[3];
+      corner_vjp<CT>(rec, Gp, own.z, k2, k1, k0, &val, gz);
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        keep[c] = fmaf(dw[c], val, keep[c]);
+        keep[3 + c] = fmaf(w, gz[c], keep[3 + c]);
+      }
+    };
+#pragma unroll 1
+    for (int k = 0; k < 7; ++k) bstep(k);
+    bstep(7);
+
+    if (valid) {
+      const CT* z = own.z;
+      const CT gphi[3] = {z[1] * keep[5] - z[2] * keep[4], z[2] * keep[3] - z[0] * keep[5],
+                          z[0] * keep[4] - z[1] * keep[3]};
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        gt_out[3 * qi + c] = keep[c];
+        gp_out[3 * qi + c] = gphi[c];
+      }
+    }
   }
 }
 
@@ -814,12 +1000,13 @@ hipError_t launch_query(const QueryArgs& a, int prec, int kind, bool grad, hipSt
   if (a.m <= 0) return hipSuccess;
   const bool dbl = (prec == 2);
   const uint64_t nvox = (uint64_t)a.g.nx * a.g.ny * a.g.nz;
-  if (kind == 0 && !grad && !dbl && nvox <= UINT32_MAX) {  // persistent: any m in one launch
+  if (kind == 0 && !dbl && nvox <= UINT32_MAX) {  // persistent: any m in one launch
     const int64_t nbatch = (a.m + 63) / 64;
     const int64_t want = (nbatch + kPipeWaves - 1) / kPipeWaves;
     const int64_t cap = pipe_blocks();
     dim3 pgrid((unsigned)(want < cap ? want : cap));
-    hipLaunchKernelGGL(query_info_pipe_kernel, pgrid, dim3(kQThreads), 0, stream, a, nbatch);
+    if (grad) hipLaunchKernelGGL(query_grad_pipe_kernel, pgrid, dim3(kQThreads), 0, stream, a, nbatch);
+    else hipLaunchKernelGGL(query_info_pipe_kernel, pgrid, dim3(kQThreads), 0, stream, a, nbatch);
     return hipGetLastError();
   }
   for (int64_t off = 0; off < a.m; off += kMaxLaunchItems) {

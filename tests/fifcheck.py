@@ -67,24 +67,3 @@ def metric_errors(gpu, ref, fim_ref21, cols=("trace", "lmin", "logdet")):
 
 def e_fim(gpu21, ref21):
     return fro21(np.asarray(gpu21) - np.asarray(ref21)) / fro21(ref21)
-
-
-# The forward query sums a pose's 8 weighted corner blocks with a chain of FP32
-# FMAs; the gradient kernel rounds each weighted block and adds them pairwise
-# across lanes.  Each order is within about 8 u sum_j |w_j Y_j| of the exact
-# sum (u = 2^-24), so the two FIMs differ by about 1e-6 of their scale (the
-# FP64 shift to the pose and the metrics add nothing at that level): the trace
-# by that much relatively, lambda_min by that much of lambda_max
-# (Weyl), and the log-det by tr(F^-1 dF), which ill-conditioned FIMs enlarge.
-FWD_ORDER_TOL = dict(trace_rel=2e-6, lmin_weyl=2e-6, logdet_abs=1e-4)
-
-
-def forward_order_errors(a, b, fim21):
-    """a, b: [m, 3] metric outputs (trace, lmin, logdet) of the same poses from the
-    two kernels; fim21 [m, 21] the FIM of one of them (scales lambda_min)
-    -> largest error per measure (NaN entries must match)."""
-    a, b, fim21 = np.asarray(a), np.asarray(b), np.asarray(fim21)
-    assert np.array_equal(np.isnan(a), np.isnan(b))
-    ok = ~np.isnan(a).any(axis=1) & ~np.isnan(fim21).any(axis=1)
-    err = metric_errors(a[ok], b[ok], fim21[ok])
-    return {k: float(np.max(v, initial=0.0)) for k, v in err.items() if k != "lmin_rel"}

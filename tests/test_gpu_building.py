@@ -10,8 +10,7 @@ import pytest
 
 import oracle
 import scenes
-from fifcheck import (FWD_ORDER_TOL, block_rel_err, e_fim, forward_order_errors, metric_errors,
-                      upper21)
+from fifcheck import block_rel_err, e_fim, metric_errors, upper21
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -463,20 +462,22 @@ def test_sorted_and_unsorted_builds_agree(fif, bld):
 
 
 def test_forward_query_agrees_with_gradient_kernel_forward(fif, bld):
-    """The forward FP32 query (persistent waves, one pose per lane) and the
-    forward part of the gradient kernel (8 lanes per pose) compute the same
-    corner terms and differ only in the FP32 order of their weighted sum: their
-    metrics agree to that rounding on ragged sizes, including a size whose
-    batches outnumber the resident waves many times over."""
+    """The forward FP32 query and the forward part of the gradient kernel (both
+    persistent waves, one pose per lane) evaluate the same per-pose arithmetic
+    in the same order: their metrics are bitwise equal on ragged sizes,
+    including a size whose batches outnumber the resident waves many times
+    over."""
     print("case: forward vs gradient-kernel forward, ragged sizes", flush=True)
     f = bld["field"]
     for m in (1, 63, 64, 65, 1000, 4097, 300_001):
         t = bld["t_d"][:m].contiguous()
         q = bld["q_d"][:m].contiguous()
-        out = fif.query(f, t, q, M7 | 8).cpu().numpy()
+        out = fif.query(f, t, q, M7)
         _, _, out_g = fif.query_grad(f, t, q, M7, torch.zeros((m, 3), dtype=torch.float64,
                                                               device="cuda"), want_out=True)
-        err = forward_order_errors(out[:, :3], out_g.cpu().numpy(), out[:, 3:])
-        print(m, err)
-        for k, tol in FWD_ORDER_TOL.items():
-            assert err[k] <= tol, (m, k, err[k])
+        a, b = out.cpu().numpy(), out_g.cpu().numpy()
+        assert np.array_equal(np.isnan(a), np.isnan(b))
+        ok = ~np.isnan(a)
+        d = np.abs(a - b)[ok] / np.maximum(np.abs(b[ok]), 1e-300)
+        print(m, "bitwise" if np.array_equal(a[ok], b[ok]) else f"max rel {d.max():.2e}")
+        assert np.array_equal(a[ok], b[ok])

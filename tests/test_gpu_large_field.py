@@ -9,7 +9,7 @@ import pytest
 
 import oracle
 import scenes
-from fifcheck import FWD_ORDER_TOL, block_rel_err, e_fim, forward_order_errors, metric_errors
+from fifcheck import block_rel_err, e_fim, metric_errors
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -90,21 +90,18 @@ def test_queries_past_4gib_match_oracle(fif, big, interp):
 
 
 def test_gradient_kernel_and_trace_field_past_4gib(fif, big):
-    """The gradient kernel's forward values agree with the forward query's to
-    the FP32 rounding of their corner sums, and the trace field (0.9 GB) gives
-    the information field's trace."""
+    """The gradient kernel's forward values equal the forward query's, and the
+    trace field (0.9 GB) gives the information field's trace."""
     f = big["field"]
-    out24 = fif.query(f, big["t_d"], big["q_d"], M7 | 8)
-    out = out24[:, :3]
+    out = fif.query(f, big["t_d"], big["q_d"], M7)
     m = out.shape[0]
     gt, gphi, out_g = fif.query_grad(f, big["t_d"], big["q_d"], M7,
                                      torch.ones((m, 3), dtype=torch.float64, device="cuda"),
                                      want_out=True)
-    o24 = out24.cpu().numpy()
-    err = forward_order_errors(o24[:, :3], out_g.cpu().numpy(), o24[:, 3:])
-    print(err)
-    for k, tol in FWD_ORDER_TOL.items():
-        assert err[k] <= tol, (k, err[k])
+    a, b = out.cpu().numpy(), out_g.cpu().numpy()
+    assert np.array_equal(np.isnan(a), np.isnan(b))
+    ok = ~np.isnan(a)
+    assert np.array_equal(a[ok], b[ok])
     assert bool(torch.isfinite(gt).all()) and bool(torch.isfinite(gphi).all())
     tf = fif.build(big["lm_d"], big["grid"], big["vis"], prec=fif.FP32_COMP, kind=fif.KIND_TRACE)
     tr = fif.query(tf, big["t_d"], big["q_d"], fif.TRACE)[:, 0]
