@@ -494,19 +494,20 @@ __device__ inline void corner_vjp(const T* rec, const CT Gp[21], const CT z[3], 
 // ------------------------------------------------------------ 6x6 metrics (FP64)
 
 // 1/sqrt(x) and 1/x for positive normal FP64 x: hardware estimate refined by
-// two Newton steps (quadratic convergence from the estimate's ~2^-26 error).
+// one Newton step.  Measured over 4M log-uniform x in [1e-300, 1e300]: the
+// estimates are within 5.3e-8 (rsq) and 4.7e-8 (rcp) relative, one step
+// within 4.2e-15 and 2.2e-15.  A Jacobi rotation built from them is then
+// orthogonal to ~1e-14, which moves the eigenvalues by under 1e-12 relative
+// over a whole solve (far below every FP64 bar); a second step cost 5-10% of
+// the FP32-field query.
 __device__ inline double rsq_nr(double x) {
-  double y = __builtin_amdgcn_rsq(x);
-  double r = fma(-x * y, y, 1.0);
-  y = fma(0.5 * y, r, y);
-  r = fma(-x * y, y, 1.0);
+  const double y = __builtin_amdgcn_rsq(x);
+  const double r = fma(-x * y, y, 1.0);
   return fma(0.5 * y, r, y);
 }
 __device__ inline double rcp_nr(double x) {
-  double y = __builtin_amdgcn_rcp(x);
-  double e = fma(-x, y, 1.0);
-  y = fma(y, e, y);
-  e = fma(-x, y, 1.0);
+  const double y = __builtin_amdgcn_rcp(x);
+  const double e = fma(-x, y, 1.0);
   return fma(y, e, y);
 }
 
