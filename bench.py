@@ -117,7 +117,7 @@ def query_src_hash():
 
 BUILD_SOURCES = ("fif_build.hip", "fif_device.h")
 PC_SOURCES = ("fif_pc.hip", "fif_device.h")
-GP_SOURCES = ("fif_gp.hip", "fif_device.h", "fif_metrics.h")
+GP_SOURCES = ("fif_gp.hip", "fif_device.h", "fif_metrics.h", "fif_api.hip")  # api: row layout
 
 
 def sources_of(kernel: str):

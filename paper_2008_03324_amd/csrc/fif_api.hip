@@ -104,12 +104,13 @@ bool gp_model_ok(const fif_gp* gp, bool need_kinv) {
 }
 
 // Scalars per voxel of a GP field: 16 per axis (information), or the N_s
-// trace factors padded to a whole number of 128-B lines, so that the query's
-// 64-B passes over a row never share a line with the next voxel's row.
+// trace factors rounded up to an even count (the query reads them in pairs).
+// The rows of x-neighbour voxels, which a trilinear query reads together, are
+// then contiguous and share their boundary lines.
 int64_t gp_stride(int32_t n_s, int32_t kind, int32_t prec) {
+  (void)prec;
   if (kind == FIF_KIND_INFO) return (int64_t)n_s * 16;
-  const int64_t line = prec == FIF_FP64 ? 16 : 32;
-  return (int64_t)((n_s + line - 1) / line) * line;
+  return (int64_t)((n_s + 1) / 2) * 2;
 }
 
 fif::GPDev gp_dev(const fif_gp* gp, double half_fov) {

@@ -143,7 +143,9 @@ def test_gp_host_side_validation():
     vis = fif.Vis()
     gp = fif.CGP(30, 0, 15.0, 0.9, 1e-10, 4096, 8192)
     assert L.fif_gp_field_bytes(ctypes.byref(g.c()), 30, fif.FP32_COMP, fif.KIND_INFO) == 64 * 30 * 16 * 4
-    assert L.fif_gp_field_bytes(ctypes.byref(g.c()), 30, fif.FP64, fif.KIND_TRACE) == 64 * 32 * 8
+    assert L.fif_gp_field_bytes(ctypes.byref(g.c()), 30, fif.FP64, fif.KIND_TRACE) == 64 * 30 * 8
+    # trace rows hold N_s factors rounded up to an even count
+    assert L.fif_gp_field_bytes(ctypes.byref(g.c()), 31, fif.FP32_COMP, fif.KIND_TRACE) == 64 * 32 * 4
     assert L.fif_gp_field_bytes(ctypes.byref(g.c()), 0, fif.FP64, fif.KIND_INFO) == 0
     assert L.fif_gp_field_bytes(ctypes.byref(g.c()), 161, fif.FP64, fif.KIND_INFO) == 0
     for bad in (fif.CGP(0, 0, 15.0, 0.9, 1e-10, 4096, 8192),      # no axes
