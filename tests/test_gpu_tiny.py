@@ -187,6 +187,83 @@ def test_field_at_voxel_centres_equals_gpu_point_cloud(fif, tiny):
     assert e_fim(f_out, pc_out).max() <= 1e-10
 
 
+def test_gradient_fp32_matches_oracle(fif, tiny):
+    """FP32 compensated field (the persistent one-pose-per-lane gradient
+    kernel): gradients against the oracle's on the oracle's FP64 factors at
+    the FP32 bar, on ragged sizes (a single pose, one short of a batch, one
+    past it, and all 1,000), and the forward values bitwise those of the
+    forward query."""
+    print("case: tiny gradient FP32 compensated, ragged sizes", flush=True)
+    grid, vis = _grid_vis(fif, tiny["g"], tiny["v"])
+    field = fif.build(_cuda(tiny["lm"]), grid, vis, prec=fif.FP32_COMP)
+    # the poses as the FP32 field's kernels see them
+    t = tiny["t"].astype(np.float32).astype(np.float64)
+    q = tiny["q"].astype(np.float32).astype(np.float64)
+    rng = np.random.default_rng(6)
+    up = rng.standard_normal((t.shape[0], 3))
+    rgt, rgphi = oracle.query_grad(tiny["ofield"], tiny["v"].half_fov, tiny["v"].v_alpha, t, q,
+                                   M7, up)
+    ref, rflags = oracle.query(tiny["ofield"], tiny["v"].half_fov, tiny["v"].v_alpha, t, q, M7, 0)
+    g = (t - np.asarray(tiny["g"].origin)) / tiny["g"].h
+    fr = g - np.floor(g)
+    ok_all = ((fr > 1e-6) & (fr < 1 - 1e-6)).all(axis=1) & ((rflags & 4) == 0)
+    for m in (1, 63, 65, t.shape[0]):
+        tf, qf = _cuda(t[:m], torch.float32), _cuda(q[:m], torch.float32)
+        gt, gphi, out = fif.query_grad(field, tf, qf, M7, _cuda(up[:m]), want_out=True)
+        assert torch.equal(out.nan_to_num(7.0), fif.query(field, tf, qf, M7).nan_to_num(7.0)), m
+        ok = ok_all[:m]
+        for a, b in ((gt.cpu().numpy(), rgt[:m]), (gphi.cpu().numpy(), rgphi[:m])):
+            scale = np.abs(b[ok]).max(axis=1, keepdims=True)
+            rel = np.abs(a[ok] - b[ok]) / scale
+            print(m, "fp32 grad rel err max", rel.max(), "median", np.median(rel))
+            assert rel.max() <= 1e-3, (m, rel.max())
+            assert rel.max() <= 2e-4, (m, rel.max())  # a guard well inside the bar
+
+
+def test_v05_gradient_fp32_with_zero_logdet_weight(fif, tiny):
+    """v_alpha = 0.5 on an FP32 compensated field: with weight 0 on the log-det
+    the gradient is finite everywhere and matches the oracle's at the FP32 bar;
+    with weight 1 it is NaN on the poses whose FIM is clearly indefinite and
+    finite on those clearly positive definite."""
+    print("case: tiny gradient FP32 compensated, v_alpha 0.5", flush=True)
+    grid, vis = _grid_vis(fif, tiny["g"], tiny["v"], v_alpha=0.5)
+    field = fif.build(_cuda(tiny["lm"]), grid, vis, prec=fif.FP32_COMP)
+    t = tiny["t"].astype(np.float32).astype(np.float64)
+    q = tiny["q"].astype(np.float32).astype(np.float64)
+    tf, qf = _cuda(t, torch.float32), _cuda(q, torch.float32)
+    g = (t - np.asarray(tiny["g"].origin)) / tiny["g"].h
+    fr = g - np.floor(g)
+    ok = ((fr > 1e-6) & (fr < 1 - 1e-6)).all(axis=1)
+    ref, rflags = oracle.query(tiny["ofield"], tiny["v"].half_fov, 0.5, t, q, M7 | 8, 0)
+    ok &= (rflags & 4) == 0
+    up = np.tile([1.0, 0.5, 0.0], (t.shape[0], 1))
+    gt, gphi = fif.query_grad(field, tf, qf, M7, _cuda(up))
+    gt, gphi = gt.cpu().numpy(), gphi.cpu().numpy()
+    assert np.isfinite(gt).all() and np.isfinite(gphi).all()
+    rgt, rgphi = oracle.query_grad(tiny["ofield"], tiny["v"].half_fov, 0.5, t, q, M7, up)
+    for a, b in ((gt, rgt), (gphi, rgphi)):
+        scale = np.abs(b[ok]).max(axis=1, keepdims=True)
+        rel = (np.abs(a[ok] - b[ok]) / scale).max()
+        print("fp32 v05 grad rel err max", rel)
+        assert rel <= 1e-3
+    lam = np.linalg.eigvalsh(_sym21(ref[:, 3:]))
+    lmax = np.abs(lam).max(axis=1)
+    indef = lam[:, 0] < -1e-6 * lmax
+    posdef = lam[:, 0] > 1e-6 * lmax
+    assert indef.any() and posdef.any()
+    gt1, _ = fif.query_grad(field, tf, qf, M7, _cuda(np.ones_like(up)))
+    gt1 = gt1.cpu().numpy()
+    assert np.isnan(gt1[indef]).all() and np.isfinite(gt1[posdef]).all()
+
+
+def _sym21(v):
+    iu = np.triu_indices(6)
+    F = np.zeros(v.shape[:-1] + (6, 6))
+    F[..., iu[0], iu[1]] = v
+    F[..., iu[1], iu[0]] = v
+    return F
+
+
 def test_v05_indefinite_parity(fif, tiny):
     """v_alpha = 0.5 (negative visibility weights): signed lmin, NaN logdet."""
     grid, vis = _grid_vis(fif, tiny["g"], tiny["v"], v_alpha=0.5)
