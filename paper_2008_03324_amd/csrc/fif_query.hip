@@ -217,33 +217,29 @@ __global__ __launch_bounds__(kQThreads) void query_info_kernel(QueryArgs a) {
   }
 }
 
-// Forward query on FP32 fields with persistent waves.  Each wave takes
-// batches of 64 queries in turn, one query per lane, and visits the 8 cell
-// corners in 8 steps: step k gathers corner k of all 64 queries.  The main
-// records of a step are loaded straight into LDS (global_load_lds_dwordx4),
-// 16 lanes per record so that each load instruction reads whole records, and
-// each lane then reads its own record from LDS; a lane loading its own record
-// instead (64 records per instruction) moves fewer bytes per second.  The
-// records of the next step are loaded before the current step is contracted,
-// and the first step of the wave's next batch (with each lane's 64-B cell side
-// record, read whole into registers once per batch) before the current
-// batch's FP64 metric step, so the gathers stay in flight throughout; no load
-// is issued where the next wait on the step's records would cover it before
-// it is needed.  Each corner
-// term is the one query_info_kernel computes; a lane adds its query's 8 terms
-// with a chain of FMAs (weight times block, in corner order), where
-// query_info_kernel rounds each weighted block and sums them in an 8-lane
-// butterfly, so the two agree to FP32 rounding of that sum (bitwise for
-// nearest-voxel queries, which take step 0 only).  The gradient on the same
-// fields runs in query_grad_pipe_kernel, whose forward part is this one's, so
-// a pose's forward values do not depend on which of the two computed them.
-// The LDS slots and records
-// are private to a wave and no workgroup barrier is used: a wave leaves as
-// soon as its batches are done.  Voxel indices are 32-bit here (grids of 2^32
-// voxels or more take query_info_kernel).
+// Forward query on FP32 fields with persistent waves.  Each wave takes batches
+// of 64 queries in turn, one query per lane, and visits the 8 cell corners in 8
+// steps: step k gathers corner k of all 64 queries.  The main records of a step
+// are loaded straight into LDS (global_load_lds_dwordx4), 16 lanes per record
+// so that each load instruction reads whole records, and each lane then reads
+// its own record from LDS; a lane loading its own record instead (64 records
+// per instruction) moves fewer bytes per second.  The records of the next step
+// are loaded before the current step is contracted, and the first step of the
+// wave's next batch (with each lane's 64-B cell side record, read whole into
+// registers once per batch) before the current batch's FP64 metric step, so the
+// gathers stay in flight throughout; no load is issued where the next wait on
+// the step's records would cover it before it is needed.  Each corner term is
+// the one query_info_kernel computes; a lane adds its query's 8 terms with a
+// chain of FMAs (weight times block, in corner order), where query_info_kernel
+// rounds each weighted block and sums them in an 8-lane butterfly, so the two
+// agree to FP32 rounding of that sum (bitwise for nearest-voxel queries, which
+// take step 0 only).  The gradient on the same fields runs in
+// query_grad_pipe_kernel, whose forward part is this one's, so a pose's forward
+// values do not depend on which of the two computed them.  The LDS slots and
+// records are private to a wave and no workgroup barrier is used: a wave leaves
+// as soon as its batches are done.  Voxel indices are 32-bit here (grids of
+// 2^32 voxels or more take query_info_kernel).
 constexpr int kPipeWaves = kQThreads / 64;
-
-
 constexpr int kRecF4 = kMain / 4;  // float4 per main record
 
 // The per-query data a lane keeps for its own query (QSlot without d f / d t).
