@@ -197,7 +197,8 @@ fif_status fif_query(const fif_field* field, const void* t, const void* q, int64
  *   dL_dphi[m][3] w.r.t. the left so(3) perturbation of R_wc.
  * metrics: subset of FIF_TRACE | FIF_LMIN | FIF_LOGDET (dL_dout has that many
  * columns, in bit order).  dL_dt/dL_dphi have the type of t (float or double).
- * out (double[m][popcount], or NULL) receives the forward metrics as well.
+ * out (double[m][popcount], or NULL) receives the forward metrics as well,
+ * bit for bit those of fif_query on the same field, poses and metrics.
  * Trilinear interpolation only; the derivative is one-sided on cell faces. */
 fif_status fif_query_grad(const fif_field* field, const void* t, const void* q, int64_t m,
                           uint32_t metrics, const double* dL_dout, void* dL_dt, void* dL_dphi,
