@@ -153,8 +153,11 @@ __global__ __launch_bounds__(kQThreads) void query_info_kernel(QueryArgs a) {
   const int nmet = (int)((a.metrics & 1u) != 0) + (int)((a.metrics & 2u) != 0) +
                    (int)((a.metrics & 4u) != 0);
   double up[3] = {0.0, 0.0, 0.0};
-  if (GRAD) {
-    for (int m = 0; m < nmet; ++m) up[m] = valid ? a.dL_dout[ql * nmet + m] : 0.0;
+  if (GRAD) {  // constant indices: the array stays in registers
+    const double* du = a.dL_dout + ql * nmet;
+    up[0] = (valid && nmet > 0) ? du[0] : 0.0;
+    up[1] = (valid && nmet > 1) ? du[1] : 0.0;
+    up[2] = (valid && nmet > 2) ? du[2] : 0.0;
   }
   double* row = (valid && a.out) ? a.out + ql * a.ncols : nullptr;
   eval_metrics<GRAD>(F, a.metrics, row, &flag, up, G, a.flags != nullptr);
@@ -812,8 +815,12 @@ __device__ inline void paper_blocks(const FT* rec, const double tv[3], double sc
   for (int k = 0; k < 10; ++k) paper_block<FT>(rec, tv, scale, k, out + 21 * k);
 }
 
+constexpr int kExportThreads = 128;
+
+// (launch bounds: the default cap for 1024-thread blocks, 128 VGPRs, spilled
+// the 210 FP64 block entries in flight)
 template <typename FT>
-__global__ void export_info_kernel(ExportArgs a) {
+__global__ __launch_bounds__(kExportThreads) void export_info_kernel(ExportArgs a) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= a.n) return;
   const int64_t v = a.ids[i];
@@ -1036,7 +1043,7 @@ hipError_t launch_export(const ExportArgs& a, int prec, int kind, hipStream_t st
     p.n = std::min(kMaxLaunchItems, a.n - off);
     p.ids = a.ids + off;
     p.out = a.out + (size_t)off * (kind == 0 ? 210 : 10);
-    dim3 grid((unsigned)((p.n + 127) / 128)), block(128);
+    dim3 grid((unsigned)((p.n + kExportThreads - 1) / kExportThreads)), block(kExportThreads);
     if (kind == 0) {
       if (dbl) hipLaunchKernelGGL((export_info_kernel<double>), grid, block, 0, stream, p);
       else hipLaunchKernelGGL((export_info_kernel<float>), grid, block, 0, stream, p);
