@@ -252,6 +252,39 @@ def test_edge_cases_on_building_field(fif, bld):
     assert np.isnan(on1[0]).all() and np.isnan(on1[2]).all()
 
 
+def test_gradient_edge_cases_on_building_field(fif, bld):
+    """The FP32 gradient kernel off the hull and on NaN poses: a pose past the
+    hull in x has a zero x-gradient (the query is constant there) and the
+    other components of the pose clamped onto the hull; NaN positions or
+    quaternions give NaN gradients on their rows only."""
+    print("case: gradient edge cases on the building field", flush=True)
+    field = bld["field"]
+    g = bld["g"]
+    lo, hi = g.hull_lo, g.hull_hi
+    mid = 0.5 * (np.asarray(lo) + np.asarray(hi))
+    t = np.array([[lo[0] - 3.0, mid[1], mid[2]], [mid[0], mid[1] + 0.37, mid[2] - 0.21],
+                  [mid[0], np.nan, mid[2]], [mid[0], mid[1], mid[2]]], np.float32)
+    q = np.array([[0.9, 0.1, 0.3, 0.2], [0.5, 0.5, 0.5, 0.5], [1, 0, 0, 0],
+                  [np.nan, 0, 0, 1]], np.float32)
+    q[:2] /= np.linalg.norm(q[:2], axis=1, keepdims=True)
+    up = torch.ones((4, 3), dtype=torch.float64, device="cuda")
+    gt, gphi = fif.query_grad(field, torch.from_numpy(t).cuda(), torch.from_numpy(q).cuda(), M7,
+                              up)
+    gt, gphi = gt.cpu().numpy(), gphi.cpu().numpy()
+    assert gt[0, 0] == 0.0
+    assert np.isfinite(gt[:2]).all() and np.isfinite(gphi[:2]).all()
+    assert np.isnan(gt[2:]).all() and np.isnan(gphi[2:]).all()
+    # the outside pose equals its clamped counterpart in the other components
+    tc = t[:1].copy()
+    tc[0, 0] = np.float32(lo[0])  # on the hull face, up to FP32 rounding
+    gtc, gphic = fif.query_grad(field, torch.from_numpy(tc).cuda(), torch.from_numpy(q[:1]).cuda(),
+                                M7, up[:1])
+    gtc, gphic = gtc.cpu().numpy(), gphic.cpu().numpy()
+    scale = max(np.abs(gtc).max(), np.abs(gphic).max())
+    assert np.abs(gt[0, 1:] - gtc[0, 1:]).max() <= 1e-4 * scale
+    assert np.abs(gphi[0] - gphic[0]).max() <= 1e-4 * scale
+
+
 def test_empty_landmark_set_and_tiny_grids(fif):
     print("case: empty landmark set, 1x1x1 and 5x1x3 grids", flush=True)
     vis = fif.Vis()
